@@ -1,0 +1,452 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself -- closed forms, symbolic differentiation, library routines (SVD solve,
+matrix exponential), brute-force ODE integration and invariants -- chosen so that
+a dropped term, a wrong sign or index, or a transposed operand fails one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import sympy as sp
+
+import oracle as O
+from paper_2606_06720_amd import workloads as W
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
+
+
+def rng_fields(rng, n, d=None, rmin=0.05, rmax=0.15):
+    d = len(n) if d is None else d
+    shape = tuple(n[::-1])
+    m = rng.uniform(-1.0, 1.0, size=(d,) + shape)
+    r = rng.uniform(rmin, rmax, size=shape)
+    S = rng.standard_normal(shape)
+    S -= S.mean()
+    return m, r, S
+
+
+# ---------------------------------------------------------------- wavenumbers / G ----
+
+def test_wavenumber_worked_example():
+    # Sec. 2.3.3: N = 8, L = 2 -> 2 pi l / L = pi l for l <= 4, pi (l - 8) above.
+    path = __file__.replace("test_oracle_pins.py", "golden/wavenumbers_N8_L2.txt")
+    want = np.loadtxt(path, comments="#")
+    assert np.allclose(O.wavenumbers(8, 2.0) / np.pi, want, rtol=0, atol=1e-15)
+    xt = O.first_derivative_wavenumbers(8, 2.0) / np.pi
+    assert xt[4] == 0.0 and np.allclose(np.delete(xt, 4), np.delete(want, 4))
+
+
+@pytest.mark.parametrize("n,L", [((16, 16), (1.0, 1.0)), ((16, 32), (1.0, 2.5)), ((8, 16, 4), (1.0, 2.0, 0.5))])
+def test_grad_of_trig_mode_closed_form(n, L):
+    X = W.grid_coords(n, L)
+    d = len(n)
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        k = [int(rng.integers(-(n[c] // 2) + 1, n[c] // 2)) for c in range(d)]
+        phi = rng.uniform(0, 2 * np.pi)
+        arg = phi + sum(2 * np.pi * k[c] * X[c] / L[c] for c in range(d))
+        g = O.grad(np.cos(arg), L)
+        for c in range(d):
+            want = -2 * np.pi * k[c] / L[c] * np.sin(arg)
+            assert np.max(np.abs(g[c] - want)) < 1e-11 * (1 + np.max(np.abs(want)))
+
+
+def test_grad_annihilates_nyquist_checkerboards():
+    n = (8, 16)
+    i = np.arange(8)[None, :]
+    j = np.arange(16)[:, None]
+    for f in ((-1.0) ** i + 0 * j, (-1.0) ** j + 0 * i, (-1.0) ** (i + j)):
+        assert np.max(np.abs(O.grad(f, (1.0, 1.0)))) < 1e-13
+    # ... but the heat kernel keeps the Nyquist wavenumber (even in xi)
+    f = ((-1.0) ** i + 0 * j)[None]
+    out = O.diffusion(np.concatenate([f, f]), 1e-3, 0.1, 1.0)
+    assert np.allclose(out[0], f[0] * math.exp(-1e-3 * (np.pi * 8) ** 2 * 0.1), atol=1e-14)
+
+
+def test_neg_div_is_transpose_of_grad():
+    rng = np.random.default_rng(5)
+    for n, L in (((12, 8), (1.0, 3.0)), ((4, 8, 6), (2.0, 1.0, 1.5))):
+        shape = n[::-1]
+        f = rng.standard_normal(shape)
+        v = rng.standard_normal((len(n),) + shape)
+        lhs = np.sum(O.grad(f, L) * v)
+        rhs = np.sum(f * O.neg_div(v, L))
+        assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + np.linalg.norm(f) * np.linalg.norm(v))
+
+
+# ---------------------------------------------------------------- operator A ---------
+
+def _manufactured_2d(Lx, Ly):
+    x, y = sp.symbols("x y", real=True)
+    X = 2 * sp.pi * x / Lx
+    Y = 2 * sp.pi * y / Ly
+    p = sp.sin(X) * sp.cos(2 * Y) + sp.Rational(3, 10) * sp.cos(X + Y)
+    mx = sp.Rational(1, 2) + sp.Rational(1, 5) * sp.cos(Y)
+    my = sp.Rational(3, 10) * sp.sin(X) - sp.Rational(1, 4) * sp.cos(X - Y)
+    r = sp.Rational(1, 10) + sp.Rational(1, 20) * sp.cos(X)
+    px, py = sp.diff(p, x), sp.diff(p, y)
+    Fx = (mx * mx + r) * px + mx * my * py
+    Fy = mx * my * px + (my * my + r) * py
+    S = -(sp.diff(Fx, x) + sp.diff(Fy, y))
+    return [sp.lambdify((x, y), e, "numpy") for e in (p, mx, my, r, S)]
+
+
+@pytest.mark.parametrize("n,L", [((16, 16), (1.0, 1.0)), ((32, 16), (2.0, 0.75))])
+def test_operator_matches_symbolic_divergence_2d(n, L):
+    # every product stays below the Nyquist wavenumber, so the spectral operator
+    # is exact and must reproduce -div((m m^T + r I) grad p) to rounding
+    fp, fmx, fmy, fr, fS = _manufactured_2d(*L)
+    X, Y = W.grid_coords(n, L)
+    p = fp(X, Y)
+    m = np.stack([fmx(X, Y) + 0 * X, fmy(X, Y) + 0 * X])
+    r = fr(X, Y) + 0 * X
+    S = fS(X, Y)
+    Ap = O.apply_A(p, m, r, L)
+    assert np.max(np.abs(Ap - S)) < 1e-11 * np.max(np.abs(S))
+
+
+def test_operator_matches_symbolic_divergence_3d():
+    x, y, z = sp.symbols("x y z", real=True)
+    L = (1.0, 2.0, 1.0)
+    X, Y, Z = 2 * sp.pi * x / L[0], 2 * sp.pi * y / L[1], 2 * sp.pi * z / L[2]
+    p = sp.sin(X + Z) * sp.cos(Y) + sp.Rational(1, 3) * sp.cos(2 * Z)
+    m = [sp.Rational(2, 5) + sp.Rational(1, 5) * sp.cos(Z), sp.Rational(1, 4) * sp.sin(X), sp.Rational(1, 3) * sp.cos(Y - X)]
+    r = sp.Rational(1, 10) + sp.Rational(1, 25) * sp.sin(Y)
+    g = [sp.diff(p, v) for v in (x, y, z)]
+    mg = sum(m[c] * g[c] for c in range(3))
+    F = [mg * m[c] + r * g[c] for c in range(3)]
+    S = -sum(sp.diff(F[c], v) for c, v in enumerate((x, y, z)))
+    fs = [sp.lambdify((x, y, z), e, "numpy") for e in [p] + m + [r, S]]
+    n = (16, 16, 16)
+    Xs = W.grid_coords(n, L)
+    vals = [f(*Xs) + 0 * Xs[0] for f in fs]
+    pg, mg3, rg, Sg = vals[0], np.stack(vals[1:4]), vals[4], vals[5]
+    Ap = O.apply_A(pg, mg3, rg, L)
+    assert np.max(np.abs(Ap - Sg)) < 1e-11 * np.max(np.abs(Sg))
+
+
+def test_permeability_tensor_eigenpairs():
+    # principal directions m/|m| (eigenvalue r + |m|^2) and m_perp (eigenvalue r), Sec. 1.1
+    rng = np.random.default_rng(7)
+    m = rng.standard_normal((2, 5, 6))
+    r = rng.uniform(0.05, 0.2, size=(5, 6))
+    mperp = np.stack([-m[1], m[0]])
+    m2 = np.sum(m * m, axis=0)
+    assert np.allclose(O.apply_K(m, r, m), (r + m2)[None] * m, rtol=1e-14, atol=1e-14)
+    assert np.allclose(O.apply_K(m, r, mperp), r[None] * mperp, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [(8, 8), (6, 10), (4, 4, 4)])
+def test_dense_operator_symmetric_psd_with_null_space(n):
+    rng = np.random.default_rng(11)
+    m, r, _ = rng_fields(rng, n)
+    A = O.assemble_A(m, r, 1.0)
+    d = len(n)
+    assert np.max(np.abs(A - A.T)) < 1e-12 * np.max(np.abs(A))
+    w, V = np.linalg.eigh(0.5 * (A + A.T))
+    assert w.min() > -1e-10 * w.max()
+    null = w < 1e-9 * w.max()
+    assert int(null.sum()) == 2 ** d
+    # the null space is spanned by the constant and the Nyquist checkerboards
+    shape = n[::-1]
+    idx = np.indices(shape)
+    basis = []
+    for bits in range(2 ** d):
+        f = np.ones(shape)
+        for c in range(d):
+            if bits >> c & 1:
+                f = f * (-1.0) ** idx[d - 1 - c]
+        basis.append(f.ravel() / np.linalg.norm(f))
+    B = np.array(basis).T
+    P = V[:, null] @ V[:, null].T
+    assert np.max(np.abs(P @ B - B)) < 1e-9
+
+
+# ---------------------------------------------------------------- pressure solve -----
+
+def test_pressure_constant_coefficients_closed_form():
+    # constant m and r: each Fourier mode cos(2 pi k.x) of S is divided by
+    # 4 pi^2 k^T K k (closed-form Fourier solution); the constant-coefficient
+    # preconditioner is then exact and PCG converges in one iteration
+    n = (32, 32)
+    X, Y = W.grid_coords(n, 1.0)
+    mc = np.array([0.7, -0.4])
+    rc = 0.2
+    K = np.outer(mc, mc) + rc * np.eye(2)
+    modes = [((2, 1), 1.0, 0.0), ((-1, 3), 0.5, 0.3), ((5, -4), -0.25, 1.1)]
+    S = np.zeros_like(X)
+    p_want = np.zeros_like(X)
+    for k, a, ph in modes:
+        arg = 2 * np.pi * (k[0] * X + k[1] * Y) + ph
+        lam = 4 * np.pi ** 2 * (np.array(k) @ K @ np.array(k))
+        S += a * np.cos(arg)
+        p_want += a * np.cos(arg) / lam
+    m = np.broadcast_to(mc[:, None, None], (2,) + X.shape).copy()
+    r = np.full(X.shape, rc)
+    p, info = O.pressure_pcg(m, r, S, None, 1e-12, 50)
+    assert info.iters == 1 and info.converged
+    assert rel(p, p_want) < 1e-13
+    # the dense minimum-norm route on a 16^2 grid (all three modes below Nyquist there too
+    # except (5,-4), which is dropped)
+    Xs, Ys = W.grid_coords((16, 16), 1.0)
+    Ss = np.zeros_like(Xs)
+    ps = np.zeros_like(Xs)
+    for k, a, ph in modes[:2]:
+        arg = 2 * np.pi * (k[0] * Xs + k[1] * Ys) + ph
+        Ss += a * np.cos(arg)
+        ps += a * np.cos(arg) / (4 * np.pi ** 2 * (np.array(k) @ K @ np.array(k)))
+    ms = np.broadcast_to(mc[:, None, None], (2, 16, 16)).copy()
+    assert rel(O.pressure_dense(ms, np.full((16, 16), rc), Ss), ps) < 1e-12
+
+
+@pytest.mark.parametrize("n", [(8, 8), (16, 16), (32, 32), (16, 8), (4, 4, 4), (8, 8, 8)])
+def test_pcg_matches_dense_min_norm_solve(n):
+    rng = np.random.default_rng(13 + len(n))
+    m, r, S = rng_fields(rng, n)
+    p_dense = O.pressure_dense(m, r, S)
+    p_cg, info = O.pressure_pcg(m, r, S, None, 1e-13, 2000)
+    assert info.converged
+    assert rel(p_cg, p_dense) < 1e-10
+    # minimum-norm solution: zero mean and zero null-mode components
+    assert abs(p_cg.mean()) < 1e-14 * np.abs(p_cg).max()
+    ph = np.fft.fftn(p_cg)
+    assert np.max(np.abs(ph[O.null_mode_mask(p_cg.shape)])) < 1e-11 * np.abs(ph).max()
+
+
+def test_pressure_energy_identity():
+    # sum grad p . K grad p = sum p Pi S at the solution (G^T K G p = Pi S)
+    rng = np.random.default_rng(17)
+    m, r, S = rng_fields(rng, (32, 16))
+    p, info = O.pressure_pcg(m, r, S, None, 1e-13, 2000)
+    g = O.grad(p)
+    lhs = np.sum(g * O.apply_K(m, r, g))
+    rhs = np.sum(p * O.project(S))
+    assert abs(lhs - rhs) < 1e-11 * abs(rhs)
+
+
+def test_pcg_invariant_to_preconditioner_scale():
+    rng = np.random.default_rng(19)
+    m, r, S = rng_fields(rng, (16, 16))
+    p1, i1 = O.pressure_pcg(m, r, S, None, 1e-11, 500, keep_history=True)
+    p2, i2 = O.pressure_pcg(m, r, S, None, 1e-11, 500, precond_scale=3.7, keep_history=True)
+    # identical in exact arithmetic; rounding drift grows slowly along the iteration
+    assert abs(i1.iters - i2.iters) <= 1
+    assert np.allclose(i1.history[:15], i2.history[:15], rtol=1e-11, atol=0)
+    assert rel(p1, p2) < 1e-10
+
+
+def test_pcg_warm_start_and_failure_paths():
+    rng = np.random.default_rng(23)
+    m, r, S = rng_fields(rng, (16, 16))
+    p, info = O.pressure_pcg(m, r, S, None, 1e-10, 500)
+    p2, info2 = O.pressure_pcg(m, r, S, p, 1e-10, 500)
+    assert info2.iters == 0 and info2.converged
+    _, info3 = O.pressure_pcg(m, r, S, None, 1e-10, 1)
+    assert info3.iters == 1 and not info3.converged
+    with pytest.raises(O.Incompatible):
+        O.pressure_pcg(m, r, S + 1e-3, None, 1e-10, 10)
+    # zero right-hand side -> the minimum-norm solution is 0
+    pz, iz = O.pressure_pcg(m, r, np.zeros_like(S), p, 1e-10, 10)
+    assert np.all(pz == 0.0) and iz.iters == 0
+
+
+# ---------------------------------------------------------------- activation ---------
+
+def test_activation_matches_matrix_exponential():
+    rng = np.random.default_rng(29)
+    for d in (2, 3):
+        m = rng.standard_normal((d, 4, 5))
+        g = rng.standard_normal((d, 4, 5))
+        c2, dt = 3.0, 0.05
+        out = O.activation(m, g, c2, dt)
+        for j in range(4):
+            for i in range(5):
+                E = scipy.linalg.expm(c2 * dt * np.outer(g[:, j, i], g[:, j, i]))
+                assert np.allclose(out[:, j, i], E @ m[:, j, i], rtol=1e-13, atol=1e-13)
+
+
+def test_activation_special_cases():
+    m = np.array([[0.3], [-0.8]])[:, :, None] * np.ones((2, 1, 3))
+    c2, dt = 2.0, 0.1
+    # g = 0: unchanged (first branch of the discrete formula)
+    assert np.array_equal(O.activation(m, np.zeros_like(m), c2, dt), m)
+    # g parallel to m: scaled by exp(c^2 |g|^2 dt); g perpendicular: unchanged
+    g = 0.5 * m
+    g2 = np.sum(g * g, axis=0)
+    assert np.allclose(O.activation(m, g, c2, dt), m * np.exp(c2 * g2 * dt)[None], rtol=1e-14)
+    gp = np.stack([-m[1], m[0]])
+    assert np.allclose(O.activation(m, gp, c2, dt), m, rtol=1e-14, atol=1e-15)
+    # semigroup in time
+    g = np.stack([0.2 + 0 * m[0], -0.7 + 0 * m[0]])
+    a = O.activation(O.activation(m, g, c2, 0.03), g, c2, 0.07)
+    assert np.allclose(a, O.activation(m, g, c2, 0.1), rtol=1e-14)
+
+
+def _rk4(f, y, t, nsteps):
+    h = t / nsteps
+    for _ in range(nsteps):
+        k1 = f(y)
+        k2 = f(y + 0.5 * h * k1)
+        k3 = f(y + 0.5 * h * k2)
+        k4 = f(y + h * k3)
+        y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
+def test_activation_matches_rk4_of_ode():
+    m = np.array([0.4, 0.9])
+    g = np.array([1.3, -0.6])
+    c2, dt = 4.0, 0.2
+    y = _rk4(lambda v: c2 * np.dot(g, v) * g, m.copy(), dt, 4000)
+    out = O.activation(m[:, None, None], g[:, None, None], c2, dt)[:, 0, 0]
+    assert np.allclose(out, y, rtol=1e-11)
+
+
+# ---------------------------------------------------------------- relaxation ---------
+
+def test_relaxation_closed_forms():
+    rng = np.random.default_rng(31)
+    m = rng.standard_normal((2, 6, 7))
+    s = np.sqrt(np.sum(m * m, axis=0))
+    dt = 0.3
+    # gamma = 1: exponential decay
+    assert np.allclose(O.relaxation(m, 1.0, dt), m * math.exp(-dt), rtol=1e-15)
+    # gamma = 1/2: ds/dt = -1, a soft threshold max(|m| - dt, 0) along m/|m|
+    want = m * (np.maximum(s - dt, 0.0) / s)[None]
+    assert np.allclose(O.relaxation(m, 0.5, dt), want, rtol=1e-13, atol=1e-15)
+    # zero vector stays zero for every gamma
+    z = np.zeros((2, 2, 2))
+    for gam in (0.5, 0.75, 1.0, 1.2):
+        assert np.array_equal(O.relaxation(z, gam, dt), z)
+
+
+@pytest.mark.parametrize("gamma", [0.6, 0.75, 0.9, 0.999, 1.2])
+def test_relaxation_matches_rk4_and_semigroup(gamma):
+    m = np.array([0.9, -0.5])
+    dt = 0.05
+    f = lambda v: -np.linalg.norm(v) ** (2 * (gamma - 1)) * v
+    y = _rk4(f, m.copy(), dt, 5000)
+    out = O.relaxation(m[:, None, None], gamma, dt)[:, 0, 0]
+    assert np.allclose(out, y, rtol=1e-10)
+    two = O.relaxation(O.relaxation(m[:, None, None], gamma, 0.02), gamma, 0.03)[:, 0, 0]
+    assert np.allclose(two, out, rtol=1e-12)
+    # the direction of m is preserved
+    assert abs(out[0] * m[1] - out[1] * m[0]) < 1e-14
+
+
+def test_relaxation_extinction_indicator():
+    # gamma < 1 and |m|^{2(1-gamma)} < 2 (1-gamma) dt: b < 0, the conductivity vanishes
+    gamma, dt = 0.75, 1.0   # |m|^{1/2} = 0.473 < 2 (1/4) dt = 0.5
+    small = np.array([0.2, 0.1])[:, None, None]
+    assert np.array_equal(O.relaxation(small, gamma, dt), np.zeros_like(small))
+    big = np.array([2.0, 1.0])[:, None, None]
+    assert np.all(np.abs(O.relaxation(big, gamma, dt)) > 0)
+
+
+# ---------------------------------------------------------------- diffusion ----------
+
+def test_diffusion_heat_kernel_per_mode():
+    n, L = (16, 32), (1.0, 2.0)
+    X, Y = W.grid_coords(n, L)
+    D2, dt = 3e-3, 0.7
+    for (a, b) in ((1, 0), (3, -5), (-7, 12), (8, 0), (0, 16)):
+        arg = 2 * np.pi * (a * X / L[0] + b * Y / L[1]) + 0.4
+        f = np.cos(arg)
+        if a == 8 or b == 16:   # Nyquist: cos(pi i + phi) has only the cos(phi) part on the grid
+            f = np.cos(arg)
+        lam = (2 * np.pi * a / L[0]) ** 2 + (2 * np.pi * b / L[1]) ** 2
+        m = np.stack([f, -2 * f])
+        out = O.diffusion(m, D2, dt, L)
+        assert np.allclose(out, m * math.exp(-D2 * lam * dt), rtol=1e-12, atol=1e-14)
+    # mean preserved, L2 non-increasing, semigroup
+    rng = np.random.default_rng(37)
+    m = rng.standard_normal((2,) + n[::-1])
+    out = O.diffusion(m, D2, dt, L)
+    assert np.allclose(out.mean(axis=(1, 2)), m.mean(axis=(1, 2)), atol=1e-15)
+    assert np.linalg.norm(out) <= np.linalg.norm(m)
+    assert np.allclose(O.diffusion(O.diffusion(m, D2, 0.3, L), D2, 0.4, L), out, atol=1e-13)
+
+
+# ---------------------------------------------------------------- full step / run ----
+
+def _T(f):
+    """Swap the x and y directions of a scalar field [y][x] -> [x][y]."""
+    return np.ascontiguousarray(f.T)
+
+
+def test_step_equivariant_under_axis_swap():
+    rng = np.random.default_rng(41)
+    m, r, S = rng_fields(rng, (16, 16))
+    prm = dict(c2=30.0, D2=1e-3, gamma=0.75, dt=2e-3)
+    m1, p1, _ = O.step(m, None, r, S, rtol=1e-13, **prm)
+    mT = np.stack([_T(m[1]), _T(m[0])])
+    m2, p2, _ = O.step(mT, None, _T(r), _T(S), rtol=1e-13, **prm)
+    assert rel(p2, _T(p1)) < 1e-11
+    assert rel(m2, np.stack([_T(m1[1]), _T(m1[0])])) < 1e-11
+
+
+def test_step_equivariant_under_reflection():
+    rng = np.random.default_rng(43)
+    m, r, S = rng_fields(rng, (16, 8))
+    prm = dict(c2=30.0, D2=1e-3, gamma=0.8, dt=2e-3)
+    ref = lambda f: np.roll(f[:, ::-1], 1, axis=1)   # i -> -i mod N (x -> -x)
+    m1, p1, _ = O.step(m, None, r, S, rtol=1e-13, **prm)
+    mR = np.stack([-ref(m[0]), ref(m[1])])
+    m2, p2, _ = O.step(mR, None, ref(r), ref(S), rtol=1e-13, **prm)
+    assert rel(p2, ref(p1)) < 1e-11
+    assert rel(m2, np.stack([-ref(m1[0]), ref(m1[1])])) < 1e-11
+
+
+def test_energy_non_increasing_for_small_dt():
+    w = W.bump_workload(32)
+    m, p, info = O.run(w["m0"], None, w["r"], w["S"], w["c2"], w["D2"], w["gamma"], w["dt"],
+                       max_steps=15, eps_dm=0.0, stop_on_energy=True, rtol=1e-12)
+    assert info.steps == 15 and info.stop_reason == O.STOP_MAX_STEPS
+    e = np.array(info.energies)
+    assert np.all(np.diff(e) < 0)
+    assert abs(p.mean()) < 1e-13
+
+
+def test_energy_terms_consistent_with_pressure_identity():
+    rng = np.random.default_rng(47)
+    m, r, S = rng_fields(rng, (16, 16))
+    c2 = 7.0
+    p, _ = O.pressure_pcg(m, r, S, None, 1e-13, 2000)
+    tot, e_diff, e_relax, e_act, e_flow = O.energy(m, p, r, c2, 1e-3, 0.75)
+    h2 = (1.0 / 16) ** 2
+    # c^2/2 (||m.grad p||^2 + sum r|grad p|^2) = c^2/2 h^2 sum p Pi S
+    assert abs((e_act + e_flow) - 0.5 * c2 * h2 * np.sum(p * O.project(S))) < 1e-11 * (e_act + e_flow)
+    assert abs(tot - (e_diff + e_relax + e_act + e_flow)) < 1e-14 * tot
+    # relaxation energy of the closed form |m|^{2 gamma} / (2 gamma) at gamma = 1: ||m||^2 / 2
+    assert abs(O.energy(m, p, r, c2, 1e-3, 1.0)[2] - 0.5 * h2 * np.sum(m * m)) < 1e-14
+
+
+def test_run_stopping_criteria():
+    w = W.bump_workload(16)
+    args = (w["r"], w["S"], w["c2"], w["D2"], w["gamma"], w["dt"])
+    _, _, i1 = O.run(w["m0"], None, *args, max_steps=3)
+    assert i1.steps == 3 and i1.stop_reason == O.STOP_MAX_STEPS
+    _, _, i2 = O.run(w["m0"], None, *args, max_steps=10, eps_dm=1e9)
+    assert i2.steps == 1 and i2.stop_reason == O.STOP_DM_BELOW_EPS
+    # a huge activation time step raises the energy: the run stops on it
+    _, _, i3 = O.run(w["m0"], None, w["r"], 10 * w["S"], 100.0, 1e-4, 0.75, 0.05,
+                     max_steps=10, stop_on_energy=True)
+    assert i3.stop_reason == O.STOP_ENERGY_INCREASE
+    assert i3.energies[-1] >= i3.energies[-2]
+
+
+def test_paper_internal_sink_has_zero_integral():
+    # Sec. 3.3: the internal sink S_int is built so that int S = 0
+    for N in (128, 256):
+        S = W.paper_Sint(N)
+        assert abs(S.mean()) < 1e-12
+    S4 = W.paper_S4(128)
+    assert abs(S4.mean()) < 1e-12
