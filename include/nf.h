@@ -1,0 +1,188 @@
+/*
+ * nf.h -- C ABI of the MI355X (gfx950) implementation of the per-time-step hot
+ * path of the Fourier spectral scheme for the periodic Hu-Cai network-formation
+ * system (Aceves-Sanchez, Degond, Merino-Aceituno, Wytrzens, "A Spectral-Based
+ * Method for Network-Formation PDEs").
+ *
+ * The system (Sec. 1.1, eqs. p and m):
+ *     -div((m (x) m + r I) grad p) = S,
+ *     d_t m - D^2 lap m - c^2 (m . grad p) grad p + |m|^{2(gamma-1)} m = 0,
+ * on a periodic box, S time independent with zero integral.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grid: n[0] = Nx, n[1] = Ny (2D), powers of two in [8, 4096]; nodes
+ *   x_i = i Lx / Nx, i < Nx (Sec. 2.2, node Nx identified with node 0).
+ * - Fields are caller-owned DEVICE buffers of double, C-contiguous, x fastest:
+ *   scalars (p, r, S) are [Ny][Nx]; the conductivity m is [2][Ny][Nx] with
+ *   component 0 = m_x.  The library never frees, reallocates or retains them.
+ * - The handle owns all workspace (allocated once by nf_create_grid); no entry
+ *   point allocates device memory.
+ * - All work is enqueued on the handle's HIP stream.  Entry points that run a
+ *   PCG solve synchronise with that stream to test convergence; they return
+ *   after the last kernel of the call has been queued and every host-visible
+ *   result has been read back.
+ * - Errors are reported by return code; on error the outputs are unspecified
+ *   (exception: NF_ENOTCONV still writes the last iterate and fills info).
+ *   nf_last_error() gives a message for the last failing call on a handle.
+ * - Discrete pressure (reading of Sec. 2.4): the minimum-norm solution of the
+ *   spectral operator of eq. p_discrete, whose first-derivative multipliers use
+ *   the discrete Fourier variable of Sec. 2.3.3 with the Nyquist entry set to
+ *   zero.  The 2^d Fourier modes on which those multipliers all vanish are
+ *   projected out of S and of p.
+ * - One handle per stream; calls on one handle must not overlap.
+ */
+#ifndef NF_H
+#define NF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nf_grid nf_grid;
+
+enum {
+  NF_OK = 0,
+  NF_EINVAL = -1,      /* invalid argument (size, dtype, dt <= 0, gamma <= 0, c2 < 0, D2 < 0, NULL field) */
+  NF_ENOMEM = -2,      /* workspace allocation failed */
+  NF_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed */
+  NF_ENOTCONV = -4,    /* PCG reached max_iter before the tolerance */
+  NF_EINCOMPAT = -5,   /* |sum S| > 1e-12 sum |S|: solvability condition of eq. p violated */
+  NF_ENONFINITE = -6   /* activation produced Inf/NaN: c^2 |grad p|^2 dt too large (Sec. 2.3.1, Remark) */
+};
+
+enum { NF_F64 = 0 };
+
+enum { NF_STOP_MAX_STEPS = 0, NF_STOP_DM_BELOW_EPS = 1, NF_STOP_ENERGY_INCREASE = 2, NF_STOP_ERROR = 3 };
+
+/* c^2, D^2 and the metabolic exponent gamma of eq. m. */
+typedef struct {
+  double c2, D2, gamma;
+} nf_params;
+
+typedef struct {
+  int iters;           /* PCG iterations taken */
+  int converged;       /* 1 if ||r|| <= rtol ||Pi S|| was reached */
+  double rel_res;      /* recurrence residual / ||Pi S|| */
+  double true_rel_res; /* ||Pi S - A p|| / ||Pi S|| (-1 when not computed) */
+} nf_solve_info;
+
+typedef struct {
+  nf_solve_info solve;
+  double dm_rel;       /* Delta m = ||m^{k+1} - m^k|| / (dt ||m^k||) (Sec. 2.5) */
+} nf_step_info;
+
+typedef struct {
+  int64_t steps;          /* time steps taken */
+  int stop_reason;        /* NF_STOP_* */
+  double last_dm;         /* Delta m of the last step */
+  double last_energy;     /* E_h of the final state (NaN if energy stopping was off) */
+  double prev_energy;     /* E_h of the state before it (NaN if off) */
+  int64_t total_cg_iters; /* PCG iterations over the whole run */
+} nf_run_info;
+
+/*
+ * Create a solver handle for a 2D periodic grid.
+ *   ndim    must be 2;
+ *   n       grid sizes (Nx, Ny[, unused]), powers of two in [8, 4096];
+ *   L       box lengths (Lx, Ly[, unused]), > 0;
+ *   dtype   NF_F64;
+ *   stream  hipStream_t to enqueue on (NULL = default stream).
+ * Allocates the workspace (8 complex half-spectrum fields plus tables) on the
+ * current HIP device.  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
+ * (*out is then NULL).
+ */
+int nf_create_grid(nf_grid **out, int ndim, const int64_t n[3], const double L[3], int dtype, void *stream);
+
+/* Release the handle and its workspace (after synchronising its stream). NULL is a no-op. */
+int nf_destroy_grid(nf_grid *g);
+
+/* Change the stream the handle enqueues on. */
+int nf_set_stream(nf_grid *g, void *stream);
+
+/*
+ * Pressure solve, Sec. 2.4 (eq. p_discrete by CG, warm started from p):
+ * solves -div((m m^T + r I) grad p) = S for the minimum-norm p by preconditioned
+ * CG with the constant-coefficient preconditioner -div(Kbar grad), Kbar the grid
+ * mean of m m^T + r I (Sec. 5 mentions it).  Stops when
+ * ||r_k||_2 <= rtol ||Pi S||_2 (recurrence residual) or after max_iter iterations.
+ *   m [2][Ny][Nx], r [Ny][Nx] (r > 0 is the caller's responsibility), S [Ny][Nx];
+ *   p [Ny][Nx] in: initial guess, out: the solution (null modes removed);
+ *   info may be NULL; if not, the true residual is computed as well.
+ * Returns NF_OK, NF_ENOTCONV, NF_EINCOMPAT, NF_EINVAL or NF_EDEVICE.
+ */
+int nf_pressure_solve(nf_grid *g, const double *m, const double *r, const double *S, double *p, double rtol,
+                      int max_iter, nf_solve_info *info);
+
+/*
+ * One pass of the time loop of Algorithm 1:
+ *   Step 1: p <- p[m^k] (as nf_pressure_solve, warm start from p on entry);
+ *   Step 2: with g = grad p, exact activation (eq. m_activation_discrete), exact
+ *           relaxation (eq. m_relaxation_discrete), exact diffusion by the heat
+ *           multiplier exp(-D^2 |xi|^2 dt) in Fourier space (eq.
+ *           diffusion_space_discrete), in that order.
+ *   m [2][Ny][Nx] in: m^k, out: m^{k+1};  p out: p[m^k].
+ * info may be NULL.  Returns NF_OK, NF_ENOTCONV (m is still advanced with the
+ * last PCG iterate), NF_EINCOMPAT, NF_ENONFINITE, NF_EINVAL or NF_EDEVICE.
+ */
+int nf_step(nf_grid *g, const nf_params *prm, double dt, double *m, double *p, const double *r, const double *S,
+            double rtol, int max_iter, nf_step_info *info);
+
+/*
+ * Time loop of Algorithm 1 with the stopping criteria of Sec. 2.5.
+ * Solves p[m^0] (warm start from p), then repeats: split update of m^k with
+ * p[m^k]; solve p[m^{k+1}] (warm start from the previous solution);
+ * Delta m^k; stop if stop_on_energy_increase and E_h(m^{k+1}) >= E_h(m^k), or
+ * if Delta m <= eps_dm, or after max_steps steps.  At least one step is taken.
+ * On return m holds the final state and p = p[m] for that state.
+ * Returns NF_OK (see info->stop_reason) or the first error of a step.
+ */
+int nf_run(nf_grid *g, const nf_params *prm, double dt, int64_t max_steps, double eps_dm,
+           int stop_on_energy_increase, double *m, double *p, const double *r, const double *S, double rtol,
+           int max_iter, nf_run_info *info);
+
+/*
+ * Discrete energy E_h of Sec. 2.5 (the energy functional of Sec. 1.1 on the grid):
+ *   out[0] total,
+ *   out[1] D^2/2 ||grad m||^2,
+ *   out[2] || |m|^gamma ||^2 / (2 gamma),
+ *   out[3] c^2/2 ||m . grad p||^2,
+ *   out[4] c^2/2 sum h^d r |grad p|^2,
+ * with ||f||^2 = h_x h_y sum f^2 and the spectral gradient.  p must be p[m]; if
+ * p is NULL the pressure is solved (cold start, rtol 1e-12, 1000 iterations).
+ */
+int nf_energy(nf_grid *g, const nf_params *prm, const double *m, const double *p, const double *r, const double *S,
+              double out[5]);
+
+/*
+ * Diagnostic entry points exposing single stages of the path, for unit checks
+ * of the transforms and of the operator against independent references.
+ *
+ * nf_transform_forward: out = unnormalised 2D DFT of the real field f [Ny][Nx],
+ *   in the packed half-spectrum layout used internally: out is [Nx/2][Ny]
+ *   complex (interleaved re, im; 2 * Nx/2 * Ny doubles), entry [kx][ky] =
+ *   F(kx, ky) for 1 <= kx < Nx/2, and column kx = 0 holds
+ *   F(0, ky) + i F(Nx/2, ky) (both columns are spectra of real sequences).
+ * nf_transform_inverse: f = inverse DFT (normalised by 1/(Nx Ny)) of a packed
+ *   half spectrum in the same layout.
+ * nf_apply_operator: out = A p, the left-hand side of eq. p_discrete for the
+ *   given m and r, p [Ny][Nx], out [Ny][Nx].
+ * All three are enqueued on the handle's stream and return after synchronising it.
+ */
+int nf_transform_forward(nf_grid *g, const double *f, double *out);
+int nf_transform_inverse(nf_grid *g, const double *spec, double *f);
+int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double *p, double *out);
+
+/* Message describing the last error on the handle ("" if none). */
+const char *nf_last_error(const nf_grid *g);
+
+/* Version string of the library. */
+const char *nf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NF_H */

@@ -1,0 +1,600 @@
+// Host side of the C ABI declared in include/nf.h: handle and workspace
+// management, the PCG driver loop, the time step, the time loop with its
+// stopping criteria (Algorithm 1, Sec. 2.5) and the discrete energy.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/nf.h"
+#include "nf_internal.h"
+
+using namespace nf;
+
+struct nf_grid {
+  int nx = 0, ny = 0, h = 0;
+  double lx = 1.0, ly = 1.0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* tw = nullptr;
+  int twlog = 0;
+  void* xh = nullptr;  // PCG iterate (spectral)
+  void* rh = nullptr;  // residual
+  void* dh = nullptr;  // search direction
+  void* qh = nullptr;  // A d
+  void* bh = nullptr;  // projected right-hand side
+  void* mix[3] = {nullptr, nullptr, nullptr};
+  double* part = nullptr;
+  DevStatus* st = nullptr;
+  DevStatus* hst = nullptr;  // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int last_iters = 0;
+  std::string err;
+  Geo geo;
+};
+
+namespace {
+
+const char* kVersion = "nf-mi355x 0.1 (gfx950, fp64 2D)";
+
+int fail(nf_grid* g, int code, const std::string& msg) {
+  if (g) g->err = msg;
+  return code;
+}
+
+#define HIPCHK(g, expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((g), NF_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_));      \
+  } while (0)
+
+bool is_pow2_in_range(int64_t v) { return v >= 8 && v <= 4096 && (v & (v - 1)) == 0; }
+
+int ilog2i(int v) {
+  int p = 0;
+  while ((1 << p) < v) ++p;
+  return p;
+}
+
+// exp(-2 pi i u / N) for u < N, from long double arithmetic with the octant
+// symmetries so that each entry is the correctly rounded value in practice.
+void make_twiddles(int N, double* out /* 2N */) {
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int u = 0; u < N; ++u) {
+    // reduce to the first octant: angle = 2 pi u / N = (pi/4) * (8u/N)
+    long double a = two_pi * (long double)u / (long double)N;
+    long double c = cosl(a), s = sinl(a);
+    if ((8LL * u) % N == 0) {  // exact multiples of pi/4
+      const int oct = (int)((8LL * u) / N);
+      const long double r2 = 0.707106781186547524400844362104849039L;
+      const long double cs[8] = {1.0L, r2, 0.0L, -r2, -1.0L, -r2, 0.0L, r2};
+      const long double sn[8] = {0.0L, r2, 1.0L, r2, 0.0L, -r2, -1.0L, -r2};
+      c = cs[oct];
+      s = sn[oct];
+    }
+    out[2 * u] = (double)c;
+    out[2 * u + 1] = (double)(-s);
+  }
+}
+
+int check_launch(nf_grid* g, hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(g, NF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return NF_OK;
+}
+
+#define LCHK(g, expr)                               \
+  do {                                              \
+    int rc_ = check_launch((g), (expr), #expr);     \
+    if (rc_ != NF_OK) return rc_;                   \
+  } while (0)
+
+int read_status(nf_grid* g, DevStatus* dst) {
+  HIPCHK(g, hipMemcpyAsync(dst, g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return NF_OK;
+}
+
+// b_hat = F(Pi S) and the compatibility partials of S
+int compute_rhs(nf_grid* g, const double* S) {
+  const Geo& G = g->geo;
+  LCHK(g, launch_row_r2c(G, S, g->mix[0], slot_ptr(g->part, SLOT_SCHK), g->stream));
+  LCHK(g, launch_col_fwd(G, g->mix[0], g->bh, 0, nullptr, nullptr, g->stream));
+  return NF_OK;
+}
+
+enum XSource { X_FROM_P = 0, X_FROM_XH = 1, X_ZERO = 2 };
+
+struct SolveOut {
+  int iters = 0, converged = 0, flags = 0, sticky = 0;
+  double rel_res = 0.0, true_rel_res = -1.0;
+};
+
+// Operator apply on the current iterate x_hat: leaves r_hat = b_hat - A x_hat,
+// partials <r,M^-1 r>, <r,r>, <b,b> in SLOT_P3INIT and Kbar in the status.
+int init_residual(nf_grid* g, const double* m, const double* r) {
+  const Geo& G = g->geo;
+  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), g->stream));
+  LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), g->stream));
+  return NF_OK;
+}
+
+// PCG for A x = Pi S (Sec. 2.4) with b_hat already in place.
+int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double* p, double rtol, int max_iter,
+        bool want_true, SolveOut* out) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_status_reset(G, 0, s));
+  if (src == X_FROM_P) {
+    LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
+    LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
+  } else {
+    if (src == X_ZERO) LCHK(g, launch_zero_spec(G, g->xh, s));
+    LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+  }
+  int rc = init_residual(g, m, r);
+  if (rc) return rc;
+  const double tol2 = rtol * rtol;
+  LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
+
+  // Iterations are queued in chunks; after each chunk the status is copied to
+  // pinned memory, and the host waits on the copy of the PREVIOUS chunk, so the
+  // GPU always has queued work.  Kernels launched after the stop are no-ops.
+  int it = 0;
+  int slot = 0, pending = -1;
+  bool first_chunk = true;
+  while (it < max_iter) {
+    int n = first_chunk ? (g->last_iters > 6 ? g->last_iters - 4 : 2) : 3;
+    first_chunk = false;
+    if (n > max_iter - it) n = max_iter - it;
+    for (int k = 0; k < n; ++k) {
+      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, s));
+      LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s));
+      LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2, s));
+      ++it;
+    }
+    HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(g, hipEventRecord(g->ev[slot], s));
+    if (pending >= 0) {
+      HIPCHK(g, hipEventSynchronize(g->ev[pending]));
+      if (g->hst[pending].conv_at != INT_MAX) break;
+    }
+    pending = slot;
+    slot ^= 1;
+  }
+  DevStatus fin;
+  rc = read_status(g, &fin);
+  if (rc) return rc;
+  out->iters = fin.iters;
+  out->converged = fin.converged;
+  out->flags = fin.flags;
+  out->sticky = fin.sticky;
+  const double rrf = fin.rr[fin.iters & 1];
+  out->rel_res = fin.bb > 0.0 ? std::sqrt(rrf > 0.0 ? rrf : 0.0) / std::sqrt(fin.bb) : 0.0;
+  out->true_rel_res = -1.0;
+  if (fin.iters > 0 || fin.converged) g->last_iters = fin.iters;
+  if (want_true && !(fin.flags & FLAG_INCOMPAT)) {
+    LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+    rc = init_residual(g, m, r);
+    if (rc) return rc;
+    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_P3INIT), 3, col_nwg(G), 0, s));
+    DevStatus t;
+    rc = read_status(g, &t);
+    if (rc) return rc;
+    out->true_rel_res = t.out[2] > 0.0 ? std::sqrt(t.out[1] / t.out[2]) : 0.0;
+  }
+  return NF_OK;
+}
+
+int check_fields(nf_grid* g, std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (!q) return fail(g, NF_EINVAL, "NULL field pointer");
+  return NF_OK;
+}
+
+int check_params(nf_grid* g, const nf_params* prm, double dt) {
+  if (!prm) return fail(g, NF_EINVAL, "NULL params");
+  if (!(dt > 0.0)) return fail(g, NF_EINVAL, "dt must be > 0");
+  if (!(prm->gamma > 0.0)) return fail(g, NF_EINVAL, "gamma must be > 0");
+  if (!(prm->c2 >= 0.0)) return fail(g, NF_EINVAL, "c2 must be >= 0");
+  if (!(prm->D2 >= 0.0)) return fail(g, NF_EINVAL, "D2 must be >= 0");
+  return NF_OK;
+}
+
+int solve_status_code(nf_grid* g, const SolveOut& so) {
+  if ((so.flags | so.sticky) & FLAG_NONFINITE)
+    return fail(g, NF_ENONFINITE, "non-finite values (activation overflow: c^2 |grad p|^2 dt too large, or NaN input)");
+  if (so.flags & FLAG_INCOMPAT) return fail(g, NF_EINCOMPAT, "S violates the solvability condition (sum S != 0)");
+  if (!so.converged) return fail(g, NF_ENOTCONV, "PCG did not reach the tolerance within max_iter");
+  return NF_OK;
+}
+
+// Step 2 of Algorithm 1 on the current x_hat: writes p = F^-1 x_hat, advances
+// m in place, leaves the partials of Delta m (and of ||grad m_new||^2 if egm).
+int split_update(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, bool egm) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_col_grad(G, g->xh, g->mix[0], g->mix[1], g->mix[2], s));
+  LCHK(g, launch_row_split(G, g->mix[0], g->mix[1], g->mix[2], m, p, prm->c2 * dt, prm->gamma, dt, std::exp(-dt), s));
+  LCHK(g, launch_col_heat(G, g->mix[0], g->mix[1], prm->D2 * dt, egm ? slot_ptr(g->part, SLOT_EGM) : nullptr, s));
+  LCHK(g, launch_row_final(G, g->mix[0], g->mix[1], m, slot_ptr(g->part, SLOT_DM), s));
+  return NF_OK;
+}
+
+// Pointwise energy terms of (m, p = F^-1 x_hat) into status.out[4..6]
+int energy_pointwise(nf_grid* g, const nf_params* prm, const double* m, const double* r) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+  LCHK(g, launch_row_energy(G, g->mix[0], g->mix[1], m, r, prm->gamma, slot_ptr(g->part, SLOT_EPT), s));
+  LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EPT), 3, row_nwg(G), 4, s));
+  return NF_OK;
+}
+
+double assemble_energy(const nf_grid* g, const nf_params* prm, double gradm2_phys, const double* pt, double* terms) {
+  const double n = (double)g->nx * g->ny;
+  const double hvol = g->lx * g->ly / n;
+  const double e_diff = 0.5 * prm->D2 * hvol * gradm2_phys;
+  const double e_relax = hvol * pt[2] / (2.0 * prm->gamma);
+  const double e_act = 0.5 * prm->c2 * hvol * pt[1];
+  const double e_flow = 0.5 * prm->c2 * hvol * pt[0];
+  const double tot = e_diff + e_relax + e_act + e_flow;
+  if (terms) {
+    terms[0] = tot;
+    terms[1] = e_diff;
+    terms[2] = e_relax;
+    terms[3] = e_act;
+    terms[4] = e_flow;
+  }
+  return tot;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nf_version(void) { return kVersion; }
+
+const char* nf_last_error(const nf_grid* g) { return g ? g->err.c_str() : "NULL handle"; }
+
+int nf_set_stream(nf_grid* g, void* stream) {
+  if (!g) return NF_EINVAL;
+  g->stream = (hipStream_t)stream;
+  return NF_OK;
+}
+
+int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3], int dtype, void* stream) {
+  if (!out) return NF_EINVAL;
+  *out = nullptr;
+  if (ndim != 2 || !n || !L || dtype != NF_F64) return NF_EINVAL;
+  if (!is_pow2_in_range(n[0]) || !is_pow2_in_range(n[1])) return NF_EINVAL;
+  if (!(L[0] > 0.0) || !(L[1] > 0.0)) return NF_EINVAL;
+  nf_grid* g = new nf_grid();
+  g->nx = (int)n[0];
+  g->ny = (int)n[1];
+  g->h = g->nx / 2;
+  g->lx = L[0];
+  g->ly = L[1];
+  g->stream = (hipStream_t)stream;
+  int rc = NF_OK;
+  auto bail = [&](int code) {
+    nf_destroy_grid(g);
+    return code;
+  };
+  if (hipGetDevice(&g->device) != hipSuccess) return bail(NF_EDEVICE);
+  const int twn = g->nx > g->ny ? g->nx : g->ny;
+  g->twlog = ilog2i(twn);
+  const size_t spec_bytes = (size_t)g->h * g->ny * 2 * sizeof(double);
+  void** bufs[] = {&g->xh, &g->rh, &g->dh, &g->qh, &g->bh, &g->mix[0], &g->mix[1], &g->mix[2]};
+  for (void** b : bufs)
+    if (hipMalloc(b, spec_bytes) != hipSuccess) return bail(NF_ENOMEM);
+  if (hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)) != hipSuccess) return bail(NF_ENOMEM);
+  if (hipMalloc((void**)&g->part, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)) != hipSuccess)
+    return bail(NF_ENOMEM);
+  if (hipMalloc((void**)&g->st, sizeof(DevStatus)) != hipSuccess) return bail(NF_ENOMEM);
+  if (hipHostMalloc((void**)&g->hst, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+    return bail(NF_ENOMEM);
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming) != hipSuccess) return bail(NF_EDEVICE);
+  {
+    double* h = new double[2 * (size_t)twn];
+    make_twiddles(twn, h);
+    hipError_t e = hipMemcpy(g->tw, h, (size_t)twn * 2 * sizeof(double), hipMemcpyHostToDevice);
+    delete[] h;
+    if (e != hipSuccess) return bail(NF_EDEVICE);
+  }
+  if (hipMemset(g->part, 0, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)) != hipSuccess) return bail(NF_EDEVICE);
+  if (hipMemset(g->st, 0, sizeof(DevStatus)) != hipSuccess) return bail(NF_EDEVICE);
+  if (hipMemset(g->xh, 0, spec_bytes) != hipSuccess) return bail(NF_EDEVICE);
+  Geo& G = g->geo;
+  G.nx = g->nx;
+  G.ny = g->ny;
+  G.h = g->h;
+  G.twlog = g->twlog;
+  G.lx = g->lx;
+  G.ly = g->ly;
+  G.inv_n = 1.0 / ((double)g->nx * (double)g->ny);
+  G.tw = g->tw;
+  G.st = g->st;
+  G.part = g->part;
+  *out = g;
+  return rc;
+}
+
+int nf_destroy_grid(nf_grid* g) {
+  if (!g) return NF_OK;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  void* bufs[] = {g->xh, g->rh, g->dh, g->qh, g->bh, g->mix[0], g->mix[1], g->mix[2], g->tw, g->part, g->st};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (g->hst) (void)hipHostFree(g->hst);
+  for (int i = 0; i < 2; ++i)
+    if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+  delete g;
+  return NF_OK;
+}
+
+int nf_transform_forward(nf_grid* g, const double* f, double* out) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  int rc = check_fields(g, {f, out});
+  if (rc) return rc;
+  LCHK(g, launch_row_r2c(g->geo, f, g->mix[0], nullptr, g->stream));
+  LCHK(g, launch_col_fwd(g->geo, g->mix[0], out, 2, nullptr, nullptr, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return NF_OK;
+}
+
+int nf_transform_inverse(nf_grid* g, const double* spec, double* f) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  int rc = check_fields(g, {spec, f});
+  if (rc) return rc;
+  LCHK(g, launch_col_grad(g->geo, spec, g->mix[0], nullptr, nullptr, g->stream));
+  LCHK(g, launch_row_c2r(g->geo, g->mix[0], f, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return NF_OK;
+}
+
+int nf_apply_operator(nf_grid* g, const double* m, const double* r, const double* p, double* out) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  int rc = check_fields(g, {m, r, p, out});
+  if (rc) return rc;
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_status_reset(G, 1, s));
+  LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
+  LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
+  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, nullptr, s));
+  LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->xh, g->xh, g->bh, 0, 0, s));
+  LCHK(g, launch_col_grad(G, g->qh, g->mix[0], nullptr, nullptr, s));
+  LCHK(g, launch_row_c2r(G, g->mix[0], out, s));
+  HIPCHK(g, hipStreamSynchronize(s));
+  return NF_OK;
+}
+
+int nf_pressure_solve(nf_grid* g, const double* m, const double* r, const double* S, double* p, double rtol,
+                      int max_iter, nf_solve_info* info) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  LCHK(g, launch_status_reset(g->geo, 1, g->stream));
+  int rc = check_fields(g, {m, r, S, p});
+  if (rc) return rc;
+  if (!(rtol >= 0.0) || max_iter < 0) return fail(g, NF_EINVAL, "rtol must be >= 0 and max_iter >= 0");
+  rc = compute_rhs(g, S);
+  if (rc) return rc;
+  SolveOut so;
+  rc = pcg(g, m, r, X_FROM_P, p, rtol, max_iter, info != nullptr, &so);
+  if (rc) return rc;
+  if (so.flags & FLAG_INCOMPAT) return solve_status_code(g, so);
+  // p = F^-1 x_hat
+  LCHK(g, launch_col_grad(g->geo, g->xh, g->mix[0], nullptr, nullptr, g->stream));
+  LCHK(g, launch_row_c2r(g->geo, g->mix[0], p, g->stream));
+  if (info) {
+    info->iters = so.iters;
+    info->converged = so.converged;
+    info->rel_res = so.rel_res;
+    info->true_rel_res = so.true_rel_res;
+  }
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return solve_status_code(g, so);
+}
+
+int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, const double* r, const double* S,
+            double rtol, int max_iter, nf_step_info* info) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  LCHK(g, launch_status_reset(g->geo, 1, g->stream));
+  int rc = check_fields(g, {m, p, r, S});
+  if (rc) return rc;
+  rc = check_params(g, prm, dt);
+  if (rc) return rc;
+  if (!(rtol >= 0.0) || max_iter < 0) return fail(g, NF_EINVAL, "rtol must be >= 0 and max_iter >= 0");
+  rc = compute_rhs(g, S);
+  if (rc) return rc;
+  SolveOut so;
+  rc = pcg(g, m, r, X_FROM_P, p, rtol, max_iter, false, &so);
+  if (rc) return rc;
+  if (so.flags & FLAG_INCOMPAT) return solve_status_code(g, so);
+  rc = split_update(g, prm, dt, m, p, false);
+  if (rc) return rc;
+  LCHK(g, launch_sum_slot(g->geo, slot_ptr(g->part, SLOT_DM), 2, row_nwg(g->geo), 8, g->stream));
+  DevStatus fin;
+  rc = read_status(g, &fin);
+  if (rc) return rc;
+  if (info) {
+    info->solve.iters = so.iters;
+    info->solve.converged = so.converged;
+    info->solve.rel_res = so.rel_res;
+    info->solve.true_rel_res = so.true_rel_res;
+    info->dm_rel = fin.out[9] > 0.0 ? std::sqrt(fin.out[8] / fin.out[9]) / dt : 0.0;
+  }
+  if (fin.sticky & FLAG_NONFINITE)
+    return fail(g, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step");
+  return solve_status_code(g, so);
+}
+
+int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p, const double* r, const double* S,
+              double out[5]) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  LCHK(g, launch_status_reset(g->geo, 1, g->stream));
+  int rc = check_fields(g, {m, r, S, out});
+  if (rc) return rc;
+  if (!prm || !(prm->gamma > 0.0)) return fail(g, NF_EINVAL, "invalid params");
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  if (p) {
+    LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
+    LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 0, nullptr, nullptr, s));
+  } else {
+    rc = compute_rhs(g, S);
+    if (rc) return rc;
+    SolveOut so;
+    rc = pcg(g, m, r, X_ZERO, nullptr, 1e-12, 1000, false, &so);
+    if (rc) return rc;
+    rc = solve_status_code(g, so);
+    if (rc) return rc;
+  }
+  const size_t n = (size_t)g->nx * g->ny;
+  LCHK(g, launch_row_r2c(G, m, g->mix[0], nullptr, s));
+  LCHK(g, launch_row_r2c(G, m + n, g->mix[1], nullptr, s));
+  LCHK(g, launch_col_gradnorm(G, g->mix[0], g->mix[1], slot_ptr(g->part, SLOT_EGM), s));
+  LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 3, s));
+  rc = energy_pointwise(g, prm, m, r);
+  if (rc) return rc;
+  DevStatus fin;
+  rc = read_status(g, &fin);
+  if (rc) return rc;
+  const double gradm2 = fin.out[3] / (double)n;  // (1/n) sum w |xi|^2 |DFT m|^2
+  assemble_energy(g, prm, gradm2, &fin.out[4], out);
+  return NF_OK;
+}
+
+int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, double eps_dm,
+           int stop_on_energy_increase, double* m, double* p, const double* r, const double* S, double rtol,
+           int max_iter, nf_run_info* info) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  LCHK(g, launch_status_reset(g->geo, 1, g->stream));
+  int rc = check_fields(g, {m, p, r, S});
+  if (rc) return rc;
+  rc = check_params(g, prm, dt);
+  if (rc) return rc;
+  if (!(rtol >= 0.0) || max_iter < 0 || max_steps < 1)
+    return fail(g, NF_EINVAL, "rtol >= 0, max_iter >= 0 and max_steps >= 1 required");
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny;
+  nf_run_info ri;
+  ri.steps = 0;
+  ri.stop_reason = NF_STOP_MAX_STEPS;
+  ri.last_dm = NAN;
+  ri.last_energy = NAN;
+  ri.prev_energy = NAN;
+  ri.total_cg_iters = 0;
+  const bool en = stop_on_energy_increase != 0;
+  const bool need_sync = en || eps_dm > 0.0;
+
+  rc = compute_rhs(g, S);
+  if (rc) return rc;
+  SolveOut so;
+  rc = pcg(g, m, r, X_FROM_P, p, rtol, max_iter, false, &so);
+  if (rc) return rc;
+  ri.total_cg_iters += so.iters;
+  rc = solve_status_code(g, so);
+  if (rc) {
+    if (info) *info = ri;
+    return rc;
+  }
+  double e_prev = NAN;
+  if (en) {
+    LCHK(g, launch_row_r2c(G, m, g->mix[0], nullptr, s));
+    LCHK(g, launch_row_r2c(G, m + n, g->mix[1], nullptr, s));
+    LCHK(g, launch_col_gradnorm(G, g->mix[0], g->mix[1], slot_ptr(g->part, SLOT_EGM), s));
+    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 3, s));
+    rc = energy_pointwise(g, prm, m, r);
+    if (rc) return rc;
+    DevStatus t;
+    rc = read_status(g, &t);
+    if (rc) return rc;
+    e_prev = assemble_energy(g, prm, t.out[3] / (double)n, &t.out[4], nullptr);
+    ri.last_energy = e_prev;
+  }
+  while (ri.steps < max_steps) {
+    rc = split_update(g, prm, dt, m, p, en);
+    if (rc) return rc;
+    // keep Delta m and ||grad m_new||^2 before the solve reuses the status block
+    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_DM), 2, row_nwg(G), 8, s));
+    if (en) LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 10, s));
+    DevStatus pre;
+    if (need_sync) {
+      rc = read_status(g, &pre);
+      if (rc) return rc;
+    }
+    rc = pcg(g, m, r, X_FROM_XH, nullptr, rtol, max_iter, false, &so);
+    if (rc) return rc;
+    ri.steps += 1;
+    ri.total_cg_iters += so.iters;
+    if ((so.flags | so.sticky) & FLAG_NONFINITE) {
+      ri.stop_reason = NF_STOP_ERROR;
+      if (info) *info = ri;
+      return fail(g, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step");
+    }
+    rc = solve_status_code(g, so);
+    if (rc) {
+      ri.stop_reason = NF_STOP_ERROR;
+      if (info) *info = ri;
+      return rc;
+    }
+    if (need_sync) {
+      const double dm = pre.out[9] > 0.0 ? std::sqrt(pre.out[8] / pre.out[9]) / dt : 0.0;
+      ri.last_dm = dm;
+      if (en) {
+        rc = energy_pointwise(g, prm, m, r);
+        if (rc) return rc;
+        DevStatus t;
+        rc = read_status(g, &t);
+        if (rc) return rc;
+        const double e = assemble_energy(g, prm, pre.out[10] * (double)n, &t.out[4], nullptr);
+        ri.prev_energy = e_prev;
+        ri.last_energy = e;
+        if (e >= e_prev) {
+          ri.stop_reason = NF_STOP_ENERGY_INCREASE;
+          break;
+        }
+        e_prev = e;
+      }
+      if (dm <= eps_dm) {
+        ri.stop_reason = NF_STOP_DM_BELOW_EPS;
+        break;
+      }
+    }
+  }
+  if (!need_sync) {
+    // Delta m of the last step (its partials are still in place)
+    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_DM), 2, row_nwg(G), 8, s));
+    DevStatus t;
+    rc = read_status(g, &t);
+    if (rc) return rc;
+    ri.last_dm = t.out[9] > 0.0 ? std::sqrt(t.out[8] / t.out[9]) / dt : 0.0;
+    if (t.sticky & FLAG_NONFINITE) {
+      ri.stop_reason = NF_STOP_ERROR;
+      if (info) *info = ri;
+      return fail(g, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step");
+    }
+  }
+  // p = p[m_final]
+  LCHK(g, launch_col_grad(G, g->xh, g->mix[0], nullptr, nullptr, s));
+  LCHK(g, launch_row_c2r(G, g->mix[0], p, s));
+  HIPCHK(g, hipStreamSynchronize(s));
+  if (info) *info = ri;
+  return NF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,299 @@
+// Device-side building blocks of the spectral solver: complex arithmetic,
+// radix-2/4/8 butterflies, an in-LDS Stockham autosort FFT over a batch of
+// lines, the real<->half-complex post/pre-processing of the x transform, and
+// deterministic workgroup reductions.
+//
+// The FFT replaces the paper's CPU FFT library (Sec. 2.3.3); transforms are
+// unnormalised in both directions, normalisation is folded into the spectral
+// multipliers by the callers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nf {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> scl(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return mk<T>(a.x, -a.y); }
+// a * b
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
+  return mk<T>(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// multiply by i (DIR=+1) or -i (DIR=-1)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  return DIR > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+// multiply by e^{DIR i pi/4}
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_w8(cx<T> a) {
+  const T s = (T)0.70710678118654752440;
+  return DIR > 0 ? mk<T>((a.x - a.y) * s, (a.x + a.y) * s) : mk<T>((a.x + a.y) * s, (a.y - a.x) * s);
+}
+// multiply by e^{DIR 3 i pi/4}
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_w83(cx<T> a) {
+  const T s = (T)0.70710678118654752440;
+  return DIR > 0 ? mk<T>(-(a.x + a.y) * s, (a.x - a.y) * s) : mk<T>((a.y - a.x) * s, -(a.x + a.y) * s);
+}
+
+// ---------------------------------------------------------------- butterflies
+// In-place DFT of size R on v[0..R-1]: v_m <- sum_q v_q e^{DIR 2 pi i q m / R}.
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = add(a, b);
+  v[1] = sub(a, b);
+}
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>& b0, cx<T>& b1, cx<T>& b2, cx<T>& b3) {
+  cx<T> s02 = add(b0, b2), d02 = sub(b0, b2);
+  cx<T> s13 = add(b1, b3), d13 = mul_i<DIR>(sub(b1, b3));
+  b0 = add(s02, s13);
+  b2 = sub(s02, s13);
+  b1 = add(d02, d13);
+  b3 = sub(d02, d13);
+}
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  dft4<DIR>(v[0], v[1], v[2], v[3]);
+}
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  // decimation in frequency: even outputs from v_q + v_{q+4}, odd outputs from
+  // (v_q - v_{q+4}) w8^q, each followed by a 4-point DFT
+  cx<T> a0 = add(v[0], v[4]), a4 = sub(v[0], v[4]);
+  cx<T> a1 = add(v[1], v[5]), a5 = sub(v[1], v[5]);
+  cx<T> a2 = add(v[2], v[6]), a6 = sub(v[2], v[6]);
+  cx<T> a3 = add(v[3], v[7]), a7 = sub(v[3], v[7]);
+  a5 = mul_w8<DIR>(a5);
+  a6 = mul_i<DIR>(a6);
+  a7 = mul_w83<DIR>(a7);
+  dft4<DIR>(a0, a1, a2, a3);
+  dft4<DIR>(a4, a5, a6, a7);
+  v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+  v[1] = a4; v[3] = a5; v[5] = a6; v[7] = a7;
+}
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else dft8<DIR>(v);
+}
+
+// ---------------------------------------------------------------- radix plan
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+// Radix of stage s for a length-2^p transform: 8s first, tails 4 or 4,4 or a lone 2.
+constexpr int plan_nstages(int p) {
+  return p <= 2 ? 1 : (p % 3 == 0 ? p / 3 : (p % 3 == 2 ? p / 3 + 1 : p / 3 + 1));
+}
+constexpr int plan_radix(int p, int s) {
+  if (p == 1) return 2;
+  if (p == 2) return 4;
+  if (p % 3 == 0) return 8;
+  if (p % 3 == 2) return s < p / 3 ? 8 : 4;
+  // p % 3 == 1: (p/3 - 1) eights then 4, 4
+  return s < p / 3 - 1 ? 8 : 4;
+}
+constexpr int plan_ns(int p, int s) {  // product of radices before stage s
+  return s == 0 ? 1 : plan_ns(p, s - 1) * plan_radix(p, s - 1);
+}
+
+// Twiddle e^{DIR 2 pi i t / M} from the table tw[u] = e^{-2 pi i u / TWN}.
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int t, int shift) {
+  cx<T> w = tw[t << shift];
+  return DIR > 0 ? conj(w) : w;
+}
+
+// One Stockham stage over B lines of length L stored at buf + line*LS.
+// Inputs are read at stride L/R, outputs written in autosort order.
+template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+  constexpr int Q = L / R;          // butterflies per line
+  constexpr int NBF = B * Q;        // butterflies in the batch
+  constexpr int PER = (NBF + NT - 1) / NT;
+  constexpr bool EXACT = (PER * NT == NBF);
+  const int tid = threadIdx.x;
+  cx<T> v[PER][R];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int f = tid + b * NT;
+    if (EXACT || f < NBF) {
+      const int line = f / Q, j = f % Q;
+      const cx<T>* src = buf + line * LS + j;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[b][q] = src[q * Q];
+    }
+  }
+  __syncthreads();
+  // twiddle index shift: the table has TWN = 2^twlog entries, this stage needs
+  // angles in units of 2 pi / (NS R)
+  const int shift = twlog - ilog2(NS * R);
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int f = tid + b * NT;
+    if (EXACT || f < NBF) {
+      const int line = f / Q, j = f % Q;
+      const int k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[b][q] = mul(v[b][q], twiddle<DIR>(tw, q * k, shift));
+      }
+      dft<R, DIR>(v[b]);
+      cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[q * NS] = v[b][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIR, int L, int B, int LS, int NT, int S>
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+  constexpr int P = ilog2(L);
+  if constexpr (S < plan_nstages(P)) {
+    fft_stage<T, DIR, L, B, LS, NT, plan_radix(P, S), plan_ns(P, S)>(buf, tw, twlog);
+    fft_stages<T, DIR, L, B, LS, NT, S + 1>(buf, tw, twlog);
+  }
+}
+
+// In-LDS FFT of B lines of length L (line stride LS), all NT threads taking part.
+// Caller must __syncthreads() before (data written) -- the routine ends with a barrier.
+template <typename T, int DIR, int L, int B, int LS, int NT>
+__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+  fft_stages<T, DIR, L, B, LS, NT, 0>(buf, tw, twlog);
+}
+
+// ------------------------------------------------- real <-> half-complex (x axis)
+// A real line f[0..N-1], N = 2H, is packed as z[j] = f[2j] + i f[2j+1] and
+// transformed with a length-H complex FFT Z.  rfft_post turns Z into the first H
+// coefficients X[0..H-1] of the length-N DFT, with the (real) X[0] and X[H]
+// packed into slot 0 as X[0] + i X[H].  irfft_pre is its inverse (up to the
+// factor N of an unnormalised inverse): it rebuilds 2 Z from the packed X, so
+// that an unnormalised length-H inverse FFT gives N (f[2j] + i f[2j+1]).
+// Both work on B lines in place; one thread per pair (k, H-k), k in [0, H/2).
+template <typename T, int H, int B, int LS, int NT>
+__device__ __forceinline__ void rfft_post(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+  constexpr int NP = H / 2;  // pairs per line (pair 0 also handles k = H/2)
+  constexpr int NTASK = B * NP;
+  const int shift = twlog - ilog2(2 * H);
+  for (int t = threadIdx.x; t < NTASK; t += NT) {
+    const int line = t / NP, k = t % NP;
+    cx<T>* l = buf + line * LS;
+    if (k == 0) {
+      cx<T> z0 = l[0];
+      l[0] = mk<T>(z0.x + z0.y, z0.x - z0.y);
+      if (H >= 2) {
+        // self-paired k = H/2: w^{H/2} = -i, X = conj(Z)
+        cx<T> zh = l[H / 2];
+        l[H / 2] = conj(zh);
+      }
+    } else {
+      cx<T> zk = l[k], zm = l[H - k];
+      cx<T> w = tw[k << shift];                      // e^{-2 pi i k / N}
+      // X[k]   = (zk + conj zm)/2 - (i/2) w (zk - conj zm)
+      // X[H-k] = (zm + conj zk)/2 + (i/2) conj(w) (zm - conj zk)
+      cx<T> e1 = add(zk, conj(zm)), o1 = sub(zk, conj(zm));
+      cx<T> e2 = add(zm, conj(zk)), o2 = sub(zm, conj(zk));
+      cx<T> t1 = mul_i<-1>(mul(w, o1));
+      cx<T> t2 = mul_i<+1>(mul(conj(w), o2));
+      l[k] = scl(add(e1, t1), (T)0.5);
+      l[H - k] = scl(add(e2, t2), (T)0.5);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int H, int B, int LS, int NT>
+__device__ __forceinline__ void irfft_pre(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+  constexpr int NP = H / 2;
+  constexpr int NTASK = B * NP;
+  const int shift = twlog - ilog2(2 * H);
+  for (int t = threadIdx.x; t < NTASK; t += NT) {
+    const int line = t / NP, k = t % NP;
+    cx<T>* l = buf + line * LS;
+    if (k == 0) {
+      cx<T> p = l[0];  // X[0] + i X[H]
+      l[0] = mk<T>(p.x + p.y, p.x - p.y);
+      if (H >= 2) {
+        // self-paired k = H/2: 2 Z = 2 conj(X)
+        cx<T> xh = l[H / 2];
+        l[H / 2] = mk<T>(xh.x + xh.x, -(xh.y + xh.y));
+      }
+    } else {
+      cx<T> xk = l[k], xm = l[H - k];
+      cx<T> w = tw[k << shift];  // e^{-2 pi i k / N}
+      // 2Z[k]   = (xk + conj xm) + i conj(w) (xk - conj xm)
+      // 2Z[H-k] = (xm + conj xk) - i w (xm - conj xk)
+      cx<T> e1 = add(xk, conj(xm)), o1 = sub(xk, conj(xm));
+      cx<T> e2 = add(xm, conj(xk)), o2 = sub(xm, conj(xk));
+      l[k] = add(e1, mul_i<+1>(mul(conj(w), o1)));
+      l[H - k] = add(e2, mul_i<-1>(mul(w, o2)));
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic workgroup sum of K doubles per thread: wavefront butterfly via
+// shuffles, then a fixed-order pass over the waves.  Every thread gets the result.
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* scratch /* >= K*NT/64 */) {
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scratch[k * NW + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += scratch[k * NW + w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Sum K arrays of n partials (layout part[k*stride + i]) in a fixed order; the
+// result is bitwise identical in every workgroup that calls it.
+template <int NT, int K>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int n, int stride,
+                                             double (&out)[K], double* scratch) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) s += part[k * stride + i];
+    out[k] = s;
+  }
+  block_sum<NT, K>(out, scratch);
+}
+
+}  // namespace nf

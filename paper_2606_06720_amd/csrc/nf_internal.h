@@ -1,0 +1,90 @@
+// Structures shared by the host driver and the kernels (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nf {
+
+// Device-resident solver status.  Written by exactly one workgroup (block 0)
+// of the kernel that owns each field; read by later launches and copied to the
+// host for convergence checks.
+struct DevStatus {
+  double kbar[4];   // grid mean of K = m m^T + r I: Kxx, Kxy, Kyy, (unused)
+  double bb;        // weighted ||b_hat||^2 of the projected right-hand side
+  double rho[2];    // <r, M^-1 r> by iteration parity
+  double rr[2];     // ||r||^2 by iteration parity
+  double rr0;       // initial ||r||^2
+  double out[16];   // results of the final reductions (energy terms, dm, ...)
+  int conv_at;      // iteration at which PCG stopped (converged or max_iter); INT_MAX while running
+  int converged;    // 1 if the stop was convergence
+  int iters;        // PCG iterations done
+  int flags;        // FLAG_* bits of the current PCG solve
+  int sticky;       // FLAG_* bits raised since the last full reset (split update)
+  int pad[3];
+};
+
+enum { FLAG_NONFINITE = 1, FLAG_INCOMPAT = 2 };
+
+// Slots of the partial-sum area; each slot holds up to SLOT_K arrays of
+// MAX_WG doubles.
+enum {
+  SLOT_P3 = 0,      // <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>, <r,M^-1 r>, <r,r>
+  SLOT_P3INIT = 1,  // <r,M^-1 r>, <r,r>, <b,b>
+  SLOT_KBAR = 2,    // sum mx^2, mx my, my^2, r
+  SLOT_SCHK = 3,    // sum S, sum |S|
+  SLOT_DM = 4,      // sum (m_new - m_old)^2, sum m_old^2
+  SLOT_EPT = 5,     // sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
+  SLOT_EGM = 6,     // sum w |xi|^2 |m_hat|^2 (both components)
+  NSLOTS = 8,
+  SLOT_K = 8,
+  MAX_WG = 4096,
+};
+
+// Geometry and workspace pointers passed by value to every kernel.
+struct Geo {
+  int nx, ny, h, twlog;
+  double lx, ly;
+  double inv_n;
+  const void* tw;     // cx<double>[2^twlog], tw[u] = exp(-2 pi i u / 2^twlog)
+  DevStatus* st;
+  double* part;       // NSLOTS * SLOT_K * MAX_WG doubles
+};
+
+__host__ __device__ inline double* slot_ptr(double* part, int slot) {
+  return part + (size_t)slot * SLOT_K * MAX_WG;
+}
+
+// ---- host-callable launchers (defined in nf_kernels.hip) --------------------------
+// All take the stream last and return hipError_t of the launch.
+struct Bufs;
+
+hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s);
+hipError_t launch_zero_spec(const Geo& g, void* xh, hipStream_t s);
+// row passes (physical <-> mixed)
+int row_nwg(const Geo& g);
+int col_nwg(const Geo& g);
+hipError_t launch_row_r2c(const Geo& g, const double* f, void* out_mixed, double* schk_slot, hipStream_t s);
+hipError_t launch_row_c2r(const Geo& g, const void* in_mixed, double* f, hipStream_t s);
+hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
+                           double* kbar_slot, hipStream_t s);
+hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
+                            double c2dt, double gamma, double dt, double relax_gamma1, hipStream_t s);
+hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dm_slot,
+                            hipStream_t s);
+hipError_t launch_row_energy(const Geo& g, const void* Gx, const void* Gy, const double* m, const double* r,
+                             double gamma, double* slot, hipStream_t s);
+// column passes (mixed <-> spectral)
+hipError_t launch_col_fwd(const Geo& g, void* in_mixed, void* out_spec, int with_grad, void* Gx, void* Gy,
+                          hipStream_t s);
+hipError_t launch_col_grad(const Geo& g, const void* xh, void* P, void* Gx, void* Gy, hipStream_t s);
+hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy, void* qh, const void* dh,
+                          void* rh, const void* bh, int it, int nwg_row, hipStream_t s);
+hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
+                             void* Gy, int it, int max_iter, double tol2, hipStream_t s);
+hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* egm_slot, hipStream_t s);
+hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* egm_slot, hipStream_t s);
+// reduce K arrays of n partials of a slot into st->out[o..o+K)
+hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o, hipStream_t s);
+
+}  // namespace nf

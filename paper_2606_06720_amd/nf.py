@@ -1,0 +1,292 @@
+"""Python binding of the C ABI in ``include/nf.h`` (argument marshalling only).
+
+Every call goes straight to ``libnf.so``; all arithmetic of the time step runs in
+the library's HIP kernels.  Fields are torch tensors on the current HIP device
+(float64, C-contiguous): scalars ``[Ny, Nx]``, the conductivity ``m`` as
+``[2, Ny, Nx]`` with component 0 = m_x.  The handle enqueues on torch's current
+stream at each call.
+
+If the library is missing this module raises on import: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnf.so")
+
+NF_OK = 0
+NF_EINVAL = -1
+NF_ENOMEM = -2
+NF_EDEVICE = -3
+NF_ENOTCONV = -4
+NF_EINCOMPAT = -5
+NF_ENONFINITE = -6
+NF_F64 = 0
+NF_STOP_MAX_STEPS = 0
+NF_STOP_DM_BELOW_EPS = 1
+NF_STOP_ENERGY_INCREASE = 2
+NF_STOP_ERROR = 3
+
+_CODES = {
+    NF_EINVAL: "NF_EINVAL",
+    NF_ENOMEM: "NF_ENOMEM",
+    NF_EDEVICE: "NF_EDEVICE",
+    NF_ENOTCONV: "NF_ENOTCONV",
+    NF_EINCOMPAT: "NF_EINCOMPAT",
+    NF_ENONFINITE: "NF_ENONFINITE",
+}
+
+
+class NfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_CODES.get(code, "NF_?"), code, msg))
+        self.code = code
+
+
+class nf_params(ctypes.Structure):
+    _fields_ = [("c2", ctypes.c_double), ("D2", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class nf_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double)]
+
+
+class nf_step_info(ctypes.Structure):
+    _fields_ = [("solve", nf_solve_info), ("dm_rel", ctypes.c_double)]
+
+
+class nf_run_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("stop_reason", ctypes.c_int), ("last_dm", ctypes.c_double),
+                ("last_energy", ctypes.c_double), ("prev_energy", ctypes.c_double),
+                ("total_cg_iters", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnf.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64p = ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)
+    lib.nf_create_grid.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_int, vp]
+    lib.nf_destroy_grid.argtypes = [vp]
+    lib.nf_set_stream.argtypes = [vp, vp]
+    lib.nf_pressure_solve.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, ctypes.POINTER(nf_solve_info)]
+    lib.nf_step.argtypes = [vp, ctypes.POINTER(nf_params), dp, vp, vp, vp, vp, dp, ctypes.c_int,
+                            ctypes.POINTER(nf_step_info)]
+    lib.nf_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp, vp,
+                           dp, ctypes.c_int, ctypes.POINTER(nf_run_info)]
+    lib.nf_energy.argtypes = [vp, ctypes.POINTER(nf_params), vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nf_transform_forward.argtypes = [vp, vp, vp]
+    lib.nf_transform_inverse.argtypes = [vp, vp, vp]
+    lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
+    lib.nf_last_error.argtypes = [vp]
+    lib.nf_last_error.restype = ctypes.c_char_p
+    lib.nf_version.restype = ctypes.c_char_p
+    for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
+              "nf_energy", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def version():
+    return _lib.nf_version().decode()
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    converged: bool
+    rel_res: float
+    true_rel_res: float
+
+
+@dataclass
+class StepInfo:
+    solve: SolveInfo
+    dm_rel: float
+
+
+@dataclass
+class RunInfo:
+    steps: int
+    stop_reason: int
+    last_dm: float
+    last_energy: float
+    prev_energy: float
+    total_cg_iters: int
+
+
+def _si(s):
+    return SolveInfo(int(s.iters), bool(s.converged), float(s.rel_res), float(s.true_rel_res))
+
+
+def _ptr(t, shape, name):
+    import torch
+
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must be a contiguous float64 device tensor of shape %s (got %s %s %s)"
+                         % (name, tuple(shape), t.dtype, t.device, tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """A solver handle (``nf_create_grid``) for an Nx x Ny periodic box."""
+
+    def __init__(self, n, L=(1.0, 1.0), dtype=NF_F64):
+        n = tuple(int(v) for v in n)
+        if len(n) != 2:
+            raise ValueError("2D grids only")
+        self.n = n
+        self.L = tuple(float(v) for v in L)
+        self._h = ctypes.c_void_p()
+        nn = (ctypes.c_int64 * 3)(n[0], n[1], 1)
+        LL = (ctypes.c_double * 3)(self.L[0], self.L[1], 1.0)
+        rc = _lib.nf_create_grid(ctypes.byref(self._h), 2, nn, LL, int(dtype), _current_stream())
+        if rc != NF_OK:
+            raise NfError(rc, "nf_create_grid failed for n=%s L=%s" % (n, self.L))
+
+    # shapes
+    @property
+    def sshape(self):
+        return (self.n[1], self.n[0])
+
+    @property
+    def vshape(self):
+        return (2, self.n[1], self.n[0])
+
+    def _check(self, rc, allow=()):
+        if rc != NF_OK and rc not in allow:
+            raise NfError(rc, _lib.nf_last_error(self._h).decode())
+        return rc
+
+    def _sync_stream(self):
+        _lib.nf_set_stream(self._h, _current_stream())
+
+    def close(self):
+        if self._h:
+            _lib.nf_destroy_grid(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def pressure_solve(self, m, r, S, p, rtol=1e-10, max_iter=1000, allow_notconv=False):
+        """nf_pressure_solve: p (in: warm start, out: solution). Returns (rc, SolveInfo)."""
+        self._sync_stream()
+        info = nf_solve_info()
+        rc = _lib.nf_pressure_solve(self._h, _ptr(m, self.vshape, "m"), _ptr(r, self.sshape, "r"),
+                                    _ptr(S, self.sshape, "S"), _ptr(p, self.sshape, "p"), float(rtol),
+                                    int(max_iter), ctypes.byref(info))
+        self._check(rc, (NF_ENOTCONV,) if allow_notconv else ())
+        return rc, _si(info)
+
+    def step(self, c2, D2, gamma, dt, m, p, r, S, rtol=1e-10, max_iter=1000, allow_notconv=False):
+        """nf_step: m^k -> m^{k+1} in place, p <- p[m^k]. Returns (rc, StepInfo)."""
+        self._sync_stream()
+        prm = nf_params(float(c2), float(D2), float(gamma))
+        info = nf_step_info()
+        rc = _lib.nf_step(self._h, ctypes.byref(prm), float(dt), _ptr(m, self.vshape, "m"),
+                          _ptr(p, self.sshape, "p"), _ptr(r, self.sshape, "r"), _ptr(S, self.sshape, "S"),
+                          float(rtol), int(max_iter), ctypes.byref(info))
+        self._check(rc, (NF_ENOTCONV,) if allow_notconv else ())
+        return rc, StepInfo(_si(info.solve), float(info.dm_rel))
+
+    def run(self, c2, D2, gamma, dt, max_steps, m, p, r, S, eps_dm=0.0, stop_on_energy_increase=False,
+            rtol=1e-10, max_iter=1000):
+        """nf_run: time loop with the stopping criteria. Returns RunInfo."""
+        self._sync_stream()
+        prm = nf_params(float(c2), float(D2), float(gamma))
+        info = nf_run_info()
+        rc = _lib.nf_run(self._h, ctypes.byref(prm), float(dt), int(max_steps), float(eps_dm),
+                         int(bool(stop_on_energy_increase)), _ptr(m, self.vshape, "m"), _ptr(p, self.sshape, "p"),
+                         _ptr(r, self.sshape, "r"), _ptr(S, self.sshape, "S"), float(rtol), int(max_iter),
+                         ctypes.byref(info))
+        self._check(rc)
+        return RunInfo(int(info.steps), int(info.stop_reason), float(info.last_dm), float(info.last_energy),
+                       float(info.prev_energy), int(info.total_cg_iters))
+
+    def energy(self, c2, D2, gamma, m, r, S, p=None):
+        """nf_energy: (total, D^2/2|grad m|^2, relaxation, c^2/2|m.grad p|^2, c^2/2 r|grad p|^2)."""
+        self._sync_stream()
+        prm = nf_params(float(c2), float(D2), float(gamma))
+        out = (ctypes.c_double * 5)()
+        rc = _lib.nf_energy(self._h, ctypes.byref(prm), _ptr(m, self.vshape, "m"), _ptr(p, self.sshape, "p"),
+                            _ptr(r, self.sshape, "r"), _ptr(S, self.sshape, "S"), out)
+        self._check(rc)
+        return tuple(float(v) for v in out)
+
+
+    # diagnostics -----------------------------------------------------------
+    @property
+    def spec_shape(self):
+        return (self.n[0] // 2, self.n[1], 2)
+
+    def transform_forward(self, f, out):
+        """nf_transform_forward: packed half spectrum [Nx/2][Ny] (re, im) of f."""
+        self._sync_stream()
+        self._check(_lib.nf_transform_forward(self._h, _ptr(f, self.sshape, "f"), _ptr(out, self.spec_shape, "out")))
+
+    def transform_inverse(self, spec, f):
+        """nf_transform_inverse: normalised inverse of a packed half spectrum."""
+        self._sync_stream()
+        self._check(_lib.nf_transform_inverse(self._h, _ptr(spec, self.spec_shape, "spec"), _ptr(f, self.sshape, "f")))
+
+    def apply_operator(self, m, r, p, out):
+        """nf_apply_operator: out = A p (left-hand side of the discrete pressure equation)."""
+        self._sync_stream()
+        self._check(_lib.nf_apply_operator(self._h, _ptr(m, self.vshape, "m"), _ptr(r, self.sshape, "r"),
+                                           _ptr(p, self.sshape, "p"), _ptr(out, self.sshape, "out")))
+
+
+# C-ABI-named aliases ------------------------------------------------------------
+def nf_create_grid(n, L=(1.0, 1.0), dtype=NF_F64):
+    return Grid(n, L, dtype)
+
+
+def nf_destroy_grid(g):
+    g.close()
+
+
+def nf_pressure_solve(g, m, r, S, p, rtol=1e-10, max_iter=1000):
+    return g.pressure_solve(m, r, S, p, rtol, max_iter)
+
+
+def nf_step(g, c2, D2, gamma, dt, m, p, r, S, rtol=1e-10, max_iter=1000):
+    return g.step(c2, D2, gamma, dt, m, p, r, S, rtol, max_iter)
+
+
+def nf_run(g, c2, D2, gamma, dt, max_steps, m, p, r, S, eps_dm=0.0, stop_on_energy_increase=False, rtol=1e-10,
+           max_iter=1000):
+    return g.run(c2, D2, gamma, dt, max_steps, m, p, r, S, eps_dm, stop_on_energy_increase, rtol, max_iter)
+
+
+def nf_energy(g, c2, D2, gamma, m, r, S, p=None):
+    return g.energy(c2, D2, gamma, m, r, S, p)
