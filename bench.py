@@ -1,0 +1,214 @@
+"""Throughput benchmark of the spectral network-formation hot path on one GPU.
+
+Workload: the 2D periodic 1024 x 1024 FP64 case -- r = 0.05 + 0.05 f (f a
+smooth random field of 16 low-wavenumber modes), a Gaussian source/sink pair
+(sigma 0.02), m0 uniform[0,1]^2, D^2 = 1e-4, c^2 = 50, dt = 5e-4, PCG relative
+tolerance 1e-10 -- run for the three metabolic exponents gamma = 0.5, 0.75, 1.0.
+One benchmark step advances all three instances by one time step (PCG solve +
+split update), so a step processes 3 * 1024^2 grid points.  All inputs are
+resident in device memory before the timed region.
+
+Prints one JSON line (metric: grid-point-steps/s) with a roofline entry for the
+dominant kernel (average duration from HIP events on the library's stream over
+the timed region) and a CPU-oracle baseline on a bounded sample.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GAMMAS = (0.5, 0.75, 1.0)
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
+
+# algorithmic bytes per grid point of one launch of each PCG-loop kernel (FP64):
+#   row_flux : reads grad_x, grad_y (2 x 8), m (16), r (8); writes F_x, F_y (2 x 8)
+#   col_div  : reads F_x, F_y (16), d, r (16); writes q (8)
+#   col_update: reads x, d, r, q (32); writes x, r, d (24) and grad_x, grad_y (16)
+KERNEL_BYTES_PER_POINT = {"row_flux": 56.0, "col_div": 40.0, "col_update": 72.0}
+KERNEL_IDS = {"row_flux": 0, "col_div": 1, "col_update": 2}
+KERNEL_SOURCES = ("paper_2606_06720_amd/csrc/nf_kernels.hip", "paper_2606_06720_amd/csrc/nf_fft.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, n):
+    """Counter-derived HBM bytes per launch from the committed profile summary,
+    or None if absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%d.json" % (kernel, n))
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(N, steps):
+    import numpy as np
+
+    import oracle as O
+    from paper_2606_06720_amd import workloads as W
+
+    w = W.dipole_workload(N, 0.75)
+    m, p = w["m0"], None
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m, p, info = O.step(m, p, w["r"], w["S"], w["c2"], w["D2"], w["gamma"], w["dt"], w["rtol"])
+        iters += info.iters
+    dt = time.perf_counter() - t0
+    return {
+        "value": N * N * steps / dt,
+        "unit": "grid-point-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "first %d time steps of the gamma=0.75 instance from m0 at %d^2 (%d PCG iterations, "
+                  "%.1f s; numpy FFT, single thread)" % (steps, N, iters, dt),
+    }
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--kernel", default="row_flux", choices=sorted(KERNEL_IDS))
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); a multi-GPU layout is "
+              "described in the design notes but not implemented" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2606_06720_amd import nf as NF
+    from paper_2606_06720_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    N = args.n
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inst = []
+    for gam in GAMMAS:
+        w = W.dipole_workload(N, gam)
+        g = NF.Grid(w["n"], w["L"])
+        inst.append(dict(w=w, g=g, m0=T(w["m0"]), m=T(w["m0"]), p=torch.zeros((N, N), dtype=torch.float64, device=dev),
+                         r=T(w["r"]), S=T(w["S"])))
+
+    def run_all(steps):
+        infos = []
+        for it in inst:
+            w = it["w"]
+            infos.append(it["g"].run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, it["m"], it["p"], it["r"], it["S"],
+                                     rtol=w["rtol"], max_iter=1000))
+        return infos
+
+    if args.warmup > 0:
+        run_all(args.warmup)
+    for it in inst:
+        it["m"].copy_(it["m0"])
+        it["p"].zero_()
+        it["g"].time_kernel(KERNEL_IDS[args.kernel])
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    infos = run_all(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    kms, kcount = 0.0, 0
+    for it in inst:
+        ms, c = it["g"].time_kernel_read()
+        kms += ms
+        kcount += c
+        it["g"].time_kernel(-1)
+    total_points = len(GAMMAS) * N * N
+    value = total_points * args.steps / elapsed
+    cg_iters = sum(i.total_cg_iters for i in infos)
+
+    avg_s = (kms / 1e3) / max(kcount, 1)
+    alg_bytes = KERNEL_BYTES_PER_POINT[args.kernel] * N * N
+    achieved = alg_bytes / avg_s / 1e9 if kcount else None
+    traffic = load_traffic(args.kernel, N)
+    roofline = {
+        "bound": "hbm",
+        "kernel": args.kernel,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "avg_launch_us": avg_s * 1e6,
+        "launches": kcount,
+    }
+    finite = all(torch.isfinite(it["m"]).all().item() for it in inst)
+
+    out = {
+        "metric": "grid-point-steps/s at 2D 1024^2 (PCG incl.)",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D periodic %dx%d FP64 dipole source/sink, smooth random r, gamma in %s, dt=5e-4, "
+                        "PCG rtol 1e-10; one step = one time step of each gamma instance" % (N, N, list(GAMMAS)),
+            "grid": [N, N],
+            "instances": len(GAMMAS),
+            "grid_points_per_step": total_points,
+            "pcg_iters_per_time_step": cg_iters / (len(GAMMAS) * args.steps),
+            "finite": bool(finite),
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
+    for it in inst:
+        it["g"].close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

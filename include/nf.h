@@ -81,6 +81,7 @@ typedef struct {
   double last_energy;     /* E_h of the final state (NaN if energy stopping was off) */
   double prev_energy;     /* E_h of the state before it (NaN if off) */
   int64_t total_cg_iters; /* PCG iterations over the whole run */
+  int64_t unconverged_solves; /* solves that reached max_iter (the run continues with the last iterate) */
 } nf_run_info;
 
 /*
@@ -136,8 +137,11 @@ int nf_step(nf_grid *g, const nf_params *prm, double dt, double *m, double *p, c
  * p[m^k]; solve p[m^{k+1}] (warm start from the previous solution);
  * Delta m^k; stop if stop_on_energy_increase and E_h(m^{k+1}) >= E_h(m^k), or
  * if Delta m <= eps_dm, or after max_steps steps.  At least one step is taken.
- * On return m holds the final state and p = p[m] for that state.
- * Returns NF_OK (see info->stop_reason) or the first error of a step.
+ * On return m holds the final state and p = p[m] for that state.  A solve that
+ * reaches max_iter does not stop the run (its last iterate is used and counted
+ * in info->unconverged_solves).
+ * Returns NF_OK (see info->stop_reason) or the first error of a step
+ * (NF_EINCOMPAT, NF_ENONFINITE, NF_EINVAL, NF_EDEVICE).
  */
 int nf_run(nf_grid *g, const nf_params *prm, double dt, int64_t max_steps, double eps_dm,
            int stop_on_energy_increase, double *m, double *p, const double *r, const double *S, double rtol,
@@ -174,6 +178,17 @@ int nf_energy(nf_grid *g, const nf_params *prm, const double *m, const double *p
 int nf_transform_forward(nf_grid *g, const double *f, double *out);
 int nf_transform_inverse(nf_grid *g, const double *spec, double *f);
 int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double *p, double *out);
+
+/*
+ * Kernel timing: nf_time_kernel(g, k) makes the handle bracket every launch of
+ * the PCG-loop kernel k (NF_KERNEL_*) with a pair of HIP events on its stream;
+ * launches queued after the solver stopped (which do no work) are discarded.
+ * k = -1 switches timing off.  Both calls reset the accumulators.
+ * nf_time_kernel_read returns the summed event time (ms) and the launch count.
+ */
+enum { NF_KERNEL_ROW_FLUX = 0, NF_KERNEL_COL_DIV = 1, NF_KERNEL_COL_UPDATE = 2 };
+int nf_time_kernel(nf_grid *g, int which);
+int nf_time_kernel_read(nf_grid *g, double *total_ms, int64_t *count);
 
 /* Message describing the last error on the handle ("" if none). */
 const char *nf_last_error(const nf_grid *g);

@@ -101,6 +101,7 @@ class RunInfo:
     last_dm: float = float("nan")
     last_energy: float = float("nan")
     total_cg_iters: int = 0
+    unconverged_solves: int = 0
     energies: list = field(default_factory=list)
     dms: list = field(default_factory=list)
 
@@ -443,11 +444,12 @@ def run(m0, p0, r, S, c2, D2, gamma, dt, max_steps, eps_dm=0.0, stop_on_energy=F
     p[m^0] is solved first; each pass then applies the split update to m^k with
     p[m^k] and solves p[m^{k+1}] (warm start).  After each pass it stops if
     E_h(m^{k+1}) >= E_h(m^k) (when enabled) or Delta m <= eps_dm.  At least one
-    pass is taken.  Returns (m_final, p[m_final], RunInfo).
+    pass is taken.  A solve that reaches max_iter does not stop the run (its
+    last iterate is used and counted).  Returns (m_final, p[m_final], RunInfo).
     """
     m = np.array(m0, dtype=np.float64, copy=True)
     p, info = pressure_pcg(m, r, S, p0, rtol, max_iter, L)
-    ri = RunInfo(total_cg_iters=info.iters)
+    ri = RunInfo(total_cg_iters=info.iters, unconverged_solves=int(not info.converged))
     e_prev = energy(m, p, r, c2, D2, gamma, L)[0] if stop_on_energy else None
     if stop_on_energy:
         ri.energies.append(e_prev)
@@ -455,6 +457,7 @@ def run(m0, p0, r, S, c2, D2, gamma, dt, max_steps, eps_dm=0.0, stop_on_energy=F
         m_new = split_update(m, p, c2, D2, gamma, dt, L)
         p, info = pressure_pcg(m_new, r, S, p, rtol, max_iter, L)
         ri.total_cg_iters += info.iters
+        ri.unconverged_solves += int(not info.converged)
         dm = dm_rel(m_new, m, dt)
         m = m_new
         ri.steps += 1

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/nf.h"
 #include "nf_internal.h"
@@ -34,6 +35,16 @@ struct nf_grid {
   int last_iters = 0;
   std::string err;
   Geo geo;
+  // optional per-kernel timing of one PCG-loop kernel (events on the handle's stream)
+  struct TimedLaunch {
+    hipEvent_t a, b;
+    int it;
+  };
+  int timed = -1;
+  std::vector<TimedLaunch> pool;
+  size_t pool_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_count = 0;
 };
 
 namespace {
@@ -108,6 +119,42 @@ int compute_rhs(nf_grid* g, const double* S) {
 
 enum XSource { X_FROM_P = 0, X_FROM_XH = 1, X_ZERO = 2 };
 
+// Timing hooks: when the handle times kernel `which`, its launches in the PCG
+// loop are bracketed by an event pair; pairs of launches that ran after the
+// solver stopped (no-op launches) are discarded when the solve ends.
+int timed_begin(nf_grid* g, int which, int it) {
+  if (g->timed != which) return NF_OK;
+  if (g->pool_used == g->pool.size()) {
+    nf_grid::TimedLaunch t;
+    HIPCHK(g, hipEventCreate(&t.a));
+    HIPCHK(g, hipEventCreate(&t.b));
+    g->pool.push_back(t);
+  }
+  g->pool[g->pool_used].it = it;
+  HIPCHK(g, hipEventRecord(g->pool[g->pool_used].a, g->stream));
+  return NF_OK;
+}
+int timed_end(nf_grid* g, int which) {
+  if (g->timed != which) return NF_OK;
+  HIPCHK(g, hipEventRecord(g->pool[g->pool_used].b, g->stream));
+  g->pool_used++;
+  return NF_OK;
+}
+// called after the stream is synchronised; a launch of iteration `it` did work
+// iff it < limit
+int timed_collect(nf_grid* g, int limit) {
+  for (size_t i = 0; i < g->pool_used; ++i) {
+    if (g->pool[i].it < limit) {
+      float ms = 0.f;
+      HIPCHK(g, hipEventElapsedTime(&ms, g->pool[i].a, g->pool[i].b));
+      g->timed_ms += ms;
+      g->timed_count++;
+    }
+  }
+  g->pool_used = 0;
+  return NF_OK;
+}
+
 struct SolveOut {
   int iters = 0, converged = 0, flags = 0, sticky = 0;
   double rel_res = 0.0, true_rel_res = -1.0;
@@ -117,7 +164,7 @@ struct SolveOut {
 // partials <r,M^-1 r>, <r,r>, <b,b> in SLOT_P3INIT and Kbar in the status.
 int init_residual(nf_grid* g, const double* m, const double* r) {
   const Geo& G = g->geo;
-  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), g->stream));
+  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, g->stream));
   LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), g->stream));
   return NF_OK;
 }
@@ -137,6 +184,7 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
   }
   int rc = init_residual(g, m, r);
   if (rc) return rc;
+  g->pool_used = 0;
   const double tol2 = rtol * rtol;
   LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
 
@@ -151,9 +199,16 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
     first_chunk = false;
     if (n > max_iter - it) n = max_iter - it;
     for (int k = 0; k < n; ++k) {
-      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, s));
+      if ((rc = timed_begin(g, NF_KERNEL_ROW_FLUX, it))) return rc;
+      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, tol2, s));
+      if ((rc = timed_end(g, NF_KERNEL_ROW_FLUX))) return rc;
+      if ((rc = timed_begin(g, NF_KERNEL_COL_DIV, it))) return rc;
       LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s));
+      if ((rc = timed_end(g, NF_KERNEL_COL_DIV))) return rc;
+      // the update of iteration it+1 does work iff the solver had not stopped before it
+      if ((rc = timed_begin(g, NF_KERNEL_COL_UPDATE, it))) return rc;
       LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2, s));
+      if ((rc = timed_end(g, NF_KERNEL_COL_UPDATE))) return rc;
       ++it;
     }
     HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -168,11 +223,24 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
   DevStatus fin;
   rc = read_status(g, &fin);
   if (rc) return rc;
+  if (g->timed >= 0) {
+    // flux/div of iteration it work iff it < conv_at; the update launched with
+    // it+1 works iff it + 1 <= conv_at, i.e. it < conv_at as well
+    if ((rc = timed_collect(g, fin.conv_at))) return rc;
+  }
+  if (!fin.converged && fin.conv_at == max_iter && max_iter > 0 && !(fin.flags & (FLAG_NONFINITE | FLAG_INCOMPAT))) {
+    // stopped by max_iter: take the stopping test on the final residual here
+    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, col_nwg(G), 11, s));
+    rc = read_status(g, &fin);
+    if (rc) return rc;
+    fin.rr[0] = fin.out[11];
+    fin.converged = fin.out[11] <= tol2 * fin.bb ? 1 : 0;
+  }
   out->iters = fin.iters;
   out->converged = fin.converged;
   out->flags = fin.flags;
   out->sticky = fin.sticky;
-  const double rrf = fin.rr[fin.iters & 1];
+  const double rrf = fin.rr[0];
   out->rel_res = fin.bb > 0.0 ? std::sqrt(rrf > 0.0 ? rrf : 0.0) / std::sqrt(fin.bb) : 0.0;
   out->true_rel_res = -1.0;
   if (fin.iters > 0 || fin.converged) g->last_iters = fin.iters;
@@ -324,6 +392,22 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   return rc;
 }
 
+int nf_time_kernel(nf_grid* g, int which) {
+  if (!g || which < -1 || which > NF_KERNEL_COL_UPDATE) return NF_EINVAL;
+  g->timed = which;
+  g->pool_used = 0;
+  g->timed_ms = 0.0;
+  g->timed_count = 0;
+  return NF_OK;
+}
+
+int nf_time_kernel_read(nf_grid* g, double* total_ms, int64_t* count) {
+  if (!g || !total_ms || !count) return NF_EINVAL;
+  *total_ms = g->timed_ms;
+  *count = g->timed_count;
+  return NF_OK;
+}
+
 int nf_destroy_grid(nf_grid* g) {
   if (!g) return NF_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
@@ -334,6 +418,10 @@ int nf_destroy_grid(nf_grid* g) {
   if (g->hst) (void)hipHostFree(g->hst);
   for (int i = 0; i < 2; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+  for (auto& t : g->pool) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
   delete g;
   return NF_OK;
 }
@@ -370,7 +458,7 @@ int nf_apply_operator(nf_grid* g, const double* m, const double* r, const double
   LCHK(g, launch_status_reset(G, 1, s));
   LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
   LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
-  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, nullptr, s));
+  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, nullptr, 0.0, s));
   LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->xh, g->xh, g->bh, 0, 0, s));
   LCHK(g, launch_col_grad(G, g->qh, g->mix[0], nullptr, nullptr, s));
   LCHK(g, launch_row_c2r(G, g->mix[0], out, s));
@@ -498,6 +586,7 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
   ri.last_energy = NAN;
   ri.prev_energy = NAN;
   ri.total_cg_iters = 0;
+  ri.unconverged_solves = 0;
   const bool en = stop_on_energy_increase != 0;
   const bool need_sync = en || eps_dm > 0.0;
 
@@ -508,6 +597,11 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
   if (rc) return rc;
   ri.total_cg_iters += so.iters;
   rc = solve_status_code(g, so);
+  if (rc == NF_ENOTCONV) {
+    ri.unconverged_solves++;
+    rc = NF_OK;
+    g->err.clear();
+  }
   if (rc) {
     if (info) *info = ri;
     return rc;
@@ -547,6 +641,11 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
       return fail(g, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step");
     }
     rc = solve_status_code(g, so);
+    if (rc == NF_ENOTCONV) {
+      ri.unconverged_solves++;
+      rc = NF_OK;
+      g->err.clear();
+    }
     if (rc) {
       ri.stop_reason = NF_STOP_ERROR;
       if (info) *info = ri;

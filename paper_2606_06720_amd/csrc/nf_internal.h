@@ -12,8 +12,8 @@ namespace nf {
 struct DevStatus {
   double kbar[4];   // grid mean of K = m m^T + r I: Kxx, Kxy, Kyy, (unused)
   double bb;        // weighted ||b_hat||^2 of the projected right-hand side
-  double rho[2];    // <r, M^-1 r> by iteration parity
-  double rr[2];     // ||r||^2 by iteration parity
+  double rho[2];    // <r, M^-1 r> by iteration parity (expanded value used for beta)
+  double rr[2];     // rr[0]: ||r||^2 of the residual at which the solve stopped
   double rr0;       // initial ||r||^2
   double out[16];   // results of the final reductions (energy terms, dm, ...)
   int conv_at;      // iteration at which PCG stopped (converged or max_iter); INT_MAX while running
@@ -36,6 +36,7 @@ enum {
   SLOT_DM = 4,      // sum (m_new - m_old)^2, sum m_old^2
   SLOT_EPT = 5,     // sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
   SLOT_EGM = 6,     // sum w |xi|^2 |m_hat|^2 (both components)
+  SLOT_RR = 7,      // ||r||^2 of the residual written by the last PCG update
   NSLOTS = 8,
   SLOT_K = 8,
   MAX_WG = 4096,
@@ -67,7 +68,7 @@ int col_nwg(const Geo& g);
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out_mixed, double* schk_slot, hipStream_t s);
 hipError_t launch_row_c2r(const Geo& g, const void* in_mixed, double* f, hipStream_t s);
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
-                           double* kbar_slot, hipStream_t s);
+                           double* kbar_slot, double tol2, hipStream_t s);
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax_gamma1, hipStream_t s);
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dm_slot,

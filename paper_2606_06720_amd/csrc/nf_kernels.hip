@@ -204,13 +204,32 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo g, const cd* __restrict__ i
 // Operator middle: gradient fields (mixed) -> physical g -> flux K g -> mixed.
 // In place: G0/G1 hold grad_x/grad_y on entry and F_x/F_y on exit.
 // Optional partials: sum mx^2, mx my, my^2, r (the preconditioner's Kbar).
+// In the PCG loop (it >= 1) the pass first takes the stopping decision for the
+// residual r_it left by k_col_update: ||r_it||^2 (reduced directly from that
+// kernel's partials) <= tol2 ||b||^2 ends the solve at iteration it.
 template <int NX>
 __global__ void __launch_bounds__(256) k_row_flux(Geo g, cd* G0, cd* G1, const double* __restrict__ m,
-                                                  const double* __restrict__ r, int it, double* kslot) {
+                                                  const double* __restrict__ r, int it, double* kslot, int nwg_col,
+                                                  double tol2) {
   using C = RowCfg<NX>;
   if (it >= 0 && g.st->conv_at <= it) return;
   __shared__ cd buf[C::R * C::LS];
   __shared__ double red[4 * 4];
+  if (it >= 1) {
+    double rr[1];
+    sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
+    const double bb = g.st->bb;
+    const bool bad = !isfinite(rr[0]);
+    if (bad || rr[0] <= tol2 * bb) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.st->rr[0] = rr[0];
+        g.st->converged = bad ? 0 : 1;
+        if (bad) g.st->flags |= FLAG_NONFINITE;
+        g.st->conv_at = it;
+      }
+      return;
+    }
+  }
   const cd* tw = (const cd*)g.tw;
   const int y0 = blockIdx.x * C::R;
   const int nrow = min(C::R, g.ny - y0);
@@ -713,29 +732,29 @@ __global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd
     if (!zero_x && (conv || bad || max_iter <= 0)) return;
     stop = zero_x;
   } else {
-    // rho = <r,M^-1 r> and ||r||^2 of the residual the last operator pass read,
-    // computed directly from it (so the expansion below never compounds)
+    // rho = <r,M^-1 r> of the residual the last operator pass read, computed
+    // directly from it; the new rho (for beta only) follows from the
+    // expansion of <r - alpha q, M^-1 (r - alpha q)> around it.  The stopping
+    // test on the new residual is taken by the next pass from its direct norm.
     double s[7];
     sum_partials<C::NT, 7>(slot_ptr(g.part, SLOT_P3), nwg_col, MAX_WG, s, red);
-    const double rho = s[5], rr = s[6], bb = st->bb;
+    const double rho = s[5];
     alpha = rho / s[0];
     const double rhon = rho - 2.0 * alpha * s[1] + alpha * alpha * s[2];
-    const double rrn = rr - 2.0 * alpha * s[3] + alpha * alpha * s[4];
     beta = rhon / rho;
-    const bool bad = !isfinite(rrn) || !isfinite(alpha);
-    const bool conv = !bad && rrn <= tol2 * bb;
-    stop = conv || bad || it >= max_iter;
+    const bool bad = !isfinite(rhon) || !isfinite(alpha);
+    stop = bad || it >= max_iter;
     if (lead) {
       if (bad) st->flags |= FLAG_NONFINITE;
       st->rho[it & 1] = rhon;
-      st->rr[it & 1] = rrn;
       st->iters = it;
       if (stop) {
         st->conv_at = it;
-        st->converged = conv ? 1 : 0;
+        st->converged = 0;
       }
     }
   }
+  double rrp[1] = {0.0};
   cd dv[C::E];
 #pragma unroll
   for (int i = 0; i < C::E; ++i) {
@@ -758,6 +777,7 @@ __global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd
         xh[idx] = add(xh[idx], scl(d, alpha));
         rv = sub(rv, scl(q, alpha));
         rh[idx] = rv;
+        rrp[0] += (kx == 0 ? 1.0 : 2.0) * (rv.x * rv.x + rv.y * rv.y);
       }
       if (!stop) {
         const double xx = kx == 0 ? 0.0 : TWO_PI * kx / g.lx;
@@ -770,6 +790,10 @@ __global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd
     } else {
       dv[i] = mk<double>(0.0, 0.0);
     }
+  }
+  if (!first && !zero_x) {
+    block_sum<C::NT, 1>(rrp, red);
+    write_partials(slot_ptr(g.part, SLOT_RR), rrp, 1);
   }
   if (stop) return;
   for (int comp = 0; comp < 2; ++comp) {
@@ -946,9 +970,10 @@ hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s
   return hipGetLastError();
 }
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
-                           double* kslot, hipStream_t s) {
+                           double* kslot, double tol2, hipStream_t s) {
   const dim3 grid(row_nwg(g)), blk(256);
-#define L_(N) hipLaunchKernelGGL(k_row_flux<N>, grid, blk, 0, s, g, (cd*)G0, (cd*)G1, m, r, it, kslot)
+  const int nwg_col = col_nwg(g);
+#define L_(N) hipLaunchKernelGGL(k_row_flux<N>, grid, blk, 0, s, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();

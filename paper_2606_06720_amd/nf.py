@@ -31,6 +31,9 @@ NF_STOP_MAX_STEPS = 0
 NF_STOP_DM_BELOW_EPS = 1
 NF_STOP_ENERGY_INCREASE = 2
 NF_STOP_ERROR = 3
+NF_KERNEL_ROW_FLUX = 0
+NF_KERNEL_COL_DIV = 1
+NF_KERNEL_COL_UPDATE = 2
 
 _CODES = {
     NF_EINVAL: "NF_EINVAL",
@@ -64,7 +67,7 @@ class nf_step_info(ctypes.Structure):
 class nf_run_info(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("stop_reason", ctypes.c_int), ("last_dm", ctypes.c_double),
                 ("last_energy", ctypes.c_double), ("prev_energy", ctypes.c_double),
-                ("total_cg_iters", ctypes.c_int64)]
+                ("total_cg_iters", ctypes.c_int64), ("unconverged_solves", ctypes.c_int64)]
 
 
 def _load():
@@ -85,11 +88,14 @@ def _load():
     lib.nf_transform_forward.argtypes = [vp, vp, vp]
     lib.nf_transform_inverse.argtypes = [vp, vp, vp]
     lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
+    lib.nf_time_kernel.argtypes = [vp, ctypes.c_int]
+    lib.nf_time_kernel_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.nf_last_error.argtypes = [vp]
     lib.nf_last_error.restype = ctypes.c_char_p
     lib.nf_version.restype = ctypes.c_char_p
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
-              "nf_energy", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator"):
+              "nf_energy", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
+              "nf_time_kernel_read"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -123,6 +129,7 @@ class RunInfo:
     last_energy: float
     prev_energy: float
     total_cg_iters: int
+    unconverged_solves: int
 
 
 def _si(s):
@@ -231,7 +238,7 @@ class Grid:
                          ctypes.byref(info))
         self._check(rc)
         return RunInfo(int(info.steps), int(info.stop_reason), float(info.last_dm), float(info.last_energy),
-                       float(info.prev_energy), int(info.total_cg_iters))
+                       float(info.prev_energy), int(info.total_cg_iters), int(info.unconverged_solves))
 
     def energy(self, c2, D2, gamma, m, r, S, p=None):
         """nf_energy: (total, D^2/2|grad m|^2, relaxation, c^2/2|m.grad p|^2, c^2/2 r|grad p|^2)."""
@@ -245,6 +252,17 @@ class Grid:
 
 
     # diagnostics -----------------------------------------------------------
+    def time_kernel(self, which):
+        """nf_time_kernel: time launches of one PCG-loop kernel (-1 = off)."""
+        self._check(_lib.nf_time_kernel(self._h, int(which)))
+
+    def time_kernel_read(self):
+        """nf_time_kernel_read: (total ms, launches counted)."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(_lib.nf_time_kernel_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)
+
     @property
     def spec_shape(self):
         return (self.n[0] // 2, self.n[1], 2)

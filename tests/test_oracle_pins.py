@@ -437,8 +437,9 @@ def test_run_stopping_criteria():
     _, _, i2 = O.run(w["m0"], None, *args, max_steps=10, eps_dm=1e9)
     assert i2.steps == 1 and i2.stop_reason == O.STOP_DM_BELOW_EPS
     # a huge activation time step raises the energy: the run stops on it
-    _, _, i3 = O.run(w["m0"], None, w["r"], 10 * w["S"], 100.0, 1e-4, 0.75, 0.05,
+    _, _, i3 = O.run(w["m0"], None, w["r"], 6 * w["S"], 100.0, 1e-4, 0.75, 0.05,
                      max_steps=10, stop_on_energy=True)
+    assert i3.unconverged_solves == 0 and i3.steps == 1
     assert i3.stop_reason == O.STOP_ENERGY_INCREASE
     assert i3.energies[-1] >= i3.energies[-2]
 
