@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,7 @@ def main():
     ap.add_argument("--kernel", default="row_flux", choices=sorted(KERNEL_IDS))
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sequential", action="store_true", help="run the instances one after another on one stream")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     args = ap.parse_args()
 
@@ -130,12 +132,32 @@ def main():
         inst.append(dict(w=w, g=g, m0=T(w["m0"]), m=T(w["m0"]), p=torch.zeros((N, N), dtype=torch.float64, device=dev),
                          r=T(w["r"]), S=T(w["S"])))
 
+    # The instances are independent: each runs on its own HIP stream (default
+    # priority) from its own host thread, so that one instance's transform phase
+    # overlaps another's memory phase on the GPU.
+    for it in inst:
+        it["stream"] = torch.cuda.Stream(device=dev)
+
+    def run_one(it, steps, out, k):
+        w = it["w"]
+        with torch.cuda.stream(it["stream"]):
+            out[k] = it["g"].run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, it["m"], it["p"], it["r"], it["S"],
+                                 rtol=w["rtol"], max_iter=1000)
+
     def run_all(steps):
-        infos = []
-        for it in inst:
-            w = it["w"]
-            infos.append(it["g"].run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, it["m"], it["p"], it["r"], it["S"],
-                                     rtol=w["rtol"], max_iter=1000))
+        infos = [None] * len(inst)
+        if args.sequential:
+            for k, it in enumerate(inst):
+                run_one(it, steps, infos, k)
+        else:
+            th = [threading.Thread(target=run_one, args=(it, steps, infos, k)) for k, it in enumerate(inst)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        for k, i in enumerate(infos):
+            if i is None:
+                raise RuntimeError("instance %d failed" % k)
         return infos
 
     if args.warmup > 0:
@@ -145,6 +167,7 @@ def main():
         it["p"].zero_()
         it["g"].time_kernel(KERNEL_IDS[args.kernel])
     torch.cuda.synchronize()
+    # the per-instance state copies above ran on the default stream
 
     t0 = time.perf_counter()
     infos = run_all(args.steps)
@@ -195,6 +218,7 @@ def main():
         "config": {
             "workload": "2D periodic %dx%d FP64 dipole source/sink, smooth random r, gamma in %s, dt=5e-4, "
                         "PCG rtol 1e-10; one step = one time step of each gamma instance" % (N, N, list(GAMMAS)),
+            "concurrency": "sequential, one stream" if args.sequential else "one stream per instance",
             "grid": [N, N],
             "instances": len(GAMMAS),
             "grid_points_per_step": total_points,

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nf.h"
+#include "nf.h"
 #include "nf_internal.h"
 
 using namespace nf;
@@ -50,6 +50,9 @@ struct nf_grid {
 namespace {
 
 const char* kVersion = "nf-mi355x 0.1 (gfx950, fp64 2D)";
+
+// message of the last nf_create_grid failure on this thread (nf_last_error(NULL))
+thread_local std::string create_err;
 
 int fail(nf_grid* g, int code, const std::string& msg) {
   if (g) g->err = msg;
@@ -120,9 +123,11 @@ int compute_rhs(nf_grid* g, const double* S) {
 enum XSource { X_FROM_P = 0, X_FROM_XH = 1, X_ZERO = 2 };
 
 // Timing hooks: when the handle times kernel `which`, its launches in the PCG
-// loop are bracketed by an event pair; pairs of launches that ran after the
-// solver stopped (no-op launches) are discarded when the solve ends.
-int timed_begin(nf_grid* g, int which, int it) {
+// loop carry a start/stop event pair timestamped by the dispatch itself
+// (hipExtLaunchKernelGGL); pairs of launches that ran after the solver
+// stopped (no-op launches) are discarded when the solve ends.
+int timed_events(nf_grid* g, int which, int it, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
   if (g->timed != which) return NF_OK;
   if (g->pool_used == g->pool.size()) {
     nf_grid::TimedLaunch t;
@@ -131,12 +136,8 @@ int timed_begin(nf_grid* g, int which, int it) {
     g->pool.push_back(t);
   }
   g->pool[g->pool_used].it = it;
-  HIPCHK(g, hipEventRecord(g->pool[g->pool_used].a, g->stream));
-  return NF_OK;
-}
-int timed_end(nf_grid* g, int which) {
-  if (g->timed != which) return NF_OK;
-  HIPCHK(g, hipEventRecord(g->pool[g->pool_used].b, g->stream));
+  *e0 = g->pool[g->pool_used].a;
+  *e1 = g->pool[g->pool_used].b;
   g->pool_used++;
   return NF_OK;
 }
@@ -199,16 +200,15 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
     first_chunk = false;
     if (n > max_iter - it) n = max_iter - it;
     for (int k = 0; k < n; ++k) {
-      if ((rc = timed_begin(g, NF_KERNEL_ROW_FLUX, it))) return rc;
-      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, tol2, s));
-      if ((rc = timed_end(g, NF_KERNEL_ROW_FLUX))) return rc;
-      if ((rc = timed_begin(g, NF_KERNEL_COL_DIV, it))) return rc;
-      LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s));
-      if ((rc = timed_end(g, NF_KERNEL_COL_DIV))) return rc;
+      hipEvent_t e0, e1;
+      if ((rc = timed_events(g, NF_KERNEL_ROW_FLUX, it, &e0, &e1))) return rc;
+      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, tol2, s, e0, e1));
+      if ((rc = timed_events(g, NF_KERNEL_COL_DIV, it, &e0, &e1))) return rc;
+      LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s, e0, e1));
       // the update of iteration it+1 does work iff the solver had not stopped before it
-      if ((rc = timed_begin(g, NF_KERNEL_COL_UPDATE, it))) return rc;
-      LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2, s));
-      if ((rc = timed_end(g, NF_KERNEL_COL_UPDATE))) return rc;
+      if ((rc = timed_events(g, NF_KERNEL_COL_UPDATE, it, &e0, &e1))) return rc;
+      LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2, s,
+                                e0, e1));
       ++it;
     }
     HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -326,7 +326,7 @@ extern "C" {
 
 const char* nf_version(void) { return kVersion; }
 
-const char* nf_last_error(const nf_grid* g) { return g ? g->err.c_str() : "NULL handle"; }
+const char* nf_last_error(const nf_grid* g) { return g ? g->err.c_str() : create_err.c_str(); }
 
 int nf_set_stream(nf_grid* g, void* stream) {
   if (!g) return NF_EINVAL;
@@ -348,35 +348,39 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   g->ly = L[1];
   g->stream = (hipStream_t)stream;
   int rc = NF_OK;
-  auto bail = [&](int code) {
+  create_err.clear();
+  hipError_t herr = hipSuccess;
+  auto bail = [&](int code, const char* what) {
+    create_err = std::string(what) + (herr != hipSuccess ? std::string(": ") + hipGetErrorString(herr) : "");
     nf_destroy_grid(g);
     return code;
   };
-  if (hipGetDevice(&g->device) != hipSuccess) return bail(NF_EDEVICE);
+#define CREATE_CHK(expr, code)                          \
+  do {                                                  \
+    if ((herr = (expr)) != hipSuccess) return bail(code, #expr); \
+  } while (0)
+  CREATE_CHK(hipGetDevice(&g->device), NF_EDEVICE);
   const int twn = g->nx > g->ny ? g->nx : g->ny;
   g->twlog = ilog2i(twn);
   const size_t spec_bytes = (size_t)g->h * g->ny * 2 * sizeof(double);
   void** bufs[] = {&g->xh, &g->rh, &g->dh, &g->qh, &g->bh, &g->mix[0], &g->mix[1], &g->mix[2]};
-  for (void** b : bufs)
-    if (hipMalloc(b, spec_bytes) != hipSuccess) return bail(NF_ENOMEM);
-  if (hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)) != hipSuccess) return bail(NF_ENOMEM);
-  if (hipMalloc((void**)&g->part, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)) != hipSuccess)
-    return bail(NF_ENOMEM);
-  if (hipMalloc((void**)&g->st, sizeof(DevStatus)) != hipSuccess) return bail(NF_ENOMEM);
-  if (hipHostMalloc((void**)&g->hst, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
-    return bail(NF_ENOMEM);
-  for (int i = 0; i < 2; ++i)
-    if (hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming) != hipSuccess) return bail(NF_EDEVICE);
+  for (void** b : bufs) CREATE_CHK(hipMalloc(b, spec_bytes), NF_ENOMEM);
+  CREATE_CHK(hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)), NF_ENOMEM);
+  CREATE_CHK(hipMalloc((void**)&g->part, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_ENOMEM);
+  CREATE_CHK(hipMalloc((void**)&g->st, sizeof(DevStatus)), NF_ENOMEM);
+  CREATE_CHK(hipHostMalloc((void**)&g->hst, 2 * sizeof(DevStatus), hipHostMallocDefault), NF_ENOMEM);
+  for (int i = 0; i < 2; ++i) CREATE_CHK(hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming), NF_EDEVICE);
   {
     double* h = new double[2 * (size_t)twn];
     make_twiddles(twn, h);
-    hipError_t e = hipMemcpy(g->tw, h, (size_t)twn * 2 * sizeof(double), hipMemcpyHostToDevice);
+    herr = hipMemcpy(g->tw, h, (size_t)twn * 2 * sizeof(double), hipMemcpyHostToDevice);
     delete[] h;
-    if (e != hipSuccess) return bail(NF_EDEVICE);
+    if (herr != hipSuccess) return bail(NF_EDEVICE, "hipMemcpy(twiddles)");
   }
-  if (hipMemset(g->part, 0, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)) != hipSuccess) return bail(NF_EDEVICE);
-  if (hipMemset(g->st, 0, sizeof(DevStatus)) != hipSuccess) return bail(NF_EDEVICE);
-  if (hipMemset(g->xh, 0, spec_bytes) != hipSuccess) return bail(NF_EDEVICE);
+  CREATE_CHK(hipMemset(g->part, 0, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_EDEVICE);
+  CREATE_CHK(hipMemset(g->st, 0, sizeof(DevStatus)), NF_EDEVICE);
+  CREATE_CHK(hipMemset(g->xh, 0, spec_bytes), NF_EDEVICE);
+#undef CREATE_CHK
   Geo& G = g->geo;
   G.nx = g->nx;
   G.ny = g->ny;

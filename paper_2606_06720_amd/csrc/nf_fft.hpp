@@ -135,20 +135,27 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
   constexpr bool EXACT = (PER * NT == NBF);
   const int tid = threadIdx.x;
   cx<T> v[PER][R];
+  cx<T> w[PER][R];
+  // twiddle index shift: the table has TWN = 2^twlog entries, this stage needs
+  // angles in units of 2 pi / (NS R).  The table loads are issued before the
+  // barrier so that their latency overlaps the LDS traffic.
+  const int shift = twlog - ilog2(NS * R);
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int f = tid + b * NT;
     if (EXACT || f < NBF) {
       const int line = f / Q, j = f % Q;
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int q = 1; q < R; ++q) w[b][q] = twiddle<DIR>(tw, q * k, shift);
+      }
       const cx<T>* src = buf + line * LS + j;
 #pragma unroll
       for (int q = 0; q < R; ++q) v[b][q] = src[q * Q];
     }
   }
   __syncthreads();
-  // twiddle index shift: the table has TWN = 2^twlog entries, this stage needs
-  // angles in units of 2 pi / (NS R)
-  const int shift = twlog - ilog2(NS * R);
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int f = tid + b * NT;
@@ -157,7 +164,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
       const int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll
-        for (int q = 1; q < R; ++q) v[b][q] = mul(v[b][q], twiddle<DIR>(tw, q * k, shift));
+        for (int q = 1; q < R; ++q) v[b][q] = mul(v[b][q], w[b][q]);
       }
       dft<R, DIR>(v[b]);
       cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;

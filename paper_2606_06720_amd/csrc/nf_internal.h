@@ -67,8 +67,10 @@ int row_nwg(const Geo& g);
 int col_nwg(const Geo& g);
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out_mixed, double* schk_slot, hipStream_t s);
 hipError_t launch_row_c2r(const Geo& g, const void* in_mixed, double* f, hipStream_t s);
+// e0/e1: optional start/stop events timestamped by the dispatch (nullptr = none)
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
-                           double* kbar_slot, double tol2, hipStream_t s);
+                           double* kbar_slot, double tol2, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax_gamma1, hipStream_t s);
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dm_slot,
@@ -80,9 +82,11 @@ hipError_t launch_col_fwd(const Geo& g, void* in_mixed, void* out_spec, int with
                           hipStream_t s);
 hipError_t launch_col_grad(const Geo& g, const void* xh, void* P, void* Gx, void* Gy, hipStream_t s);
 hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy, void* qh, const void* dh,
-                          void* rh, const void* bh, int it, int nwg_row, hipStream_t s);
+                          void* rh, const void* bh, int it, int nwg_row, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
-                             void* Gy, int it, int max_iter, double tol2, hipStream_t s);
+                             void* Gy, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* egm_slot, hipStream_t s);
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* egm_slot, hipStream_t s);
 // reduce K arrays of n partials of a slot into st->out[o..o+K)

@@ -19,6 +19,8 @@
 // Spectral vectors hold the unnormalised DFT of the physical field.  Inner
 // products are sum_k w_k Re(a conj b) with w = 1 on the packed column and 2
 // elsewhere, which is n times the physical Euclidean product (Parseval).
+#include <hip/hip_ext.h>
+
 #include <climits>
 
 #include "nf_fft.hpp"
@@ -31,23 +33,39 @@ typedef cx<double> cd;
 static constexpr double TWO_PI = 6.283185307179586476925286766559;
 
 // ---------------------------------------------------------------- tile configs
-template <int NX>
+// A row pass works on R physical rows of NX points (R*H complex pairs per
+// field, H = NX/2) and transforms NF fields of the block together in one
+// batched LDS FFT of NF*R lines; a column pass works on C columns of NY
+// complex values, NF fields at once.
+// Elements of one field held by a workgroup.  At 1024^2 this gives 512
+// workgroups per pass, two per CU, so that one workgroup's transform overlaps
+// the other's memory phase.
+static constexpr int TILE = 1024;
+static constexpr int TPF = TILE / 8;  // threads per field: one radix-8 butterfly per stage
+
+template <int NX, int NF>
 struct RowCfg {
   static constexpr int H = NX / 2;
-  static constexpr int R0 = 2048 / H;
+  static constexpr int R0 = TILE / H;
   static constexpr int R = R0 < 1 ? 1 : (R0 > 64 ? 64 : R0);  // rows per workgroup
-  static constexpr int NT = 256;
-  static constexpr int LS = H + 1;                              // padded LDS line stride
-  static constexpr int E = (R * H + NT - 1) / NT;               // complex elements per thread
+  static constexpr int NT = TPF * NF;
+  static constexpr int LS = H + 2;                              // padded LDS line stride
+  static constexpr int RH = R * H;                              // pairs per field in the block
+  static constexpr int NB = NF * R;                             // LDS lines
+  static constexpr int ET = (NF * RH + NT - 1) / NT;            // transposed-image elements per thread
+  static constexpr int EP = (RH + NT - 1) / NT;                 // pointwise elements per thread
 };
 
-template <int NY>
+template <int NY, int NF>
 struct ColCfg {
-  static constexpr int C0 = 2048 / NY;
+  static constexpr int C0 = TILE / NY;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
-  static constexpr int NT = 256;
+  static constexpr int NT = TPF * NF;
   static constexpr int LS = NY;
-  static constexpr int E = (C * NY + NT - 1) / NT;
+  static constexpr int CN = C * NY;                             // elements per field in the block
+  static constexpr int NB = NF * C;                             // LDS lines
+  static constexpr int ET = (NF * CN + NT - 1) / NT;
+  static constexpr int EP = (CN + NT - 1) / NT;
 };
 
 // first-derivative wavenumber (Nyquist zeroed) and full wavenumber
@@ -60,58 +78,117 @@ __device__ __forceinline__ double xi_full(int k, int n, double L) {
   const int kk = (2 * k <= n) ? k : k - n;
   return TWO_PI * (double)kk / L;
 }
+// x wavenumber of packed column kx (zero on the packed kx = 0 / Nx/2 column)
+__device__ __forceinline__ double xi_col(int kx, double lx) { return kx == 0 ? 0.0 : TWO_PI * kx / lx; }
 
-// ---------------------------------------------------------------- row helpers
-// mixed [kx][y] (global) -> LDS lines [row][kx]
-template <int NX>
-__device__ __forceinline__ void row_load_mixed(cd* buf, const cd* __restrict__ src, int ny, int y0, int nrow) {
-  using C = RowCfg<NX>;
-  for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-    const int rr = e % C::R, kx = e / C::R;
-    if (rr < nrow) buf[rr * C::LS + kx] = src[(size_t)kx * ny + y0 + rr];
-  }
-}
-template <int NX>
-__device__ __forceinline__ void row_store_mixed(const cd* buf, cd* __restrict__ dst, int ny, int y0, int nrow) {
-  using C = RowCfg<NX>;
-  for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-    const int rr = e % C::R, kx = e / C::R;
-    if (rr < nrow) dst[(size_t)kx * ny + y0 + rr] = buf[rr * C::LS + kx];
-  }
-}
-// inverse x transform of the block in LDS (mixed -> physical pairs, times Nx)
-template <int NX>
-__device__ __forceinline__ void row_c2r(cd* buf, const cd* tw, int twlog) {
-  using C = RowCfg<NX>;
-  irfft_pre<double, C::H, C::R, C::LS, C::NT>(buf, tw, twlog);
-  lds_fft<double, +1, C::H, C::R, C::LS, C::NT>(buf, tw, twlog);
-}
-// forward x transform of the block in LDS (physical pairs -> mixed)
-template <int NX>
-__device__ __forceinline__ void row_r2c(cd* buf, const cd* tw, int twlog) {
-  using C = RowCfg<NX>;
-  lds_fft<double, -1, C::H, C::R, C::LS, C::NT>(buf, tw, twlog);
-  rfft_post<double, C::H, C::R, C::LS, C::NT>(buf, tw, twlog);
+// Workgroups are dealt round-robin over the 8 XCDs; map them so that
+// consecutive logical blocks (adjacent row blocks, which share cache lines of
+// the column-major mixed layout) run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
 }
 
-// ---------------------------------------------------------------- column helpers
-template <int NY>
-__device__ __forceinline__ void col_load(cd* buf, const cd* __restrict__ src, int kx0, int h) {
-  using C = ColCfg<NY>;
-  for (int e = threadIdx.x; e < C::C * NY; e += C::NT) {
-    const int c = e / NY, ky = e % NY;
-    if (kx0 + c < h) buf[c * C::LS + ky] = src[(size_t)(kx0 + c) * NY + ky];
+__device__ __forceinline__ const cd* pick(int f, const cd* a, const cd* b, const cd* c) {
+  return f == 0 ? a : (f == 1 ? b : c);
+}
+__device__ __forceinline__ cd* pickw(int f, cd* a, cd* b, cd* c) { return f == 0 ? a : (f == 1 ? b : c); }
+
+// ---------------------------------------------------------------- row images
+// "T" image: element e -> field e / RH, row (e % RH) % R, column (e % RH) / R;
+// coalesced over the column-major mixed layout M[kx][y].  LDS line of (field,
+// row) is field * R + row.
+template <int NX, int NF>
+__device__ __forceinline__ void rowT_gload(cd (&v)[(RowCfg<NX, NF>::ET)], const cd* s0, const cd* s1, const cd* s2,
+                                           int ny, int y0, int nrow) {
+  using C = RowCfg<NX, NF>;
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::RH, ee = e % C::RH;
+    const int rr = ee % C::R, kx = ee / C::R;
+    v[i] = (e < NF * C::RH && rr < nrow) ? pick(f, s0, s1, s2)[(size_t)kx * ny + y0 + rr] : mk<double>(0.0, 0.0);
   }
 }
-template <int NY>
-__device__ __forceinline__ void col_store(const cd* buf, cd* __restrict__ dst, int kx0, int h) {
-  using C = ColCfg<NY>;
-  for (int e = threadIdx.x; e < C::C * NY; e += C::NT) {
-    const int c = e / NY, ky = e % NY;
-    if (kx0 + c < h) dst[(size_t)(kx0 + c) * NY + ky] = buf[c * C::LS + ky];
+template <int NX, int NF>
+__device__ __forceinline__ void rowT_put(cd* buf, const cd (&v)[(RowCfg<NX, NF>::ET)]) {
+  using C = RowCfg<NX, NF>;
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::RH, ee = e % C::RH;
+    if (e < NF * C::RH) buf[(f * C::R + ee % C::R) * C::LS + ee / C::R] = v[i];
+  }
+}
+// store the first NFS fields of the block back to the mixed layout
+template <int NX, int NF, int NFS>
+__device__ __forceinline__ void rowT_store(const cd* buf, cd* d0, cd* d1, cd* d2, int ny, int y0, int nrow) {
+  using C = RowCfg<NX, NF>;
+  for (int e = threadIdx.x; e < NFS * C::RH; e += C::NT) {
+    const int f = e / C::RH, ee = e % C::RH;
+    const int rr = ee % C::R, kx = ee / C::R;
+    if (rr < nrow) pickw(f, d0, d1, d2)[(size_t)kx * ny + y0 + rr] = buf[(f * C::R + rr) * C::LS + kx];
+  }
+}
+// "P" image of a physical field: element p -> row p / H, pair p % H (the
+// grid points 2j, 2j+1 of the row), coalesced over the row-major layout
+template <int NX, int NF>
+__device__ __forceinline__ void rowP_gload(double2 (&v)[(RowCfg<NX, NF>::EP)], const double* __restrict__ f, int y0,
+                                           int nrow) {
+  using C = RowCfg<NX, NF>;
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    v[i] = (p < C::RH && rr < nrow) ? *(const double2*)(f + (size_t)(y0 + rr) * NX + 2 * j) : make_double2(0.0, 0.0);
   }
 }
 
+// ---------------------------------------------------------------- column images
+template <int NY, int NF, int NFL>
+__device__ __forceinline__ void colT_gload(cd (&v)[(ColCfg<NY, NF>::ET)], const cd* s0, const cd* s1, int kx0, int h) {
+  using C = ColCfg<NY, NF>;
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::CN, ee = e % C::CN;
+    const int c = ee / NY, ky = ee % NY;
+    v[i] = (e < NFL * C::CN && kx0 + c < h) ? (f == 0 ? s0 : s1)[(size_t)(kx0 + c) * NY + ky] : mk<double>(0.0, 0.0);
+  }
+}
+template <int NY, int NF, int NFL>
+__device__ __forceinline__ void colT_put(cd* buf, const cd (&v)[(ColCfg<NY, NF>::ET)]) {
+  using C = ColCfg<NY, NF>;
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::CN, ee = e % C::CN;
+    if (e < NFL * C::CN) buf[(f * C::C + ee / NY) * C::LS + ee % NY] = v[i];
+  }
+}
+template <int NY, int NF, int NFS>
+__device__ __forceinline__ void colT_store(const cd* buf, cd* d0, cd* d1, int kx0, int h) {
+  using C = ColCfg<NY, NF>;
+  for (int e = threadIdx.x; e < NFS * C::CN; e += C::NT) {
+    const int f = e / C::CN, ee = e % C::CN;
+    const int c = ee / NY, ky = ee % NY;
+    if (kx0 + c < h) (f == 0 ? d0 : d1)[(size_t)(kx0 + c) * NY + ky] = buf[(f * C::C + c) * C::LS + ky];
+  }
+}
+// pointwise image of one field: p -> column p / NY, row p % NY
+template <int NY, int NF>
+__device__ __forceinline__ void colP_gload(cd (&v)[(ColCfg<NY, NF>::EP)], const cd* __restrict__ src, int kx0, int h) {
+  using C = ColCfg<NY, NF>;
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
+    v[i] = (p < C::CN && kx0 + c < h) ? src[(size_t)(kx0 + c) * NY + ky] : mk<double>(0.0, 0.0);
+  }
+}
+
+template <int NT>
 __device__ __forceinline__ void write_partials(double* slot, const double* v, int K) {
   if (threadIdx.x == 0) {
     for (int k = 0; k < K; ++k) slot[(size_t)k * MAX_WG + blockIdx.x] = v[k];
@@ -154,46 +231,52 @@ __global__ void __launch_bounds__(256) k_sum_slot(const double* __restrict__ slo
 // ================================================================ row kernels
 // physical -> mixed; optional partials sum f, sum |f| (compatibility of S)
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
+__global__ void __launch_bounds__(TPF) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
                                                  double* schk) {
-  using C = RowCfg<NX>;
-  __shared__ cd buf[C::R * C::LS];
-  __shared__ double red[2 * 4];
+  using C = RowCfg<NX, 1>;
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[2 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
+  const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
+  double2 v[C::EP];
+  rowP_gload<NX, 1>(v, f, y0, nrow);
   double s[2] = {0.0, 0.0};
-  for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-    const int rr = e / C::H, j = e % C::H;
-    if (rr < nrow) {
-      const double2 v = *(const double2*)(f + (size_t)(y0 + rr) * NX + 2 * j);
-      buf[rr * C::LS + j] = mk<double>(v.x, v.y);
-      s[0] += v.x + v.y;
-      s[1] += fabs(v.x) + fabs(v.y);
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    if (p < C::RH) {
+      buf[(p / C::H) * C::LS + p % C::H] = mk<double>(v[i].x, v[i].y);
+      s[0] += v[i].x + v[i].y;
+      s[1] += fabs(v[i].x) + fabs(v[i].y);
     }
   }
   __syncthreads();
-  row_r2c<NX>(buf, tw, g.twlog);
-  row_store_mixed<NX>(buf, out, g.ny, y0, nrow);
+  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, g.ny, y0, nrow);
   if (schk) {
     block_sum<C::NT, 2>(s, red);
-    write_partials(schk, s, 2);
+    write_partials<C::NT>(schk, s, 2);
   }
 }
 
-// mixed -> physical (times 1: the caller folds 1/n into the spectral side)
+// mixed -> physical (unnormalised inverse: the caller folds 1/n into the spectral side)
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
-  using C = RowCfg<NX>;
-  __shared__ cd buf[C::R * C::LS];
+__global__ void __launch_bounds__(TPF) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
+  using C = RowCfg<NX, 1>;
+  __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
+  const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
-  row_load_mixed<NX>(buf, in, g.ny, y0, nrow);
+  cd tv[C::ET];
+  rowT_gload<NX, 1>(tv, in, nullptr, nullptr, g.ny, y0, nrow);
+  rowT_put<NX, 1>(buf, tv);
   __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-  for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-    const int rr = e / C::H, j = e % C::H;
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  for (int p = threadIdx.x; p < C::RH; p += C::NT) {
+    const int rr = p / C::H, j = p % C::H;
     if (rr < nrow) {
       const cd v = buf[rr * C::LS + j];
       *(double2*)(f + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(v.x, v.y);
@@ -201,20 +284,31 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo g, const cd* __restrict__ i
   }
 }
 
-// Operator middle: gradient fields (mixed) -> physical g -> flux K g -> mixed.
-// In place: G0/G1 hold grad_x/grad_y on entry and F_x/F_y on exit.
-// Optional partials: sum mx^2, mx my, my^2, r (the preconditioner's Kbar).
+// Operator middle: gradient fields (mixed) -> physical g -> flux K g -> mixed,
+// both components in one batched transform each way.  In place: G0/G1 hold
+// grad_x/grad_y on entry and F_x/F_y on exit.  Optional partials: sum mx^2,
+// mx my, my^2, r (the preconditioner's Kbar).
 // In the PCG loop (it >= 1) the pass first takes the stopping decision for the
 // residual r_it left by k_col_update: ||r_it||^2 (reduced directly from that
 // kernel's partials) <= tol2 ||b||^2 ends the solve at iteration it.
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_flux(Geo g, cd* G0, cd* G1, const double* __restrict__ m,
+__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cd* G0, cd* G1, const double* __restrict__ m,
                                                   const double* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2) {
-  using C = RowCfg<NX>;
+  using C = RowCfg<NX, 2>;
   if (it >= 0 && g.st->conv_at <= it) return;
-  __shared__ cd buf[C::R * C::LS];
-  __shared__ double red[4 * 4];
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[4 * (C::NT / 64)];
+  const cd* tw = (const cd*)g.tw;
+  const int y0 = xcd_block() * C::R;
+  const int nrow = min(C::R, g.ny - y0);
+  const size_t n = (size_t)g.nx * g.ny;
+  cd tv[C::ET];
+  rowT_gload<NX, 2>(tv, G0, G1, nullptr, g.ny, y0, nrow);
+  double2 mx[C::EP], my[C::EP], rv[C::EP];
+  rowP_gload<NX, 2>(mx, m, y0, nrow);
+  rowP_gload<NX, 2>(my, m + n, y0, nrow);
+  rowP_gload<NX, 2>(rv, r, y0, nrow);
   if (it >= 1) {
     double rr[1];
     sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
@@ -230,77 +324,39 @@ __global__ void __launch_bounds__(256) k_row_flux(Geo g, cd* G0, cd* G1, const d
       return;
     }
   }
-  const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
-  const int nrow = min(C::R, g.ny - y0);
-  const size_t n = (size_t)g.nx * g.ny;
-  cd gx[C::E], gy[C::E];
-
-  row_load_mixed<NX>(buf, G0, g.ny, y0, nrow);
+  rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gx[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
-  __syncthreads();
-  row_load_mixed<NX>(buf, G1, g.ny, y0, nrow);
-  __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gy[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
-  __syncthreads();
-
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double ks[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int rr = e / C::H, j = e % C::H;
-    if (e < C::R * C::H && rr < nrow) {
-      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
-      const double2 mx = *(const double2*)(m + idx);
-      const double2 my = *(const double2*)(m + n + idx);
-      const double2 rv = *(const double2*)(r + idx);
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      cd* px = buf + rr * C::LS + j;
+      cd* py = buf + (C::R + rr) * C::LS + j;
+      const cd gx = *px, gy = *py;
       // K g = (m.g) m + r g at the two grid points packed in this element
-      const double a0 = mx.x * gx[i].x + my.x * gy[i].x;
-      const double a1 = mx.y * gx[i].y + my.y * gy[i].y;
-      const cd fx = mk<double>(fma(a0, mx.x, rv.x * gx[i].x), fma(a1, mx.y, rv.y * gx[i].y));
-      const cd fy = mk<double>(fma(a0, my.x, rv.x * gy[i].x), fma(a1, my.y, rv.y * gy[i].y));
-      gx[i] = fx;
-      gy[i] = fy;
+      const double a0 = mx[i].x * gx.x + my[i].x * gy.x;
+      const double a1 = mx[i].y * gx.y + my[i].y * gy.y;
+      *px = mk<double>(fma(a0, mx[i].x, rv[i].x * gx.x), fma(a1, mx[i].y, rv[i].y * gx.y));
+      *py = mk<double>(fma(a0, my[i].x, rv[i].x * gy.x), fma(a1, my[i].y, rv[i].y * gy.y));
       if (kslot) {
-        ks[0] += mx.x * mx.x + mx.y * mx.y;
-        ks[1] += mx.x * my.x + mx.y * my.y;
-        ks[2] += my.x * my.x + my.y * my.y;
-        ks[3] += rv.x + rv.y;
+        ks[0] += mx[i].x * mx[i].x + mx[i].y * mx[i].y;
+        ks[1] += mx[i].x * my[i].x + mx[i].y * my[i].y;
+        ks[2] += my[i].x * my[i].x + my[i].y * my[i].y;
+        ks[3] += rv[i].x + rv[i].y;
       }
     }
   }
-  // forward x transform of F_x, then F_y
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) buf[(e / C::H) * C::LS + e % C::H] = gx[i];
-  }
   __syncthreads();
-  row_r2c<NX>(buf, tw, g.twlog);
-  row_store_mixed<NX>(buf, G0, g.ny, y0, nrow);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) buf[(e / C::H) * C::LS + e % C::H] = gy[i];
-  }
-  __syncthreads();
-  row_r2c<NX>(buf, tw, g.twlog);
-  row_store_mixed<NX>(buf, G1, g.ny, y0, nrow);
+  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  rowT_store<NX, 2, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
-    write_partials(kslot, ks, 4);
+    write_partials<C::NT>(kslot, ks, 4);
   }
 }
 
@@ -308,60 +364,39 @@ __global__ void __launch_bounds__(256) k_row_flux(Geo g, cd* G0, cd* G1, const d
 // exact activation then exact relaxation of m, forward x transform of the
 // result.  In place: P, Gx hold the transformed m_x, m_y on exit.
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
+__global__ void __launch_bounds__(3 * TPF) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
-  using C = RowCfg<NX>;
-  __shared__ cd buf[C::R * C::LS];
+  using C = RowCfg<NX, 3>;
+  __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
+  const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
-  cd gx[C::E], gy[C::E];
-
-  // pressure: write p to the caller's buffer
-  row_load_mixed<NX>(buf, P, g.ny, y0, nrow);
+  cd tv[C::ET];
+  rowT_gload<NX, 3>(tv, P, Gx, Gy, g.ny, y0, nrow);
+  double2 mxv[C::EP], myv[C::EP];
+  rowP_gload<NX, 3>(mxv, m, y0, nrow);
+  rowP_gload<NX, 3>(myv, m + n, y0, nrow);
+  rowT_put<NX, 3>(buf, tv);
   __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-  for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-    const int rr = e / C::H, j = e % C::H;
-    if (rr < nrow) {
-      const cd v = buf[rr * C::LS + j];
-      *(double2*)(p_out + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(v.x, v.y);
-    }
-  }
-  __syncthreads();
-  row_load_mixed<NX>(buf, Gx, g.ny, y0, nrow);
-  __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gx[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
-  __syncthreads();
-  row_load_mixed<NX>(buf, Gy, g.ny, y0, nrow);
-  __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gy[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
-  __syncthreads();
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
 
   const double e1 = 1.0 - gamma;
   bool bad = false;
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int rr = e / C::H, j = e % C::H;
-    if (e < C::R * C::H && rr < nrow) {
-      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
-      const double2 mxv = *(const double2*)(m + idx);
-      const double2 myv = *(const double2*)(m + n + idx);
-      double mx[2] = {mxv.x, mxv.y}, my[2] = {myv.x, myv.y};
-      const double gxa[2] = {gx[i].x, gx[i].y}, gya[2] = {gy[i].x, gy[i].y};
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      cd* pp = buf + rr * C::LS + j;
+      cd* px = buf + (C::R + rr) * C::LS + j;
+      const cd pv = *pp;
+      const cd gxv = *px, gyv = buf[(2 * C::R + rr) * C::LS + j];
+      *(double2*)(p_out + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(pv.x, pv.y);
+      double mx[2] = {mxv[i].x, mxv[i].y}, my[2] = {myv[i].x, myv[i].y};
+      const double gxa[2] = {gxv.x, gxv.y}, gya[2] = {gyv.x, gyv.y};
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         // activation: m + c^2 dt phi1(c^2 dt |g|^2) (g.m) g, phi1(z) = expm1(z)/z
@@ -369,14 +404,14 @@ __global__ void __launch_bounds__(256) k_row_split(Geo g, cd* P, cd* Gx, const c
         const double z = c2dt * g2;
         const double phi = z > 0.0 ? expm1(z) / z : 1.0;
         const double coef = c2dt * phi * (gxa[t] * mx[t] + gya[t] * my[t]);
-        double ax = fma(coef, gxa[t], mx[t]);
-        double ay = fma(coef, gya[t], my[t]);
+        double qx = fma(coef, gxa[t], mx[t]);
+        double qy = fma(coef, gya[t], my[t]);
         // relaxation: exact decay of |m| along m/|m|
         double fac;
         if (gamma == 1.0) {
           fac = relax1;
         } else {
-          const double s2 = ax * ax + ay * ay;
+          const double s2 = qx * qx + qy * qy;
           if (s2 == 0.0) {
             fac = 1.0;
           } else {
@@ -384,115 +419,97 @@ __global__ void __launch_bounds__(256) k_row_split(Geo g, cd* P, cd* Gx, const c
             fac = (u >= 1.0) ? 0.0 : exp(log1p(-u) / (2.0 * e1));
           }
         }
-        ax *= fac;
-        ay *= fac;
-        if (!isfinite(ax) || !isfinite(ay)) bad = true;
-        mx[t] = ax;
-        my[t] = ay;
+        qx *= fac;
+        qy *= fac;
+        if (!isfinite(qx) || !isfinite(qy)) bad = true;
+        mx[t] = qx;
+        my[t] = qy;
       }
-      gx[i] = mk<double>(mx[0], mx[1]);
-      gy[i] = mk<double>(my[0], my[1]);
+      *pp = mk<double>(mx[0], mx[1]);
+      *px = mk<double>(my[0], my[1]);
     }
   }
   if (bad) atomicOr(&g.st->sticky, (int)FLAG_NONFINITE);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) buf[(e / C::H) * C::LS + e % C::H] = gx[i];
-  }
   __syncthreads();
-  row_r2c<NX>(buf, tw, g.twlog);
-  row_store_mixed<NX>(buf, P, g.ny, y0, nrow);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) buf[(e / C::H) * C::LS + e % C::H] = gy[i];
-  }
-  __syncthreads();
-  row_r2c<NX>(buf, tw, g.twlog);
-  row_store_mixed<NX>(buf, Gx, g.ny, y0, nrow);
+  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  rowT_store<NX, 3, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
 }
 
 // Last pass of the step: inverse x transform of the diffused m, written over
 // m; partials sum (m_new - m_old)^2 and sum m_old^2.
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+__global__ void __launch_bounds__(2 * TPF) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                    double* m, double* dslot) {
-  using C = RowCfg<NX>;
-  __shared__ cd buf[C::R * C::LS];
-  __shared__ double red[2 * 4];
+  using C = RowCfg<NX, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[2 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
+  const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
+  cd tv[C::ET];
+  rowT_gload<NX, 2>(tv, Mx, My, nullptr, g.ny, y0, nrow);
+  double2 o0[C::EP], o1[C::EP];
+  rowP_gload<NX, 2>(o0, m, y0, nrow);
+  rowP_gload<NX, 2>(o1, m + n, y0, nrow);
+  rowT_put<NX, 2>(buf, tv);
+  __syncthreads();
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[2] = {0.0, 0.0};
-  for (int comp = 0; comp < 2; ++comp) {
-    row_load_mixed<NX>(buf, comp == 0 ? Mx : My, g.ny, y0, nrow);
-    __syncthreads();
-    row_c2r<NX>(buf, tw, g.twlog);
-    for (int e = threadIdx.x; e < C::R * C::H; e += C::NT) {
-      const int rr = e / C::H, j = e % C::H;
-      if (rr < nrow) {
-        const cd v = buf[rr * C::LS + j];
-        double* dst = m + comp * n + (size_t)(y0 + rr) * NX + 2 * j;
-        const double2 old = *(const double2*)dst;
-        const double d0 = v.x - old.x, d1 = v.y - old.y;
-        s[0] += d0 * d0 + d1 * d1;
-        s[1] += old.x * old.x + old.y * old.y;
-        *(double2*)dst = make_double2(v.x, v.y);
-      }
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      const cd a0 = buf[rr * C::LS + j], a1 = buf[(C::R + rr) * C::LS + j];
+      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
+      const double d0 = a0.x - o0[i].x, d1 = a0.y - o0[i].y;
+      const double d2 = a1.x - o1[i].x, d3 = a1.y - o1[i].y;
+      s[0] += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+      s[1] += o0[i].x * o0[i].x + o0[i].y * o0[i].y + o1[i].x * o1[i].x + o1[i].y * o1[i].y;
+      *(double2*)(m + idx) = make_double2(a0.x, a0.y);
+      *(double2*)(m + n + idx) = make_double2(a1.x, a1.y);
     }
-    __syncthreads();
   }
   if (dslot) {
     block_sum<C::NT, 2>(s, red);
-    write_partials(dslot, s, 2);
+    write_partials<C::NT>(dslot, s, 2);
   }
 }
 
 // Pointwise energy terms: sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
 template <int NX>
-__global__ void __launch_bounds__(256) k_row_energy(Geo g, const cd* __restrict__ Gx, const cd* __restrict__ Gy,
+__global__ void __launch_bounds__(2 * TPF) k_row_energy(Geo g, const cd* __restrict__ Gx, const cd* __restrict__ Gy,
                                                     const double* __restrict__ m, const double* __restrict__ r,
                                                     double gamma, double* eslot) {
-  using C = RowCfg<NX>;
-  __shared__ cd buf[C::R * C::LS];
-  __shared__ double red[3 * 4];
+  using C = RowCfg<NX, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[3 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
-  const int y0 = blockIdx.x * C::R;
+  const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
-  cd gx[C::E], gy[C::E];
-  row_load_mixed<NX>(buf, Gx, g.ny, y0, nrow);
+  cd tv[C::ET];
+  rowT_gload<NX, 2>(tv, Gx, Gy, nullptr, g.ny, y0, nrow);
+  double2 mx[C::EP], my[C::EP], rv[C::EP];
+  rowP_gload<NX, 2>(mx, m, y0, nrow);
+  rowP_gload<NX, 2>(my, m + n, y0, nrow);
+  rowP_gload<NX, 2>(rv, r, y0, nrow);
+  rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gx[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
-  __syncthreads();
-  row_load_mixed<NX>(buf, Gy, g.ny, y0, nrow);
-  __syncthreads();
-  row_c2r<NX>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    if (e < C::R * C::H) gy[i] = buf[(e / C::H) * C::LS + e % C::H];
-  }
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int rr = e / C::H, j = e % C::H;
-    if (e < C::R * C::H && rr < nrow) {
-      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
-      const double2 mx = *(const double2*)(m + idx);
-      const double2 my = *(const double2*)(m + n + idx);
-      const double2 rv = *(const double2*)(r + idx);
-      const double gxa[2] = {gx[i].x, gx[i].y}, gya[2] = {gy[i].x, gy[i].y};
-      const double mxa[2] = {mx.x, mx.y}, mya[2] = {my.x, my.y}, ra[2] = {rv.x, rv.y};
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      const cd gxv = buf[rr * C::LS + j], gyv = buf[(C::R + rr) * C::LS + j];
+      const double gxa[2] = {gxv.x, gxv.y}, gya[2] = {gyv.x, gyv.y};
+      const double mxa[2] = {mx[i].x, mx[i].y}, mya[2] = {my[i].x, my[i].y}, ra[2] = {rv[i].x, rv[i].y};
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const double mg = mxa[t] * gxa[t] + mya[t] * gya[t];
@@ -504,92 +521,79 @@ __global__ void __launch_bounds__(256) k_row_energy(Geo g, const cd* __restrict_
     }
   }
   block_sum<C::NT, 3>(s, red);
-  write_partials(eslot, s, 3);
+  write_partials<C::NT>(eslot, s, 3);
 }
 
 // ================================================================ column kernels
+// Write the gradient multipliers i xi_c f_hat / n of one spectral value into
+// the two gradient lines of the column block.
+template <int NY, int NF>
+__device__ __forceinline__ void put_grad(cd* buf, int c, int ky, int kx, const cd v, const Geo& g) {
+  using C = ColCfg<NY, NF>;
+  const double sx = xi_col(kx, g.lx) * g.inv_n, sy = xi_tilde(ky, NY, g.ly) * g.inv_n;
+  buf[c * C::LS + ky] = mk<double>(-sx * v.y, sx * v.x);
+  buf[(C::C + c) * C::LS + ky] = mk<double>(-sy * v.y, sy * v.x);
+}
+
 // mixed -> spectral (null modes zeroed unless bit 1 of mode is set); with bit 0
 // of mode also the gradient of the result back to mixed:
 // Gx = F_y^-1(i xi_x f_hat / n), Gy likewise.
 template <int NY>
-__global__ void __launch_bounds__(256) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int with_grad, cd* Gx,
-                                                 cd* Gy) {
-  using C = ColCfg<NY>;
-  __shared__ cd buf[C::C * C::LS];
+__global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
+  using C = ColCfg<NY, 2>;
+  __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
-  col_load<NY>(buf, in, kx0, g.h);
+  cd tv[C::ET];
+  colT_gload<NY, 2, 1>(tv, in, nullptr, kx0, g.h);
+  colT_put<NY, 2, 1>(buf, tv);
   __syncthreads();
   lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-  cd v[C::E];
+  cd v[C::EP];
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int c = e / NY, ky = e % NY;
-    cd a = buf[c * C::LS + ky];
-    if (!(with_grad & 2) && kx0 + c == 0 && (ky == 0 || 2 * ky == NY)) a = mk<double>(0.0, 0.0);
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
+    cd a = p < C::CN ? buf[c * C::LS + ky] : mk<double>(0.0, 0.0);
+    if (!(mode & 2) && kx0 + c == 0 && (ky == 0 || 2 * ky == NY)) a = mk<double>(0.0, 0.0);
     v[i] = a;
+    if (p < C::CN && kx0 + c < g.h) out[(size_t)(kx0 + c) * NY + ky] = a;
   }
+  if (!(mode & 1)) return;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    buf[(e / NY) * C::LS + e % NY] = v[i];
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    if (p < C::CN) put_grad<NY, 2>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
   }
   __syncthreads();
-  col_store<NY>(buf, out, kx0, g.h);
-  if (!(with_grad & 1)) return;
-  __syncthreads();
-  for (int comp = 0; comp < 2; ++comp) {
-#pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      const int c = e / NY, ky = e % NY;
-      const int kx = kx0 + c;
-      const double xi = comp == 0 ? (kx == 0 ? 0.0 : TWO_PI * kx / g.lx) : xi_tilde(ky, NY, g.ly);
-      const double s = xi * g.inv_n;
-      buf[c * C::LS + ky] = mk<double>(-s * v[i].y, s * v[i].x);
-    }
-    __syncthreads();
-    lds_fft<double, +1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-    col_store<NY>(buf, comp == 0 ? Gx : Gy, kx0, g.h);
-    __syncthreads();
-  }
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 
-// spectral -> mixed: optional P = F_y^-1(x_hat / n), Gx, Gy as in k_col_fwd
-template <int NY>
-__global__ void __launch_bounds__(256) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx, cd* Gy) {
-  using C = ColCfg<NY>;
-  __shared__ cd buf[C::C * C::LS];
+// spectral -> mixed: P = F_y^-1(x_hat / n)  (GRAD false)  or
+//                    Gx, Gy as in k_col_fwd (GRAD true)
+template <int NY, bool GRAD>
+__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
+                                                               cd* Gy) {
+  using C = ColCfg<NY, GRAD ? 2 : 1>;
+  __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
-  cd v[C::E];
+  cd v[C::EP];
+  colP_gload<NY, GRAD ? 2 : 1>(v, xh, kx0, g.h);
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int c = e / NY, ky = e % NY;
-    v[i] = (kx0 + c < g.h) ? xh[(size_t)(kx0 + c) * NY + ky] : mk<double>(0.0, 0.0);
-  }
-  for (int comp = (P ? -1 : 0); comp < (Gx ? 2 : 0); ++comp) {
-#pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      const int c = e / NY, ky = e % NY;
-      const int kx = kx0 + c;
-      if (comp < 0) {
-        buf[c * C::LS + ky] = scl(v[i], g.inv_n);
-      } else {
-        const double xi = comp == 0 ? (kx == 0 ? 0.0 : TWO_PI * kx / g.lx) : xi_tilde(ky, NY, g.ly);
-        const double s = xi * g.inv_n;
-        buf[c * C::LS + ky] = mk<double>(-s * v[i].y, s * v[i].x);
-      }
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    if (p < C::CN) {
+      if (GRAD) put_grad<NY, 2>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
+      else buf[(p / NY) * C::LS + p % NY] = scl(v[i], g.inv_n);
     }
-    __syncthreads();
-    lds_fft<double, +1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-    col_store<NY>(buf, comp < 0 ? P : (comp == 0 ? Gx : Gy), kx0, g.h);
-    __syncthreads();
   }
+  __syncthreads();
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  if (GRAD) colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  else colT_store<NY, 1, 1>(buf, P, nullptr, kx0, g.h);
 }
 
 __device__ __forceinline__ double precond_symbol_inv(const double* K, double xx, double yy) {
@@ -603,16 +607,24 @@ __device__ __forceinline__ double precond_symbol_inv(const double* K, double xx,
 // else: q_hat stored, partials <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>,
 //       <r,M^-1 r>, <r,r>.
 template <int NY, bool INIT>
-__global__ void __launch_bounds__(256) k_col_div(Geo g, const cd* __restrict__ Fx, const cd* __restrict__ Fy,
+__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cd* __restrict__ Fx, const cd* __restrict__ Fy,
                                                  cd* __restrict__ qh, const cd* __restrict__ dh, cd* rh,
                                                  const cd* __restrict__ bh, int it, int nwg_row) {
-  using C = ColCfg<NY>;
+  using C = ColCfg<NY, 2>;
   if (!INIT && g.st->conv_at <= it) return;
-  __shared__ cd buf[C::C * C::LS];
-  __shared__ double red[7 * 4];
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[7 * (C::NT / 64)];
   __shared__ double Ks[4];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
+  cd tv[C::ET], av[C::EP], bv[C::EP];
+  colT_gload<NY, 2, 2>(tv, Fx, Fy, kx0, g.h);
+  if (INIT) {
+    colP_gload<NY, 2>(av, bh, kx0, g.h);
+  } else {
+    colP_gload<NY, 2>(av, dh, kx0, g.h);
+    colP_gload<NY, 2>(bv, rh, kx0, g.h);
+  }
   if (INIT) {
     double kb[4], sc[2];
     sum_partials<C::NT, 4>(slot_ptr(g.part, SLOT_KBAR), nwg_row, MAX_WG, kb, red);
@@ -630,37 +642,27 @@ __global__ void __launch_bounds__(256) k_col_div(Geo g, const cd* __restrict__ F
   } else if (threadIdx.x < 4) {
     Ks[threadIdx.x] = g.st->kbar[threadIdx.x];
   }
-  cd fx[C::E];
-  col_load<NY>(buf, Fx, kx0, g.h);
+  colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-#pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    fx[i] = buf[(e / NY) * C::LS + e % NY];
-  }
-  __syncthreads();
-  col_load<NY>(buf, Fy, kx0, g.h);
-  __syncthreads();
-  lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int c = e / NY, ky = e % NY;
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
     const int kx = kx0 + c;
-    if (kx < g.h) {
-      const cd fy = buf[c * C::LS + ky];
-      const double xx = kx == 0 ? 0.0 : TWO_PI * kx / g.lx;
+    if (p < C::CN && kx < g.h) {
+      const cd fx = buf[c * C::LS + ky], fy = buf[(C::C + c) * C::LS + ky];
+      const double xx = xi_col(kx, g.lx);
       const double yy = xi_tilde(ky, NY, g.ly);
       // q = -i (xx Fx + yy Fy)
-      const double ax = xx * fx[i].x + yy * fy.x, ay = xx * fx[i].y + yy * fy.y;
+      const double ax = xx * fx.x + yy * fy.x, ay = xx * fx.y + yy * fy.y;
       const cd q = mk<double>(ay, -ax);
       const double w = kx == 0 ? 1.0 : 2.0;
       const double sig = precond_symbol_inv(Ks, xx, yy);
       const size_t idx = (size_t)kx * NY + ky;
       if (INIT) {
-        const cd b = bh[idx];
+        const cd b = av[i];
         const cd rn = sub(b, q);
         rh[idx] = rn;
         const double rr = rn.x * rn.x + rn.y * rn.y;
@@ -669,7 +671,7 @@ __global__ void __launch_bounds__(256) k_col_div(Geo g, const cd* __restrict__ F
         s[2] += w * (b.x * b.x + b.y * b.y);
       } else {
         qh[idx] = q;
-        const cd d = dh[idx], rv = rh[idx];
+        const cd d = av[i], rv = bv[i];
         const double qq = q.x * q.x + q.y * q.y;
         const double rq = rv.x * q.x + rv.y * q.y;
         s[0] += w * (d.x * q.x + d.y * q.y);
@@ -684,28 +686,38 @@ __global__ void __launch_bounds__(256) k_col_div(Geo g, const cd* __restrict__ F
     }
   }
   block_sum<C::NT, 7>(s, red);
-  write_partials(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
+  write_partials<C::NT>(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
 }
 
 // PCG scalar step + vector update + next direction + its gradient (mixed).
 // first: d = M^-1 r.  else: alpha, beta from the partials of k_col_div (the
-// new <r,M^-1 r> and ||r||^2 follow from the expansion of r - alpha q around
-// the directly computed old values), then x += alpha d, r -= alpha q,
-// d = M^-1 r + beta d.
+// new <r,M^-1 r> follows from the expansion of <r - alpha q, M^-1 (r - alpha q)>
+// around the directly computed old value; it is used for beta only), then
+// x += alpha d, r -= alpha q, d = M^-1 r + beta d.  The stopping test on the
+// new residual is taken by the next pass from its direct norm (SLOT_RR).
 template <int NY>
-__global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd* rh, cd* dh,
+__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cd* xh, cd* rh, cd* dh,
                                                     const cd* __restrict__ qh, cd* Gx, cd* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
-  using C = ColCfg<NY>;
+  using C = ColCfg<NY, 2>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
-  __shared__ cd buf[C::C * C::LS];
-  __shared__ double red[7 * 4];
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[7 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   const bool lead = (blockIdx.x == 0 && threadIdx.x == 0);
   double K[4];
   for (int i = 0; i < 4; ++i) K[i] = st->kbar[i];
+  // vectors of the block, loaded before the scalar reduction so that both
+  // latencies overlap
+  cd xv[C::EP], rv0[C::EP], dv0[C::EP], qv[C::EP];
+  colP_gload<NY, 2>(rv0, rh, kx0, g.h);
+  if (!first) {
+    colP_gload<NY, 2>(xv, xh, kx0, g.h);
+    colP_gload<NY, 2>(dv0, dh, kx0, g.h);
+    colP_gload<NY, 2>(qv, qh, kx0, g.h);
+  }
   double alpha = 0.0, beta = 0.0;
   bool stop = false, zero_x = false;
   if (first) {
@@ -733,9 +745,7 @@ __global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd
     stop = zero_x;
   } else {
     // rho = <r,M^-1 r> of the residual the last operator pass read, computed
-    // directly from it; the new rho (for beta only) follows from the
-    // expansion of <r - alpha q, M^-1 (r - alpha q)> around it.  The stopping
-    // test on the new residual is taken by the next pass from its direct norm.
+    // directly from it
     double s[7];
     sum_partials<C::NT, 7>(slot_ptr(g.part, SLOT_P3), nwg_col, MAX_WG, s, red);
     const double rho = s[5];
@@ -755,92 +765,77 @@ __global__ void __launch_bounds__(256) k_col_update(Geo g, int first, cd* xh, cd
     }
   }
   double rrp[1] = {0.0};
-  cd dv[C::E];
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int c = e / NY, ky = e % NY;
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
     const int kx = kx0 + c;
-    if (kx < g.h) {
+    cd d = mk<double>(0.0, 0.0);
+    if (p < C::CN && kx < g.h) {
       const size_t idx = (size_t)kx * NY + ky;
       if (zero_x) {
         xh[idx] = mk<double>(0.0, 0.0);
-        continue;
-      }
-      cd rv = rh[idx];
-      cd d;
-      if (first) {
-        d = mk<double>(0.0, 0.0);
       } else {
-        d = dh[idx];
-        const cd q = qh[idx];
-        xh[idx] = add(xh[idx], scl(d, alpha));
-        rv = sub(rv, scl(q, alpha));
-        rh[idx] = rv;
-        rrp[0] += (kx == 0 ? 1.0 : 2.0) * (rv.x * rv.x + rv.y * rv.y);
+        cd rv = rv0[i];
+        if (!first) {
+          d = dv0[i];
+          xh[idx] = add(xv[i], scl(d, alpha));
+          rv = sub(rv, scl(qv[i], alpha));
+          rh[idx] = rv;
+          rrp[0] += (kx == 0 ? 1.0 : 2.0) * (rv.x * rv.x + rv.y * rv.y);
+        }
+        if (!stop) {
+          const double sig = precond_symbol_inv(K, xi_col(kx, g.lx), xi_tilde(ky, NY, g.ly));
+          d = add(scl(rv, sig), scl(d, beta));
+          dh[idx] = d;
+        }
       }
-      if (!stop) {
-        const double xx = kx == 0 ? 0.0 : TWO_PI * kx / g.lx;
-        const double yy = xi_tilde(ky, NY, g.ly);
-        const double sig = precond_symbol_inv(K, xx, yy);
-        d = add(scl(rv, sig), scl(d, beta));
-        dh[idx] = d;
-      }
-      dv[i] = d;
-    } else {
-      dv[i] = mk<double>(0.0, 0.0);
     }
+    if (!stop && p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, d, g);
   }
   if (!first && !zero_x) {
     block_sum<C::NT, 1>(rrp, red);
-    write_partials(slot_ptr(g.part, SLOT_RR), rrp, 1);
+    write_partials<C::NT>(slot_ptr(g.part, SLOT_RR), rrp, 1);
   }
   if (stop) return;
-  for (int comp = 0; comp < 2; ++comp) {
-#pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      const int c = e / NY, ky = e % NY;
-      const int kx = kx0 + c;
-      const double xi = comp == 0 ? (kx == 0 ? 0.0 : TWO_PI * kx / g.lx) : xi_tilde(ky, NY, g.ly);
-      const double s = xi * g.inv_n;
-      buf[c * C::LS + ky] = mk<double>(-s * dv[i].y, s * dv[i].x);
-    }
-    __syncthreads();
-    lds_fft<double, +1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-    col_store<NY>(buf, comp == 0 ? Gx : Gy, kx0, g.h);
-    __syncthreads();
-  }
+  __syncthreads();
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 
 // Diffusion: forward y transform, multiply by exp(-D^2 |xi|^2 dt) / n (the
 // packed column is unpacked into its kx = 0 and kx = Nx/2 halves for this),
-// inverse y transform.  Optional partial sum w |xi_tilde|^2 |m_hat_new|^2.
+// inverse y transform; both components batched.  Optional partial sum
+// w |xi_tilde|^2 |m_hat_new|^2.
 template <int NY>
-__global__ void __launch_bounds__(256) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
-  using C = ColCfg<NY>;
-  __shared__ cd buf[C::C * C::LS];
-  __shared__ double red[1 * 4];
+__global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
+  using C = ColCfg<NY, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[1 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   const double xnyq = TWO_PI * (g.nx / 2) / g.lx;  // full wavenumber of the kx = Nx/2 column
+  cd tv[C::ET];
+  colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
+  colT_put<NY, 2, 2>(buf, tv);
+  __syncthreads();
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[1] = {0.0};
-  for (int comp = 0; comp < 2; ++comp) {
-    cd* F = comp == 0 ? Mx : My;
-    col_load<NY>(buf, F, kx0, g.h);
-    __syncthreads();
-    lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-    cd v[C::E];
+  cd v[2][C::EP];
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      const int c = e / NY, ky = e % NY;
+  for (int f = 0; f < 2; ++f) {
+#pragma unroll
+    for (int i = 0; i < C::EP; ++i) {
+      const int p = threadIdx.x + i * C::NT;
+      const int c = p / NY, ky = p % NY;
       const int kx = kx0 + c;
+      if (p >= C::CN) continue;
       const double yf = xi_full(ky, NY, g.ly);
-      const cd a = buf[c * C::LS + ky];
+      const cd* line = buf + (f * C::C + c) * C::LS;
+      const cd a = line[ky];
       cd out;
       if (kx == 0) {
-        const cd b = buf[c * C::LS + ((NY - ky) & (NY - 1))];
+        const cd b = line[(NY - ky) & (NY - 1)];
         const double hA = exp(-D2dt * (yf * yf)) * g.inv_n;
         const double hB = exp(-D2dt * (xnyq * xnyq + yf * yf)) * g.inv_n;
         // P' = (hA+hB)/2 P(ky) + (hA-hB)/2 conj P(-ky)
@@ -849,62 +844,60 @@ __global__ void __launch_bounds__(256) k_col_heat(Geo g, cd* Mx, cd* My, double 
         const double xx = TWO_PI * kx / g.lx;
         out = scl(a, exp(-D2dt * (xx * xx + yf * yf)) * g.inv_n);
       }
-      v[i] = out;
+      v[f][i] = out;
       if (eslot && kx < g.h) {
-        const double xt = kx == 0 ? 0.0 : TWO_PI * kx / g.lx;
-        const double yt = xi_tilde(ky, NY, g.ly);
+        const double xt = xi_col(kx, g.lx), yt = xi_tilde(ky, NY, g.ly);
         const double w = kx == 0 ? 1.0 : 2.0;
         s[0] += w * (xt * xt + yt * yt) * (out.x * out.x + out.y * out.y);
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      buf[(e / NY) * C::LS + e % NY] = v[i];
-    }
-    __syncthreads();
-    lds_fft<double, +1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-    col_store<NY>(buf, F, kx0, g.h);
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+#pragma unroll
+    for (int i = 0; i < C::EP; ++i) {
+      const int p = threadIdx.x + i * C::NT;
+      if (p < C::CN) buf[(f * C::C + p / NY) * C::LS + p % NY] = v[f][i];
+    }
+  }
+  __syncthreads();
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  colT_store<NY, 2, 2>(buf, Mx, My, kx0, g.h);
   if (eslot) {
     block_sum<C::NT, 1>(s, red);
-    write_partials(eslot, s, 1);
+    write_partials<C::NT>(eslot, s, 1);
   }
 }
 
 // Parseval sum w |xi_tilde|^2 |f_hat|^2 over two mixed fields (||grad m||^2 * n)
 template <int NY>
-__global__ void __launch_bounds__(256) k_col_gradnorm(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+__global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                       double* eslot) {
-  using C = ColCfg<NY>;
-  __shared__ cd buf[C::C * C::LS];
-  __shared__ double red[1 * 4];
+  using C = ColCfg<NY, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  __shared__ double red[1 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
+  cd tv[C::ET];
+  colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
+  colT_put<NY, 2, 2>(buf, tv);
+  __syncthreads();
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[1] = {0.0};
-  for (int comp = 0; comp < 2; ++comp) {
-    col_load<NY>(buf, comp == 0 ? Mx : My, kx0, g.h);
-    __syncthreads();
-    lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
-#pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int e = threadIdx.x + i * C::NT;
-      const int c = e / NY, ky = e % NY;
-      const int kx = kx0 + c;
-      if (kx < g.h) {
-        const cd a = buf[c * C::LS + ky];
-        const double xt = kx == 0 ? 0.0 : TWO_PI * kx / g.lx;
-        const double yt = xi_tilde(ky, NY, g.ly);
-        const double w = kx == 0 ? 1.0 : 2.0;
-        s[0] += w * (xt * xt + yt * yt) * (a.x * a.x + a.y * a.y);
-      }
+  for (int e = threadIdx.x; e < 2 * C::CN; e += C::NT) {
+    const int f = e / C::CN, ee = e % C::CN;
+    const int c = ee / NY, ky = ee % NY;
+    const int kx = kx0 + c;
+    if (kx < g.h) {
+      const cd a = buf[(f * C::C + c) * C::LS + ky];
+      const double xt = xi_col(kx, g.lx), yt = xi_tilde(ky, NY, g.ly);
+      const double w = kx == 0 ? 1.0 : 2.0;
+      s[0] += w * (xt * xt + yt * yt) * (a.x * a.x + a.y * a.y);
     }
-    __syncthreads();
   }
   block_sum<C::NT, 1>(s, red);
-  write_partials(eslot, s, 1);
+  write_partials<C::NT>(eslot, s, 1);
 }
 
 // ================================================================ launchers
@@ -923,13 +916,21 @@ __global__ void __launch_bounds__(256) k_col_gradnorm(Geo g, const cd* __restric
     default: return hipErrorInvalidValue;    \
   }
 
+// Launch through hipExtLaunchKernelGGL when a start/stop event pair is given
+// (the events are then timestamped by the dispatch itself).
+#define NF_LAUNCH(K, GRID, BLK, S, E0, E1, ...)                                   \
+  do {                                                                             \
+    if (E0) hipExtLaunchKernelGGL(K, GRID, BLK, 0, S, E0, E1, 0, __VA_ARGS__);     \
+    else hipLaunchKernelGGL(K, GRID, BLK, 0, S, __VA_ARGS__);                      \
+  } while (0)
+
 static int row_rows(int nx) {
   const int h = nx / 2;
-  int r = 2048 / h;
+  int r = TILE / h;
   return r < 1 ? 1 : (r > 64 ? 64 : r);
 }
 static int col_cols(int ny) {
-  int c = 2048 / ny;
+  int c = TILE / ny;
   return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
 int row_nwg(const Geo& g) {
@@ -956,31 +957,31 @@ hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o
 }
 
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out, double* schk, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+  const dim3 grid(row_nwg(g)), blk(TPF);
 #define L_(N) hipLaunchKernelGGL(k_row_r2c<N>, grid, blk, 0, s, g, f, (cd*)out, schk)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+  const dim3 grid(row_nwg(g)), blk(TPF);
 #define L_(N) hipLaunchKernelGGL(k_row_c2r<N>, grid, blk, 0, s, g, (const cd*)in, f)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
-                           double* kslot, double tol2, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+                           double* kslot, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(row_nwg(g)), blk(2 * TPF);
   const int nwg_col = col_nwg(g);
-#define L_(N) hipLaunchKernelGGL(k_row_flux<N>, grid, blk, 0, s, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2)
+#define L_(N) NF_LAUNCH(k_row_flux<N>, grid, blk, s, e0, e1, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+  const dim3 grid(row_nwg(g)), blk(3 * TPF);
 #define L_(N)                                                                                            \
   hipLaunchKernelGGL(k_row_split<N>, grid, blk, 0, s, g, (cd*)P, (cd*)Gx, (const cd*)Gy, m, p_out, c2dt, \
                      gamma, dt, relax1)
@@ -990,7 +991,7 @@ hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const dou
 }
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dslot,
                             hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+  const dim3 grid(row_nwg(g)), blk(2 * TPF);
 #define L_(N) hipLaunchKernelGGL(k_row_final<N>, grid, blk, 0, s, g, (const cd*)Mx, (const cd*)My, m, dslot)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -998,7 +999,7 @@ hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double
 }
 hipError_t launch_row_energy(const Geo& g, const void* Gx, const void* Gy, const double* m, const double* r,
                              double gamma, double* slot, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(256);
+  const dim3 grid(row_nwg(g)), blk(2 * TPF);
 #define L_(N) \
   hipLaunchKernelGGL(k_row_energy<N>, grid, blk, 0, s, g, (const cd*)Gx, (const cd*)Gy, m, r, gamma, slot)
   NF_DISPATCH(g.nx, L_)
@@ -1007,57 +1008,66 @@ hipError_t launch_row_energy(const Geo& g, const void* Gx, const void* Gy, const
 }
 
 hipError_t launch_col_fwd(const Geo& g, void* in, void* out, int with_grad, void* Gx, void* Gy, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
 #define L_(N) hipLaunchKernelGGL(k_col_fwd<N>, grid, blk, 0, s, g, (cd*)in, (cd*)out, with_grad, (cd*)Gx, (cd*)Gy)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_col_grad(const Geo& g, const void* xh, void* P, void* Gx, void* Gy, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
-#define L_(N) hipLaunchKernelGGL(k_col_grad<N>, grid, blk, 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
-  NF_DISPATCH(g.ny, L_)
+  const dim3 grid(col_nwg(g));
+  if (P) {
+#define L_(N) hipLaunchKernelGGL((k_col_grad<N, false>), grid, dim3(TPF), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
+    NF_DISPATCH(g.ny, L_)
 #undef L_
+  }
+  if (Gx) {
+#define L_(N) hipLaunchKernelGGL((k_col_grad<N, true>), grid, dim3(2 * TPF), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  }
   return hipGetLastError();
 }
 hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy, void* qh, const void* dh,
-                          void* rh, const void* bh, int it, int nwg_row, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
+                          void* rh, const void* bh, int it, int nwg_row, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
   if (init) {
 #define L_(N)                                                                                                 \
-  hipLaunchKernelGGL((k_col_div<N, true>), grid, blk, 0, s, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,         \
-                     (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
+  NF_LAUNCH((k_col_div<N, true>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,             \
+            (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   } else {
 #define L_(N)                                                                                                 \
-  hipLaunchKernelGGL((k_col_div<N, false>), grid, blk, 0, s, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,        \
-                     (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
+  NF_LAUNCH((k_col_div<N, false>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,            \
+            (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
   return hipGetLastError();
 }
 hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
-                             void* Gy, int it, int max_iter, double tol2, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
+                             void* Gy, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
   const int nwg = col_nwg(g);
-#define L_(N)                                                                                              \
-  hipLaunchKernelGGL(k_col_update<N>, grid, blk, 0, s, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, \
-                     (cd*)Gx, (cd*)Gy, it, max_iter, tol2, nwg)
+#define L_(N)                                                                                                  \
+  NF_LAUNCH(k_col_update<N>, grid, blk, s, e0, e1, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, (cd*)Gx, \
+            (cd*)Gy, it, max_iter, tol2, nwg)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* eslot, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
 #define L_(N) hipLaunchKernelGGL(k_col_heat<N>, grid, blk, 0, s, g, (cd*)Mx, (cd*)My, D2dt, eslot)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* eslot, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(256);
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
 #define L_(N) hipLaunchKernelGGL(k_col_gradnorm<N>, grid, blk, 0, s, g, (const cd*)Mx, (const cd*)My, eslot)
   NF_DISPATCH(g.ny, L_)
 #undef L_

@@ -73,6 +73,10 @@ class nf_run_info(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libnf.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+    # torch brings its own HIP runtime; it must be the one in the process before
+    # the library is loaded, or two runtimes end up fighting over the device
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, dp, i64p = ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)
     lib.nf_create_grid.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double),
@@ -169,7 +173,8 @@ class Grid:
         LL = (ctypes.c_double * 3)(self.L[0], self.L[1], 1.0)
         rc = _lib.nf_create_grid(ctypes.byref(self._h), 2, nn, LL, int(dtype), _current_stream())
         if rc != NF_OK:
-            raise NfError(rc, "nf_create_grid failed for n=%s L=%s" % (n, self.L))
+            raise NfError(rc, "nf_create_grid failed for n=%s L=%s: %s"
+                          % (n, self.L, _lib.nf_last_error(None).decode()))
 
     # shapes
     @property
