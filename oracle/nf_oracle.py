@@ -74,6 +74,9 @@ __all__ = [
     "energy",
     "dm_rel",
     "run",
+    "step_adjoint",
+    "misfit_loss",
+    "run_gradient",
 ]
 
 STOP_MAX_STEPS = 0
@@ -475,3 +478,121 @@ def run(m0, p0, r, S, c2, D2, gamma, dt, max_steps, eps_dm=0.0, stop_on_energy=F
             ri.stop_reason = STOP_DM_BELOW_EPS
             break
     return m, p, ri
+
+
+# ---------------------------------------------------------------------------------
+# Discrete adjoint of one time step (reverse mode of the step above)
+# ---------------------------------------------------------------------------------
+#
+# The step maps (m, r, S) to m' = H Rel(Act(m, G p)), p = A(m, r)^+ Pi S.  Given
+# lam = dL/dm', the adjoint returns dL/dm, dL/dr, dL/dS.  Each stage below is the
+# transpose of the corresponding forward stage, written out from its formula:
+#   diffusion H = F^-1 diag(h) F is real symmetric, so H^T = H;
+#   relaxation m** = rho(s) m*/s has Jacobian (rho/s)(I - u u^T) + rho' u u^T;
+#   activation m* = m + kappa(z) (g.m) g, kappa = c2 dt phi1(z), z = c2 dt |g|^2;
+#   g = G p has transpose G^T = neg_div;
+#   the pressure satisfies A p = Pi S with A = G^T K G, K = m m^T + r I, so for
+#   lam_p = dL/dp the adjoint pressure mu solves A mu = Pi lam_p and
+#   dL/dS = Pi mu, dL/dr = -(G mu . G p), dL/dm gains -[(m.Gp) G mu + (m.G mu) G p].
+
+def _relaxation_jacobian_apply(mstar, lam, gamma, dt):
+    """J^T lam for the relaxation map at m* (J is symmetric)."""
+    if gamma == 1.0:
+        return lam * math.exp(-dt)
+    s = np.sqrt(np.sum(mstar * mstar, axis=0))
+    e = 1.0 - gamma
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        b = s ** (2.0 * e) - 2.0 * e * dt
+        rho = np.maximum(b, 0.0) ** (1.0 / (2.0 * e))
+        drho = (s / rho) ** (2.0 * e - 1.0)          # d rho / d s where b > 0
+        u = mstar / s[None]
+        ul = np.sum(u * lam, axis=0)
+        out = (rho / s)[None] * (lam - u * ul[None]) + (drho * ul)[None] * u
+    alive = (b > 0.0) & (s > 0.0)
+    out = np.where(alive[None], out, 0.0)
+    # at |m*| = 0 the map is the identity for gamma > 1 (s^{-2e} -> 0) and
+    # extinct for gamma < 1
+    if gamma > 1.0:
+        out = np.where((s == 0.0)[None], lam, out)
+    return out
+
+
+def _phi1(z):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(z == 0.0, 1.0, np.expm1(z) / np.where(z == 0.0, 1.0, z))
+
+
+def _dphi1(z):
+    """phi1'(z) = (e^z (z - 1) + 1) / z^2, by its Taylor series near 0."""
+    zs = np.where(np.abs(z) < 1e-3, 0.0, z)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        closed = (np.expm1(zs) * (zs - 1.0) + zs) / np.where(zs == 0.0, 1.0, zs * zs)
+    series = 0.5 + z / 3.0 + z * z / 8.0 + z ** 3 / 30.0
+    return np.where(np.abs(z) < 1e-3, series, closed)
+
+
+def step_adjoint(m, p, r, S, c2, D2, gamma, dt, lam_next, rtol=1e-12, max_iter=2000, L=1.0, mu0=None):
+    """Reverse of ``step``: given m = m^k, p = p[m^k] and lam = dL/dm^{k+1},
+    return (dL/dm^k, dL/dr, dL/dS, mu, SolveInfo) for this step alone."""
+    d = m.shape[0]
+    L = _L(L, d)
+    g = grad(p, L)
+    # forward intermediates
+    g2 = np.sum(g * g, axis=0)
+    z = c2 * dt * g2
+    kappa = c2 * dt * _phi1(z)
+    gm = np.sum(g * m, axis=0)
+    mstar = m + (kappa * gm)[None] * g
+    # diffusion (symmetric)
+    lam2 = diffusion(lam_next, D2, dt, L)
+    # relaxation
+    lam1 = _relaxation_jacobian_apply(mstar, lam2, gamma, dt)
+    # activation: w.r.t. m and w.r.t. g
+    gl = np.sum(g * lam1, axis=0)
+    lam_m = lam1 + (kappa * gl)[None] * g
+    dkappa = c2 * dt * _dphi1(z)
+    lam_g = (2.0 * c2 * dt * dkappa * gm * gl)[None] * g + (kappa * gl)[None] * m + (kappa * gm)[None] * lam1
+    # g = G p
+    lam_p = neg_div(lam_g, L)
+    # adjoint pressure: A mu = Pi lam_p (A symmetric); S = 0 trick: solve with lam_p as source
+    mu, info = pressure_pcg(m, r, project(lam_p, L), mu0, rtol, max_iter, L, check=False)
+    gmu = grad(mu, L)
+    dS = project(mu, L)
+    dr = -np.sum(gmu * g, axis=0)
+    mg = np.sum(m * g, axis=0)
+    mgmu = np.sum(m * gmu, axis=0)
+    lam_k = lam_m - (mg[None] * gmu + mgmu[None] * g)
+    return lam_k, dr, dS, mu, info
+
+
+def misfit_loss(m, m_target):
+    """L = 1/2 sum (|m| - |m_target|)^2 and dL/dm (zero where |m| = 0)."""
+    a = np.sqrt(np.sum(m * m, axis=0))
+    at = np.sqrt(np.sum(m_target * m_target, axis=0))
+    diff = a - at
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lam = np.where((a > 0.0)[None], (diff / a)[None] * m, 0.0)
+    return 0.5 * float(np.sum(diff * diff)), lam
+
+
+def run_gradient(m0, r, S, c2, D2, gamma, dt, steps, m_target, rtol=1e-12, max_iter=2000, L=1.0):
+    """Loss of the final state after `steps` time steps (Algorithm 1 without the
+    stopping tests) and its gradients w.r.t. r and S, by storing every state and
+    sweeping the step adjoints backwards.  Returns (loss, dL/dr, dL/dS)."""
+    ms, ps = [], []
+    m = np.array(m0, dtype=np.float64, copy=True)
+    p = None
+    for _ in range(steps):
+        p, _ = pressure_pcg(m, r, S, p, rtol, max_iter, L)
+        ms.append(m)
+        ps.append(p)
+        m = split_update(m, p, c2, D2, gamma, dt, L)
+    loss, lam = misfit_loss(m, m_target)
+    gr = np.zeros_like(r)
+    gS = np.zeros_like(S)
+    mu = None
+    for k in range(steps - 1, -1, -1):
+        lam, dr, dS, mu, _ = step_adjoint(ms[k], ps[k], r, S, c2, D2, gamma, dt, lam, rtol, max_iter, L, mu)
+        gr += dr
+        gS += dS
+    return loss, gr, gS

@@ -12,6 +12,7 @@ import scipy.linalg
 import sympy as sp
 
 import oracle as O
+from oracle import nf_oracle as ON
 from paper_2606_06720_amd import workloads as W
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -451,3 +452,91 @@ def test_paper_internal_sink_has_zero_integral():
         assert abs(S.mean()) < 1e-12
     S4 = W.paper_S4(128)
     assert abs(S4.mean()) < 1e-12
+
+
+# ---------------------------------------------------------------- adjoint -------------
+
+def _fd(fun, x, v, h):
+    return (fun(x + h * v) - fun(x - h * v)) / (2 * h)
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.75, 1.0, 1.2])
+def test_step_adjoint_matches_central_differences(gamma):
+    # the hand-written reverse of one step against central differences of the
+    # forward step (directional derivatives along random m, r, S directions)
+    rng = np.random.default_rng(51)
+    n = (16, 16)
+    sh = n[::-1]
+    m = rng.uniform(0.2, 1.0, (2,) + sh)
+    r = rng.uniform(0.05, 0.15, sh)
+    S = rng.standard_normal(sh)
+    S -= S.mean()
+    c2, D2, dt = 30.0, 2e-3, 2e-3
+    lam = rng.standard_normal((2,) + sh)
+
+    def F(m_, r_, S_):
+        p_, _ = O.pressure_pcg(m_, r_, S_, None, 1e-14, 4000)
+        return float(np.sum(lam * O.split_update(m_, p_, c2, D2, gamma, dt)))
+
+    p, _ = O.pressure_pcg(m, r, S, None, 1e-14, 4000)
+    lk, dr, dS, mu, info = O.step_adjoint(m, p, r, S, c2, D2, gamma, dt, lam, rtol=1e-14)
+    vm = rng.standard_normal((2,) + sh)
+    vr = rng.standard_normal(sh)
+    vS = rng.standard_normal(sh)
+    vS -= vS.mean()
+    h = 1e-6
+    fd_m = _fd(lambda x: F(x, r, S), m, vm, h)
+    fd_r = _fd(lambda x: F(m, x, S), r, vr, h)
+    fd_S = _fd(lambda x: F(m, r, x), S, vS, h)
+    for fd, ad in ((fd_m, np.sum(lk * vm)), (fd_r, np.sum(dr * vr)), (fd_S, np.sum(dS * vS))):
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3 * abs(fd_m))
+
+
+def test_relaxation_and_activation_derivative_pieces():
+    # phi1' by its Taylor series near 0 joins the closed form continuously
+    z = np.array([0.0, 1e-8, 9.99e-4, 1.001e-3, 0.3, 2.0])
+    d = ON._dphi1(z)
+    assert abs(d[0] - 0.5) < 1e-16 and abs(d[1] - (0.5 + 1e-8 / 3)) < 1e-15
+    assert abs(d[2] - d[3]) < 1e-6
+    for zz in (0.3, 2.0):
+        h = 1e-6
+        fd = (ON._phi1(np.array(zz + h)) - ON._phi1(np.array(zz - h))) / (2 * h)
+        assert abs(ON._dphi1(np.array(zz)) - fd) < 1e-8
+    # relaxation Jacobian (symmetric) against central differences of the map
+    rng = np.random.default_rng(53)
+    for gamma in (0.6, 1.0, 1.3):
+        ms = rng.uniform(0.3, 1.0, (2, 3, 3))
+        lam = rng.standard_normal((2, 3, 3))
+        v = rng.standard_normal((2, 3, 3))
+        jt = ON._relaxation_jacobian_apply(ms, lam, gamma, 0.05)
+        fd = _fd(lambda x: float(np.sum(lam * O.relaxation(x, gamma, 0.05))), ms, v, 1e-7)
+        assert abs(fd - np.sum(jt * v)) < 1e-7 * abs(fd)
+
+
+def test_run_gradient_matches_central_differences():
+    # multi-step reverse sweep (every state stored) against central differences
+    # of the misfit of the final |m|, along random r and S directions
+    w = W.bump_workload(16)
+    rng = np.random.default_rng(57)
+    steps = 4
+    prm = (w["c2"], w["D2"], w["gamma"], w["dt"])
+    m_tgt = O.run(w["m0"], None, w["r"] * 1.05, w["S"], *prm, max_steps=steps, rtol=1e-14)[0]
+
+    def loss(r_, S_):
+        m = w["m0"]
+        p = None
+        for _ in range(steps):
+            p, _ = O.pressure_pcg(m, r_, S_, p, 1e-14, 4000)
+            m = O.split_update(m, p, *prm)
+        return O.misfit_loss(m, m_tgt)[0]
+
+    l0, gr, gS = O.run_gradient(w["m0"], w["r"], w["S"], *prm, steps, m_tgt, rtol=1e-14)
+    assert abs(l0 - loss(w["r"], w["S"])) < 1e-12 * l0
+    vr = rng.standard_normal(w["r"].shape)
+    vS = rng.standard_normal(w["S"].shape)
+    vS -= vS.mean()
+    h = 1e-6
+    fd_r = _fd(lambda x: loss(x, w["S"]), w["r"], vr, h)
+    fd_S = _fd(lambda x: loss(w["r"], x), w["S"], vS, h)
+    assert abs(fd_r - np.sum(gr * vr)) < 1e-5 * abs(fd_r)
+    assert abs(fd_S - np.sum(gS * vS)) < 1e-5 * abs(fd_S)
