@@ -82,6 +82,80 @@ def cpu_baseline(N, steps):
     }
 
 
+def adjoint_cost(N, steps):
+    """Cost of reverse mode at N^2 (gamma = 0.75, the 1024^2 dipole case): one
+    nf_step_adjoint against one nf_step (both from the same state), and the
+    sqrt(T)-checkpointed gradient of the misfit of the final |m| after `steps`
+    steps against the forward run of those steps."""
+    import numpy as np
+    import torch
+
+    from paper_2606_06720_amd import adjoint as A
+    from paper_2606_06720_amd import nf as NF
+    from paper_2606_06720_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    w = W.dipole_workload(N, 0.75)
+    prm = (w["c2"], w["D2"], w["gamma"])
+    r, S, m0 = T(w["r"]), T(w["S"]), T(w["m0"])
+    f2 = W.smooth_random_field(np.random.default_rng(6), (N, N), 1.0)
+    rtol = 1e-10
+    with NF.Grid(w["n"], w["L"]) as g:
+        m_tgt, _ = A.forward_states(g, prm, w["dt"], steps, m0, T(w["r"] * (1 + 0.1 * f2)), S, rtol, 1000, steps)
+        # warm state after a few steps
+        m = m0.clone()
+        p = torch.zeros_like(r)
+        for _ in range(5):
+            g.step(*prm, w["dt"], m, p, r, S, rtol=rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_T, ckpt = A.forward_states(g, prm, w["dt"], steps, m0, r, S, rtol, 1000, steps + 1)
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t0
+        stride = int(np.ceil(np.sqrt(steps)))
+        # one untimed gradient first, so that the checkpoint buffers come from
+        # the caching allocator in the timed one
+        m_T, ckpt = A.forward_states(g, prm, w["dt"], steps, m0, r, S, rtol, 1000, stride)
+        _, lam_T = A.misfit_loss(m_T, m_tgt)
+        A.adjoint_sweep(g, prm, w["dt"], steps, r, S, ckpt, lam_T, rtol, 1000, stride)
+        del ckpt
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_T, ckpt = A.forward_states(g, prm, w["dt"], steps, m0, r, S, rtol, 1000, stride)
+        _, lam_T = A.misfit_loss(m_T, m_tgt)
+        torch.cuda.synchronize()
+        t_ckpt = time.perf_counter() - t0
+        st = {}
+        t0 = time.perf_counter()
+        A.adjoint_sweep(g, prm, w["dt"], steps, r, S, ckpt, lam_T, rtol, 1000, stride, st)
+        torch.cuda.synchronize()
+        t_sweep = time.perf_counter() - t0
+        # the sweep recomputes every segment: time that part alone
+        t0 = time.perf_counter()
+        for c in sorted(ckpt):
+            mm, pp = ckpt[c][0].clone(), ckpt[c][1].clone()
+            for k in range(c, min(c + stride, steps)):
+                g.step(*prm, w["dt"], mm, pp, r, S, rtol=rtol, max_iter=1000)
+        torch.cuda.synchronize()
+        t_rec = time.perf_counter() - t0
+    t_adj = t_sweep - t_rec
+    t_fwd = t_run / steps
+    return {
+        "workload": "%d^2 dipole case, gamma 0.75, PCG rtol 1e-10, misfit of the final |m|" % N,
+        "gradient_steps": steps,
+        "checkpoint_stride": stride,
+        "forward_step_ms": 1e3 * t_fwd,
+        "adjoint_step_ms": 1e3 * t_adj / steps,
+        "adjoint_over_forward_step": (t_adj / steps) / t_fwd,
+        "forward_pcg_iters_per_step": st.get("recompute_iters", 0) / steps,
+        "adjoint_pcg_iters_per_step": st.get("adjoint_iters", 0) / steps,
+        "forward_run_ms": 1e3 * t_run,
+        "checkpointed_gradient_ms": 1e3 * (t_ckpt + t_sweep),
+        "gradient_over_forward_run": (t_ckpt + t_sweep) / t_run,
+    }
+
+
 def copy_calibration(nbytes):
     """A plain device-to-device copy of known size, for scaling HBM counters."""
     import torch
@@ -104,6 +178,7 @@ def main():
     ap.add_argument("--kernel", default="row_flux", choices=sorted(KERNEL_IDS))
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the reverse-mode cost run (0 = skip)")
     ap.add_argument("--sequential", action="store_true", help="run the instances one after another on one stream")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     args = ap.parse_args()
@@ -227,6 +302,8 @@ def main():
         },
         "roofline": roofline,
     }
+    if args.adjoint_steps > 0:
+        out["adjoint_cost"] = adjoint_cost(N, args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
     for it in inst:

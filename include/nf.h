@@ -161,6 +161,28 @@ int nf_energy(nf_grid *g, const nf_params *prm, const double *m, const double *p
               double out[5]);
 
 /*
+ * Discrete adjoint (reverse mode) of one nf_step.  The step maps
+ * (m^k, r, S) -> m^{k+1} = H Rel(Act(m^k, grad p)), p = p[m^k].  Given
+ * lam_next = dL/dm^{k+1}, this computes, by transposing each stage:
+ *   diffusion (H symmetric), relaxation (Jacobian of eq. m_relaxation_discrete),
+ *   activation (Jacobian of eq. m_activation_discrete w.r.t. m and grad p),
+ *   the gradient grad p, and the pressure equation (eq. p_discrete): since the
+ *   operator A is symmetric, the adjoint pressure mu solves A mu = Pi G^T lam_g
+ *   with the same PCG as nf_pressure_solve.
+ * Inputs (device, layouts as above): m = m^k [2][Ny][Nx], p = p[m^k] (as
+ * returned by nf_step for that step), r, S, lam_next [2][Ny][Nx].
+ * Outputs: lam_k [2][Ny][Nx] = dL/dm^k (overwritten); grad_r, grad_S [Ny][Nx]
+ * are ACCUMULATED (+=) with this step's dL/dr and dL/dS; mu [Ny][Nx] is the
+ * adjoint pressure (in: warm start, out: solution).  rtol/max_iter as in
+ * nf_pressure_solve; info may be NULL.
+ * Returns NF_OK, NF_ENOTCONV (outputs written with the last iterate),
+ * NF_ENONFINITE, NF_EINVAL or NF_EDEVICE.
+ */
+int nf_step_adjoint(nf_grid *g, const nf_params *prm, double dt, const double *m, const double *p, const double *r,
+                    const double *S, const double *lam_next, double *lam_k, double *grad_r, double *grad_S,
+                    double *mu, double rtol, int max_iter, nf_solve_info *info);
+
+/*
  * Diagnostic entry points exposing single stages of the path, for unit checks
  * of the transforms and of the operator against independent references.
  *

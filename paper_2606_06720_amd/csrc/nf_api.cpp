@@ -531,6 +531,56 @@ int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, c
   return solve_status_code(g, so);
 }
 
+int nf_step_adjoint(nf_grid* g, const nf_params* prm, double dt, const double* m, const double* p, const double* r,
+                    const double* S, const double* lam_next, double* lam_k, double* grad_r, double* grad_S,
+                    double* mu, double rtol, int max_iter, nf_solve_info* info) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  int rc = check_fields(g, {m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu});
+  if (rc) return rc;
+  rc = check_params(g, prm, dt);
+  if (rc) return rc;
+  if (!(rtol >= 0.0) || max_iter < 0) return fail(g, NF_EINVAL, "rtol must be >= 0 and max_iter >= 0");
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny;
+  LCHK(g, launch_status_reset(G, 1, s));
+  // adjoint through the diffusion stage: H lam (H symmetric)
+  LCHK(g, launch_row_r2c(G, lam_next, g->mix[0], nullptr, s));
+  LCHK(g, launch_row_r2c(G, lam_next + n, g->mix[1], nullptr, s));
+  LCHK(g, launch_col_heat(G, g->mix[0], g->mix[1], prm->D2 * dt, nullptr, s));
+  // grad p^k
+  LCHK(g, launch_row_r2c(G, p, g->mix[2], nullptr, s));
+  LCHK(g, launch_col_fwd(G, g->mix[2], g->dh, 1, g->mix[2], g->qh, s));
+  // through relaxation and activation: lam_m -> lam_k, lam_g -> mix[0..1]
+  LCHK(g, launch_row_adj1(G, g->mix[0], g->mix[1], g->mix[2], g->qh, m, lam_k, prm->c2 * dt, prm->gamma, dt,
+                          std::exp(-dt), s));
+  // adjoint pressure: A mu = Pi G^T lam_g
+  LCHK(g, launch_col_divrhs(G, g->mix[0], g->mix[1], g->bh, s));
+  LCHK(g, launch_zero_doubles(slot_ptr(g->part, SLOT_SCHK), 2 * (size_t)MAX_WG, s));
+  SolveOut so;
+  rc = pcg(g, m, r, X_FROM_P, mu, rtol, max_iter, info != nullptr, &so);
+  if (rc) return rc;
+  // gradients
+  LCHK(g, launch_col_grad(G, g->xh, g->mix[0], g->mix[1], g->mix[2], s));
+  LCHK(g, launch_row_c2r(G, g->mix[0], mu, s));
+  LCHK(g, launch_row_r2c(G, p, g->rh, nullptr, s));
+  LCHK(g, launch_col_fwd(G, g->rh, g->dh, 1, g->rh, g->qh, s));
+  LCHK(g, launch_row_adj2(G, g->mix[1], g->mix[2], g->rh, g->qh, m, mu, lam_k, grad_r, grad_S, s));
+  DevStatus fin;
+  rc = read_status(g, &fin);
+  if (rc) return rc;
+  if (info) {
+    info->iters = so.iters;
+    info->converged = so.converged;
+    info->rel_res = so.rel_res;
+    info->true_rel_res = so.true_rel_res;
+  }
+  if ((so.flags | fin.flags) & FLAG_NONFINITE) return fail(g, NF_ENONFINITE, "non-finite values in the adjoint step");
+  if (!so.converged) return fail(g, NF_ENOTCONV, "adjoint PCG did not reach the tolerance within max_iter");
+  return NF_OK;
+}
+
 int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p, const double* r, const double* S,
               double out[5]) {
   if (!g) return NF_EINVAL;

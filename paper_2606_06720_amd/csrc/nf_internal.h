@@ -89,6 +89,14 @@ hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* 
                              hipEvent_t e1 = nullptr);
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* egm_slot, hipStream_t s);
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* egm_slot, hipStream_t s);
+// adjoint passes
+hipError_t launch_row_adj1(const Geo& g, void* A0, void* A1, const void* G0, const void* G1, const double* m,
+                           double* lam_out, double c2dt, double gamma, double dt, double relax1, hipStream_t s);
+hipError_t launch_row_adj2(const Geo& g, const void* M1, const void* M2, const void* P1, const void* P2,
+                           const double* m, const double* mu, double* lam, double* grad_r, double* grad_S,
+                           hipStream_t s);
+hipError_t launch_col_divrhs(const Geo& g, const void* V0, const void* V1, void* bh, hipStream_t s);
+hipError_t launch_zero_doubles(double* p, size_t n, hipStream_t s);
 // reduce K arrays of n partials of a slot into st->out[o..o+K)
 hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o, hipStream_t s);
 

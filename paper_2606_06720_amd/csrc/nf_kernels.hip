@@ -524,6 +524,180 @@ __global__ void __launch_bounds__(2 * TPF) k_row_energy(Geo g, const cd* __restr
   write_partials<C::NT>(eslot, s, 3);
 }
 
+// ================================================================ adjoint row kernels
+// phi1'(z) = (e^z (z - 1) + 1) / z^2, by its Taylor series near 0
+__device__ __forceinline__ double dphi1(double z) {
+  if (fabs(z) < 1e-3) return 0.5 + z * (1.0 / 3.0 + z * (0.125 + z * (1.0 / 30.0)));
+  return (expm1(z) * (z - 1.0) + z) / (z * z);
+}
+
+// Reverse of the pointwise part of the split update at one grid point.
+// In: m (= m^k), g (= grad p^k), lam2 (= H^T lam^{k+1}, the adjoint after the
+// diffusion stage).  Out: lam_m (adjoint of m through activation and
+// relaxation) and lam_g (adjoint of g).
+__device__ __forceinline__ void adjoint_point(double mx, double my, double gx, double gy, double lx, double ly,
+                                              double c2dt, double gamma, double dt, double relax1, double& lmx,
+                                              double& lmy, double& lgx, double& lgy) {
+  // forward activation intermediates
+  const double g2 = gx * gx + gy * gy;
+  const double z = c2dt * g2;
+  const double kap = c2dt * (z > 0.0 ? expm1(z) / z : 1.0);
+  const double dkap = c2dt * dphi1(z);
+  const double gm = gx * mx + gy * my;
+  const double sx = fma(kap * gm, gx, mx), sy = fma(kap * gm, gy, my);  // m*
+  // relaxation Jacobian (symmetric): fac (I - u u^T) + rho' u u^T
+  double ax, ay;
+  if (gamma == 1.0) {
+    ax = relax1 * lx;
+    ay = relax1 * ly;
+  } else {
+    const double s2 = sx * sx + sy * sy;
+    const double e1 = 1.0 - gamma;
+    if (s2 == 0.0) {
+      ax = gamma > 1.0 ? lx : 0.0;
+      ay = gamma > 1.0 ? ly : 0.0;
+    } else {
+      const double u = 2.0 * e1 * dt * exp(-e1 * log(s2));
+      if (u >= 1.0) {
+        ax = ay = 0.0;
+      } else {
+        const double fac = exp(log1p(-u) / (2.0 * e1));   // rho / s
+        const double drho = exp((1.0 - 2.0 * e1) * log(fac));  // rho'(s) = (s/rho)^{2e-1}
+        const double is = 1.0 / sqrt(s2);
+        const double ux = sx * is, uy = sy * is;
+        const double ul = ux * lx + uy * ly;
+        ax = fac * (lx - ux * ul) + drho * ul * ux;
+        ay = fac * (ly - uy * ul) + drho * ul * uy;
+      }
+    }
+  }
+  // activation: d m*/d m = I + kap g g^T;  d m*/d g as in the oracle
+  const double gl = gx * ax + gy * ay;
+  lmx = fma(kap * gl, gx, ax);
+  lmy = fma(kap * gl, gy, ay);
+  const double t = 2.0 * c2dt * dkap * gm * gl;
+  lgx = t * gx + kap * gl * mx + kap * gm * ax;
+  lgy = t * gy + kap * gl * my + kap * gm * ay;
+}
+
+// Adjoint, first pass: c2r of (H lam_x, H lam_y, grad_x p, grad_y p); the
+// pointwise reverse of relaxation and activation; lam_m written to lam_out,
+// lam_g transformed forward back into A0 / A1 (in place).
+template <int NX>
+__global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, const cd* __restrict__ G0,
+                                                      const cd* __restrict__ G1, const double* __restrict__ m,
+                                                      double* __restrict__ lam_out, double c2dt, double gamma,
+                                                      double dt, double relax1) {
+  using C = RowCfg<NX, 4>;
+  __shared__ cd buf[C::NB * C::LS];
+  const cd* tw = (const cd*)g.tw;
+  const int y0 = xcd_block() * C::R;
+  const int nrow = min(C::R, g.ny - y0);
+  const size_t n = (size_t)g.nx * g.ny;
+  cd tv[C::ET];
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::RH, ee = e % C::RH;
+    const int rr = ee % C::R, kx = ee / C::R;
+    const cd* src = f == 0 ? A0 : (f == 1 ? A1 : (f == 2 ? G0 : G1));
+    tv[i] = (e < 4 * C::RH && rr < nrow) ? src[(size_t)kx * g.ny + y0 + rr] : mk<double>(0.0, 0.0);
+  }
+  double2 mx[C::EP], my[C::EP];
+  rowP_gload<NX, 4>(mx, m, y0, nrow);
+  rowP_gload<NX, 4>(my, m + n, y0, nrow);
+  rowT_put<NX, 4>(buf, tv);
+  __syncthreads();
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      cd* plx = buf + rr * C::LS + j;
+      cd* ply = buf + (C::R + rr) * C::LS + j;
+      const cd lx = *plx, ly = *ply;
+      const cd gxv = buf[(2 * C::R + rr) * C::LS + j], gyv = buf[(3 * C::R + rr) * C::LS + j];
+      double lm[2][2], lg[2][2];
+      adjoint_point(mx[i].x, my[i].x, gxv.x, gyv.x, lx.x, ly.x, c2dt, gamma, dt, relax1, lm[0][0], lm[1][0], lg[0][0],
+                    lg[1][0]);
+      adjoint_point(mx[i].y, my[i].y, gxv.y, gyv.y, lx.y, ly.y, c2dt, gamma, dt, relax1, lm[0][1], lm[1][1], lg[0][1],
+                    lg[1][1]);
+      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
+      *(double2*)(lam_out + idx) = make_double2(lm[0][0], lm[0][1]);
+      *(double2*)(lam_out + n + idx) = make_double2(lm[1][0], lm[1][1]);
+      *plx = mk<double>(lg[0][0], lg[0][1]);
+      *ply = mk<double>(lg[1][0], lg[1][1]);
+    }
+  }
+  __syncthreads();
+  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  rowT_store<NX, 4, 2>(buf, A0, A1, nullptr, g.ny, y0, nrow);
+}
+
+// Adjoint, second pass: c2r of (grad mu, grad p); with mu (physical) and m:
+// dL/dS += mu, dL/dr -= grad mu . grad p, and
+// lam -= (m.grad p) grad mu + (m.grad mu) grad p.
+template <int NX>
+__global__ void __launch_bounds__(4 * TPF) k_row_adj2(Geo g, const cd* __restrict__ M1, const cd* __restrict__ M2,
+                                                      const cd* __restrict__ P1, const cd* __restrict__ P2,
+                                                      const double* __restrict__ m, const double* __restrict__ mu,
+                                                      double* lam, double* grad_r, double* grad_S) {
+  using C = RowCfg<NX, 4>;
+  __shared__ cd buf[C::NB * C::LS];
+  const cd* tw = (const cd*)g.tw;
+  const int y0 = xcd_block() * C::R;
+  const int nrow = min(C::R, g.ny - y0);
+  const size_t n = (size_t)g.nx * g.ny;
+  cd tv[C::ET];
+#pragma unroll
+  for (int i = 0; i < C::ET; ++i) {
+    const int e = threadIdx.x + i * C::NT;
+    const int f = e / C::RH, ee = e % C::RH;
+    const int rr = ee % C::R, kx = ee / C::R;
+    const cd* src = f == 0 ? M1 : (f == 1 ? M2 : (f == 2 ? P1 : P2));
+    tv[i] = (e < 4 * C::RH && rr < nrow) ? src[(size_t)kx * g.ny + y0 + rr] : mk<double>(0.0, 0.0);
+  }
+  double2 mx[C::EP], my[C::EP], muv[C::EP];
+  rowP_gload<NX, 4>(mx, m, y0, nrow);
+  rowP_gload<NX, 4>(my, m + n, y0, nrow);
+  rowP_gload<NX, 4>(muv, mu, y0, nrow);
+  rowT_put<NX, 4>(buf, tv);
+  __syncthreads();
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int rr = p / C::H, j = p % C::H;
+    if (p < C::RH && rr < nrow) {
+      const cd umx = buf[rr * C::LS + j], umy = buf[(C::R + rr) * C::LS + j];
+      const cd upx = buf[(2 * C::R + rr) * C::LS + j], upy = buf[(3 * C::R + rr) * C::LS + j];
+      const size_t idx = (size_t)(y0 + rr) * NX + 2 * j;
+      double2 gS = *(const double2*)(grad_S + idx);
+      double2 gr = *(const double2*)(grad_r + idx);
+      double2 l0 = *(const double2*)(lam + idx);
+      double2 l1 = *(const double2*)(lam + n + idx);
+      gS.x += muv[i].x;
+      gS.y += muv[i].y;
+      gr.x -= umx.x * upx.x + umy.x * upy.x;
+      gr.y -= umx.y * upx.y + umy.y * upy.y;
+      const double mgp0 = mx[i].x * upx.x + my[i].x * upy.x, mgp1 = mx[i].y * upx.y + my[i].y * upy.y;
+      const double mgm0 = mx[i].x * umx.x + my[i].x * umy.x, mgm1 = mx[i].y * umx.y + my[i].y * umy.y;
+      l0.x -= mgp0 * umx.x + mgm0 * upx.x;
+      l0.y -= mgp1 * umx.y + mgm1 * upx.y;
+      l1.x -= mgp0 * umy.x + mgm0 * upy.x;
+      l1.y -= mgp1 * umy.y + mgm1 * upy.y;
+      *(double2*)(grad_S + idx) = gS;
+      *(double2*)(grad_r + idx) = gr;
+      *(double2*)(lam + idx) = l0;
+      *(double2*)(lam + n + idx) = l1;
+    }
+  }
+}
+
 // ================================================================ column kernels
 // Write the gradient multipliers i xi_c f_hat / n of one spectral value into
 // the two gradient lines of the column block.
@@ -870,6 +1044,37 @@ __global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, dou
   }
 }
 
+// Adjoint right-hand side: b_hat = Pi F(G^T v) = -i xi_tilde . F(v) for the
+// two mixed fields of v (null modes vanish since xi_tilde does).
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_divrhs(Geo g, const cd* __restrict__ V0, const cd* __restrict__ V1,
+                                                        cd* __restrict__ bh) {
+  using C = ColCfg<NY, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  const cd* tw = (const cd*)g.tw;
+  const int kx0 = blockIdx.x * C::C;
+  cd tv[C::ET];
+  colT_gload<NY, 2, 2>(tv, V0, V1, kx0, g.h);
+  colT_put<NY, 2, 2>(buf, tv);
+  __syncthreads();
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  for (int p = threadIdx.x; p < C::CN; p += C::NT) {
+    const int c = p / NY, ky = p % NY;
+    const int kx = kx0 + c;
+    if (kx < g.h) {
+      const cd fx = buf[c * C::LS + ky], fy = buf[(C::C + c) * C::LS + ky];
+      const double xx = xi_col(kx, g.lx), yy = xi_tilde(ky, NY, g.ly);
+      const double ax = xx * fx.x + yy * fy.x, ay = xx * fx.y + yy * fy.y;
+      bh[(size_t)kx * NY + ky] = mk<double>(ay, -ax);
+    }
+  }
+}
+
+__global__ void k_zero_d(double* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 // Parseval sum w |xi_tilde|^2 |f_hat|^2 over two mixed fields (||grad m||^2 * n)
 template <int NY>
 __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
@@ -1074,4 +1279,39 @@ hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, dou
   return hipGetLastError();
 }
 
+}  // namespace nf
+
+namespace nf {
+hipError_t launch_row_adj1(const Geo& g, void* A0, void* A1, const void* G0, const void* G1, const double* m,
+                           double* lam_out, double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
+  const dim3 grid(row_nwg(g)), blk(4 * TPF);
+#define L_(N)                                                                                                    \
+  hipLaunchKernelGGL(k_row_adj1<N>, grid, blk, 0, s, g, (cd*)A0, (cd*)A1, (const cd*)G0, (const cd*)G1, m, lam_out, \
+                     c2dt, gamma, dt, relax1)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_row_adj2(const Geo& g, const void* M1, const void* M2, const void* P1, const void* P2,
+                           const double* m, const double* mu, double* lam, double* grad_r, double* grad_S,
+                           hipStream_t s) {
+  const dim3 grid(row_nwg(g)), blk(4 * TPF);
+#define L_(N)                                                                                                 \
+  hipLaunchKernelGGL(k_row_adj2<N>, grid, blk, 0, s, g, (const cd*)M1, (const cd*)M2, (const cd*)P1,           \
+                     (const cd*)P2, m, mu, lam, grad_r, grad_S)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_col_divrhs(const Geo& g, const void* V0, const void* V1, void* bh, hipStream_t s) {
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+#define L_(N) hipLaunchKernelGGL(k_col_divrhs<N>, grid, blk, 0, s, g, (const cd*)V0, (const cd*)V1, (cd*)bh)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_zero_doubles(double* p, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 }  // namespace nf

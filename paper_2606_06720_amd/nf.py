@@ -89,6 +89,8 @@ def _load():
     lib.nf_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp, vp,
                            dp, ctypes.c_int, ctypes.POINTER(nf_run_info)]
     lib.nf_energy.argtypes = [vp, ctypes.POINTER(nf_params), vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nf_step_adjoint.argtypes = [vp, ctypes.POINTER(nf_params), dp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dp,
+                                     ctypes.c_int, ctypes.POINTER(nf_solve_info)]
     lib.nf_transform_forward.argtypes = [vp, vp, vp]
     lib.nf_transform_inverse.argtypes = [vp, vp, vp]
     lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
@@ -98,7 +100,7 @@ def _load():
     lib.nf_last_error.restype = ctypes.c_char_p
     lib.nf_version.restype = ctypes.c_char_p
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
-              "nf_energy", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
+              "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
               "nf_time_kernel_read"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
@@ -245,6 +247,20 @@ class Grid:
         return RunInfo(int(info.steps), int(info.stop_reason), float(info.last_dm), float(info.last_energy),
                        float(info.prev_energy), int(info.total_cg_iters), int(info.unconverged_solves))
 
+    def step_adjoint(self, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol=1e-12,
+                     max_iter=2000, allow_notconv=False):
+        """nf_step_adjoint: lam_k <- dL/dm^k; grad_r, grad_S += this step's gradients; mu inout."""
+        self._sync_stream()
+        prm = nf_params(float(c2), float(D2), float(gamma))
+        info = nf_solve_info()
+        rc = _lib.nf_step_adjoint(self._h, ctypes.byref(prm), float(dt), _ptr(m, self.vshape, "m"),
+                                  _ptr(p, self.sshape, "p"), _ptr(r, self.sshape, "r"), _ptr(S, self.sshape, "S"),
+                                  _ptr(lam_next, self.vshape, "lam_next"), _ptr(lam_k, self.vshape, "lam_k"),
+                                  _ptr(grad_r, self.sshape, "grad_r"), _ptr(grad_S, self.sshape, "grad_S"),
+                                  _ptr(mu, self.sshape, "mu"), float(rtol), int(max_iter), ctypes.byref(info))
+        self._check(rc, (NF_ENOTCONV,) if allow_notconv else ())
+        return rc, _si(info)
+
     def energy(self, c2, D2, gamma, m, r, S, p=None):
         """nf_energy: (total, D^2/2|grad m|^2, relaxation, c^2/2|m.grad p|^2, c^2/2 r|grad p|^2)."""
         self._sync_stream()
@@ -313,3 +329,8 @@ def nf_run(g, c2, D2, gamma, dt, max_steps, m, p, r, S, eps_dm=0.0, stop_on_ener
 
 def nf_energy(g, c2, D2, gamma, m, r, S, p=None):
     return g.energy(c2, D2, gamma, m, r, S, p)
+
+
+def nf_step_adjoint(g, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol=1e-12,
+                    max_iter=2000):
+    return g.step_adjoint(c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol, max_iter)

@@ -1,0 +1,116 @@
+"""GPU parity of the discrete adjoint (nf_step_adjoint) and of the checkpointed
+multi-step gradient, against the CPU oracle's adjoint (itself pinned by central
+differences in test_oracle_pins.py), plus central differences of the GPU
+forward run on the 1024^2 grid."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_06720_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2606_06720_amd import adjoint as A
+    from paper_2606_06720_amd import nf as NF
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    return NF, A, T, torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("n,gamma", [((64, 64), 0.75), ((64, 32), 0.5), ((32, 64), 1.0), ((128, 128), 1.2)])
+def test_step_adjoint_matches_oracle(env, n, gamma):
+    NF, A, T, torch = env
+    rng = np.random.default_rng(61)
+    sh = n[::-1]
+    m = rng.uniform(0.2, 1.0, (2,) + sh)
+    r = rng.uniform(0.05, 0.15, sh)
+    S = rng.standard_normal(sh)
+    S -= S.mean()
+    lam = rng.standard_normal((2,) + sh)
+    c2, D2, dt = 30.0, 2e-3, 2e-3
+    p, _ = O.pressure_pcg(m, r, S, None, 1e-13, 4000)
+    lk, dr, dS, mu, _ = O.step_adjoint(m, p, r, S, c2, D2, gamma, dt, lam, rtol=1e-13, max_iter=4000)
+    with NF.Grid(n) as g:
+        lam_k = torch.zeros((2,) + sh, dtype=torch.float64, device="cuda:0")
+        gr = torch.full(sh, 0.5, dtype=torch.float64, device="cuda:0")   # accumulated into
+        gS = torch.zeros(sh, dtype=torch.float64, device="cuda:0")
+        mug = torch.zeros(sh, dtype=torch.float64, device="cuda:0")
+        rc, info = g.step_adjoint(c2, D2, gamma, dt, T(m), T(p), T(r), T(S), T(lam), lam_k, gr, gS, mug,
+                                  rtol=1e-13, max_iter=4000)
+    assert info.converged
+    assert rel(lam_k.cpu().numpy(), lk) <= 1e-9
+    assert rel(gr.cpu().numpy() - 0.5, dr) <= 1e-9
+    assert rel(gS.cpu().numpy(), dS) <= 1e-9
+    assert rel(mug.cpu().numpy(), mu) <= 1e-9
+
+
+def test_checkpointed_gradient_matches_oracle(env):
+    NF, A, T, torch = env
+    w = W.bump_workload(32)
+    prm = (w["c2"], w["D2"], w["gamma"])
+    steps = 7
+    m_tgt = O.run(w["m0"], None, w["r"] * 1.5, 1.2 * w["S"], *prm, w["dt"], max_steps=steps, rtol=1e-13)[0]
+    l_or, gr_or, gS_or = O.run_gradient(w["m0"], w["r"], w["S"], *prm, w["dt"], steps, m_tgt, rtol=1e-13)
+    with NF.Grid(w["n"]) as g:
+        for stride in (1, 3, 7):
+            loss, gr, gS = A.run_gradient(g, prm, w["dt"], steps, T(w["m0"]), T(w["r"]), T(w["S"]), T(m_tgt),
+                                          rtol=1e-13, stride=stride)
+            # the loss is a sum of squared small differences of |m|: its relative
+            # error is the relative error of m over the size of those differences
+            assert abs(loss - l_or) <= 1e-8 * l_or
+            assert rel(gr.cpu().numpy(), gr_or) <= 1e-7
+            assert rel(gS.cpu().numpy(), gS_or) <= 1e-7
+
+
+def test_autograd_function_and_central_differences_1024(env):
+    # the 1024^2 case: gradient of the misfit of the final |m| (target from a
+    # run with r perturbed by a second smooth random field) w.r.t. r and S,
+    # checked against central differences of the GPU forward run along smooth
+    # directions (the FD noise floor is about rtol / h relative to the loss, so
+    # h and the directions are chosen to keep the signal well above it)
+    NF, A, T, torch = env
+    N, steps = 1024, 20
+    w = W.dipole_workload(N, 0.75)
+    f2 = W.smooth_random_field(np.random.default_rng(6), (N, N), 1.0)
+    prm = (w["c2"], w["D2"], w["gamma"])
+    rtol = 1e-13
+    r = T(w["r"])
+    S = T(w["S"])
+    m0 = T(w["m0"])
+    with NF.Grid(w["n"]) as g:
+        m_tgt, _ = A.forward_states(g, prm, w["dt"], steps, m0, T(w["r"] * (1 + 0.5 * f2)), S, rtol, 2000, steps)
+        rr = r.clone().requires_grad_(True)
+        SS = S.clone().requires_grad_(True)
+        mT = A.network_run(rr, SS, g, prm, w["dt"], steps, m0, rtol=rtol)
+        loss = 0.5 * ((torch.sqrt((mT * mT).sum(0)) - torch.sqrt((m_tgt * m_tgt).sum(0))) ** 2).sum()
+        loss.backward()
+        l2, gr2, gS2 = A.run_gradient(g, prm, w["dt"], steps, m0, r, S, m_tgt, rtol=rtol)
+        assert abs(float(loss) - l2) <= 1e-12 * l2
+        assert torch.equal(rr.grad, gr2) and torch.equal(SS.grad, gS2)
+
+        def L(r_, S_):
+            m_T, _ = A.forward_states(g, prm, w["dt"], steps, m0, r_, S_, rtol, 2000, steps)
+            return A.misfit_loss(m_T, m_tgt)[0]
+
+        h = 1e-4
+        for k in range(3):
+            vr = T(W.smooth_random_field(np.random.default_rng(70 + k), (N, N), 1.0))
+            vS = W.smooth_random_field(np.random.default_rng(80 + k), (N, N), 1.0)
+            vS = T(vS - vS.mean())
+            fd_r = (L(r + h * vr, S) - L(r - h * vr, S)) / (2 * h)
+            fd_S = (L(r, S + h * vS) - L(r, S - h * vS)) / (2 * h)
+            ad_r = float((gr2 * vr).sum())
+            ad_S = float((gS2 * vS).sum())
+            assert abs(fd_r - ad_r) <= 1e-3 * abs(ad_r)
+            assert abs(fd_S - ad_S) <= 1e-3 * abs(ad_S)
