@@ -53,7 +53,17 @@ enum {
   NF_ENONFINITE = -6   /* activation produced Inf/NaN: c^2 |grad p|^2 dt too large (Sec. 2.3.1, Remark) */
 };
 
-enum { NF_F64 = 0 };
+/*
+ * Precision of the pressure solve (every other pass is FP64 in both):
+ *   NF_F64          FP64 storage and arithmetic throughout;
+ *   NF_F32_REFINED  iterative refinement: the iterate and the residual
+ *                   Pi S - A p are FP64, each correction is the same PCG run
+ *                   with FP32 transforms, fields and vector updates (FP64 inner
+ *                   products and scalars).  The stopping test is on the FP64
+ *                   residual, so rtol has the same meaning as for NF_F64 and
+ *                   rel_res is the true relative residual.
+ */
+enum { NF_F64 = 0, NF_F32_REFINED = 1 };
 
 enum { NF_STOP_MAX_STEPS = 0, NF_STOP_DM_BELOW_EPS = 1, NF_STOP_ENERGY_INCREASE = 2, NF_STOP_ERROR = 3 };
 
@@ -89,10 +99,11 @@ typedef struct {
  *   ndim    must be 2;
  *   n       grid sizes (Nx, Ny[, unused]), powers of two in [8, 4096];
  *   L       box lengths (Lx, Ly[, unused]), > 0;
- *   dtype   NF_F64;
+ *   dtype   NF_F64 or NF_F32_REFINED;
  *   stream  hipStream_t to enqueue on (NULL = default stream).
- * Allocates the workspace (8 complex half-spectrum fields plus tables) on the
- * current HIP device.  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
+ * Allocates the workspace (8 complex half-spectrum fields plus tables; with
+ * NF_F32_REFINED also 6 single-precision half-spectrum fields and FP32 copies
+ * of m and r) on the current HIP device.  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
  * (*out is then NULL).
  */
 int nf_create_grid(nf_grid **out, int ndim, const int64_t n[3], const double L[3], int dtype, void *stream);
@@ -104,11 +115,21 @@ int nf_destroy_grid(nf_grid *g);
 int nf_set_stream(nf_grid *g, void *stream);
 
 /*
+ * NF_F32_REFINED handles: smallest relative residual reduction asked of one
+ * FP32 correction (default 1e-5; each correction asks for the reduction that
+ * reaches rtol with a margin of 2, but not below this floor).  Must lie in
+ * (0, 0.5); NF_EINVAL otherwise.  No effect on NF_F64 handles.
+ */
+int nf_set_inner_tolerance(nf_grid *g, double floor_rtol);
+
+/*
  * Pressure solve, Sec. 2.4 (eq. p_discrete by CG, warm started from p):
  * solves -div((m m^T + r I) grad p) = S for the minimum-norm p by preconditioned
  * CG with the constant-coefficient preconditioner -div(Kbar grad), Kbar the grid
  * mean of m m^T + r I (Sec. 5 mentions it).  Stops when
- * ||r_k||_2 <= rtol ||Pi S||_2 (recurrence residual) or after max_iter iterations.
+ * ||r_k||_2 <= rtol ||Pi S||_2 (recurrence residual; for NF_F32_REFINED handles
+ * the FP64 residual of the refined iterate, max_iter then bounding the sum of
+ * the FP32 iterations) or after max_iter iterations.
  *   m [2][Ny][Nx], r [Ny][Nx] (r > 0 is the caller's responsibility), S [Ny][Nx];
  *   p [Ny][Nx] in: initial guess, out: the solution (null modes removed);
  *   info may be NULL; if not, the true residual is computed as well.

@@ -35,6 +35,18 @@ struct nf_grid {
   int last_iters = 0;
   std::string err;
   Geo geo;
+  // mixed-precision solve (dtype NF_F32_REFINED): FP32 inner PCG state
+  int dtype = NF_F64;
+  void* tw32 = nullptr;
+  void* x32 = nullptr;  // inner iterate (correction e)
+  void* r32 = nullptr;
+  void* d32 = nullptr;
+  void* q32 = nullptr;
+  void* mix32[2] = {nullptr, nullptr};
+  float* lo = nullptr;  // FP32 copies of m (2n) and r (n)
+  double inner_floor = 1e-5;
+  int last_inner[4] = {0, 0, 0, 0};
+  Geo geo32;
   // optional per-kernel timing of one PCG-loop kernel (events on the handle's stream)
   struct TimedLaunch {
     hipEvent_t a, b;
@@ -49,7 +61,7 @@ struct nf_grid {
 
 namespace {
 
-const char* kVersion = "nf-mi355x 0.1 (gfx950, fp64 2D)";
+const char* kVersion = "nf-mi355x 0.2 (gfx950, 2D, fp64 and fp32-refined pressure solve)";
 
 // message of the last nf_create_grid failure on this thread (nf_last_error(NULL))
 thread_local std::string create_err;
@@ -76,7 +88,8 @@ int ilog2i(int v) {
 
 // exp(-2 pi i u / N) for u < N, from long double arithmetic with the octant
 // symmetries so that each entry is the correctly rounded value in practice.
-void make_twiddles(int N, double* out /* 2N */) {
+template <typename T>
+void make_twiddles(int N, T* out /* 2N */) {
   const long double two_pi = 6.283185307179586476925286766559005768L;
   for (int u = 0; u < N; ++u) {
     // reduce to the first octant: angle = 2 pi u / N = (pi/4) * (8u/N)
@@ -90,8 +103,8 @@ void make_twiddles(int N, double* out /* 2N */) {
       c = cs[oct];
       s = sn[oct];
     }
-    out[2 * u] = (double)c;
-    out[2 * u + 1] = (double)(-s);
+    out[2 * u] = (T)c;
+    out[2 * u + 1] = (T)(-s);
   }
 }
 
@@ -170,45 +183,46 @@ int init_residual(nf_grid* g, const double* m, const double* r) {
   return NF_OK;
 }
 
-// PCG for A x = Pi S (Sec. 2.4) with b_hat already in place.
-int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double* p, double rtol, int max_iter,
-        bool want_true, SolveOut* out) {
-  const Geo& G = g->geo;
+// Iterations it = 0, 1, ... of the PCG loop after its first update, queued in
+// chunks; after each chunk the status is copied to pinned memory, and the host
+// waits on the copy of the PREVIOUS chunk, so the GPU always has queued work.
+// Kernels launched after the stop are no-ops.  f32 selects the FP32 passes of
+// the mixed-precision inner solve.  `expect` sizes the first chunk.  On return
+// the stream is synchronised and *fin holds the final status.
+int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_iter, double tol2, int expect,
+             DevStatus* fin) {
+  const Geo& G = f32 ? g->geo32 : g->geo;
   hipStream_t s = g->stream;
-  LCHK(g, launch_status_reset(G, 0, s));
-  if (src == X_FROM_P) {
-    LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
-    LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
-  } else {
-    if (src == X_ZERO) LCHK(g, launch_zero_spec(G, g->xh, s));
-    LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
-  }
-  int rc = init_residual(g, m, r);
-  if (rc) return rc;
+  const size_t n = (size_t)g->nx * g->ny;
+  int rc = NF_OK;
   g->pool_used = 0;
-  const double tol2 = rtol * rtol;
-  LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
-
-  // Iterations are queued in chunks; after each chunk the status is copied to
-  // pinned memory, and the host waits on the copy of the PREVIOUS chunk, so the
-  // GPU always has queued work.  Kernels launched after the stop are no-ops.
   int it = 0;
   int slot = 0, pending = -1;
   bool first_chunk = true;
   while (it < max_iter) {
-    int n = first_chunk ? (g->last_iters > 6 ? g->last_iters - 4 : 2) : 3;
+    int nk = first_chunk ? (expect > 6 ? expect - 4 : 2) : 3;
     first_chunk = false;
-    if (n > max_iter - it) n = max_iter - it;
-    for (int k = 0; k < n; ++k) {
+    if (nk > max_iter - it) nk = max_iter - it;
+    for (int k = 0; k < nk; ++k) {
       hipEvent_t e0, e1;
       if ((rc = timed_events(g, NF_KERNEL_ROW_FLUX, it, &e0, &e1))) return rc;
-      LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, tol2, s, e0, e1));
+      if (f32)
+        LCHK(g, launch_row_flux32(G, g->mix32[0], g->mix32[1], g->lo, g->lo + 2 * n, it, tol2, s, e0, e1));
+      else
+        LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, it, nullptr, tol2, s, e0, e1));
       if ((rc = timed_events(g, NF_KERNEL_COL_DIV, it, &e0, &e1))) return rc;
-      LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s, e0, e1));
+      if (f32)
+        LCHK(g, launch_col_div32(G, g->mix32[0], g->mix32[1], g->q32, g->d32, g->r32, it, s, e0, e1));
+      else
+        LCHK(g, launch_col_div(G, 0, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, it, 0, s, e0, e1));
       // the update of iteration it+1 does work iff the solver had not stopped before it
       if ((rc = timed_events(g, NF_KERNEL_COL_UPDATE, it, &e0, &e1))) return rc;
-      LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2, s,
-                                e0, e1));
+      if (f32)
+        LCHK(g, launch_col_update32(G, g->x32, g->r32, g->d32, g->q32, g->mix32[0], g->mix32[1], it + 1, max_iter,
+                                    tol2, s, e0, e1));
+      else
+        LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2,
+                                  s, e0, e1));
       ++it;
     }
     HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -220,14 +234,97 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
     pending = slot;
     slot ^= 1;
   }
-  DevStatus fin;
-  rc = read_status(g, &fin);
+  rc = read_status(g, fin);
   if (rc) return rc;
   if (g->timed >= 0) {
     // flux/div of iteration it work iff it < conv_at; the update launched with
     // it+1 works iff it + 1 <= conv_at, i.e. it < conv_at as well
-    if ((rc = timed_collect(g, fin.conv_at))) return rc;
+    if ((rc = timed_collect(g, fin->conv_at))) return rc;
   }
+  return NF_OK;
+}
+
+// Initial iterate x_hat from p (X_FROM_P), kept (X_FROM_XH) or zero, and its
+// gradient in the mixed buffers for the first operator pass.
+int prepare_iterate(nf_grid* g, XSource src, const double* p) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  if (src == X_FROM_P) {
+    LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
+    LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
+  } else {
+    if (src == X_ZERO) LCHK(g, launch_zero_spec(G, g->xh, s));
+    LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+  }
+  return NF_OK;
+}
+
+// Mixed-precision PCG (dtype NF_F32_REFINED): iterative refinement of
+// A x = Pi S with x and the residual b - A x in FP64 and each correction
+// A e = r solved by the same PCG in FP32 storage and arithmetic (FP64 inner
+// products and scalars).  The solve stops on the FP64 residual, so rtol means
+// what it means for the FP64 solver.  max_iter bounds the sum of the inner
+// iterations; a correction that does not lower the FP64 residual ends the
+// solve as not converged.
+int pcg_refined(nf_grid* g, const double* m, const double* r, XSource src, const double* p, double rtol,
+                int max_iter, bool want_true, SolveOut* out) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_status_reset(G, 0, s));
+  int rc = prepare_iterate(g, src, p);
+  if (rc) return rc;
+  const double tol2 = rtol * rtol;
+  int total = 0, outer = 0;
+  double rr_cap = INFINITY;
+  DevStatus fin;
+  for (;;) {
+    // FP64 residual r = b - A x (and, on the first pass, the FP32 copies of m, r)
+    LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, s, nullptr,
+                            nullptr, outer == 0 ? g->lo : nullptr));
+    LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), s));
+    const int budget = max_iter - total;
+    LCHK(g, launch_col_refine_start(g->geo32, g->rh, g->xh, g->x32, g->r32, g->d32, g->mix32[0], g->mix32[1], tol2,
+                                    g->inner_floor, budget, rr_cap, s));
+    const int slot = outer < 3 ? outer : 3;
+    rc = pcg_loop(g, true, m, r, budget > 0 ? budget : 0, 1.0, g->last_inner[slot], &fin);
+    if (rc) return rc;
+    if (fin.outer_done) break;
+    total += fin.iters;
+    if (fin.iters > 0) g->last_inner[slot] = fin.iters;
+    if (fin.flags & FLAG_NONFINITE) break;
+    rr_cap = fin.orr;
+    // x += ||r|| e and the gradient of the new x for the next residual
+    LCHK(g, launch_col_refine_acc(G, g->xh, g->x32, g->mix[0], g->mix[1], s));
+    ++outer;
+  }
+  out->iters = total;
+  out->converged = fin.outer_done ? fin.converged : 0;
+  out->flags = fin.flags;
+  out->sticky = fin.sticky;
+  const double rrf = fin.outer_done ? fin.orr : fin.rr[0];
+  const double bbf = fin.outer_done ? fin.obb : fin.bb;
+  out->rel_res = bbf > 0.0 ? std::sqrt(rrf > 0.0 ? rrf : 0.0) / std::sqrt(bbf) : 0.0;
+  // the stopping test is already on the FP64 residual of the returned iterate
+  out->true_rel_res = (want_true && fin.outer_done && !(fin.flags & FLAG_INCOMPAT)) ? out->rel_res : -1.0;
+  return NF_OK;
+}
+
+// PCG for A x = Pi S (Sec. 2.4) with b_hat already in place.
+int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double* p, double rtol, int max_iter,
+        bool want_true, SolveOut* out) {
+  if (g->dtype == NF_F32_REFINED) return pcg_refined(g, m, r, src, p, rtol, max_iter, want_true, out);
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch_status_reset(G, 0, s));
+  int rc = prepare_iterate(g, src, p);
+  if (rc) return rc;
+  rc = init_residual(g, m, r);
+  if (rc) return rc;
+  const double tol2 = rtol * rtol;
+  LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
+  DevStatus fin;
+  rc = pcg_loop(g, false, m, r, max_iter, tol2, g->last_iters, &fin);
+  if (rc) return rc;
   if (!fin.converged && fin.conv_at == max_iter && max_iter > 0 && !(fin.flags & (FLAG_NONFINITE | FLAG_INCOMPAT))) {
     // stopped by max_iter: take the stopping test on the final residual here
     LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, col_nwg(G), 11, s));
@@ -337,7 +434,7 @@ int nf_set_stream(nf_grid* g, void* stream) {
 int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3], int dtype, void* stream) {
   if (!out) return NF_EINVAL;
   *out = nullptr;
-  if (ndim != 2 || !n || !L || dtype != NF_F64) return NF_EINVAL;
+  if (ndim != 2 || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) return NF_EINVAL;
   if (!is_pow2_in_range(n[0]) || !is_pow2_in_range(n[1])) return NF_EINVAL;
   if (!(L[0] > 0.0) || !(L[1] > 0.0)) return NF_EINVAL;
   nf_grid* g = new nf_grid();
@@ -347,6 +444,7 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   g->lx = L[0];
   g->ly = L[1];
   g->stream = (hipStream_t)stream;
+  g->dtype = dtype;
   int rc = NF_OK;
   create_err.clear();
   hipError_t herr = hipSuccess;
@@ -380,6 +478,18 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   CREATE_CHK(hipMemset(g->part, 0, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_EDEVICE);
   CREATE_CHK(hipMemset(g->st, 0, sizeof(DevStatus)), NF_EDEVICE);
   CREATE_CHK(hipMemset(g->xh, 0, spec_bytes), NF_EDEVICE);
+  if (dtype == NF_F32_REFINED) {
+    const size_t spec32 = (size_t)g->h * g->ny * 2 * sizeof(float);
+    void** b32[] = {&g->x32, &g->r32, &g->d32, &g->q32, &g->mix32[0], &g->mix32[1]};
+    for (void** b : b32) CREATE_CHK(hipMalloc(b, spec32), NF_ENOMEM);
+    CREATE_CHK(hipMalloc((void**)&g->lo, 3 * (size_t)g->nx * g->ny * sizeof(float)), NF_ENOMEM);
+    CREATE_CHK(hipMalloc(&g->tw32, (size_t)twn * 2 * sizeof(float)), NF_ENOMEM);
+    float* h = new float[2 * (size_t)twn];
+    make_twiddles(twn, h);
+    herr = hipMemcpy(g->tw32, h, (size_t)twn * 2 * sizeof(float), hipMemcpyHostToDevice);
+    delete[] h;
+    if (herr != hipSuccess) return bail(NF_EDEVICE, "hipMemcpy(twiddles32)");
+  }
 #undef CREATE_CHK
   Geo& G = g->geo;
   G.nx = g->nx;
@@ -392,8 +502,17 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.tw = g->tw;
   G.st = g->st;
   G.part = g->part;
+  g->geo32 = G;
+  g->geo32.tw = g->tw32;
   *out = g;
   return rc;
+}
+
+int nf_set_inner_tolerance(nf_grid* g, double floor_rtol) {
+  if (!g) return NF_EINVAL;
+  if (!(floor_rtol > 0.0 && floor_rtol < 0.5)) return fail(g, NF_EINVAL, "inner tolerance must lie in (0, 0.5)");
+  g->inner_floor = floor_rtol;
+  return NF_OK;
 }
 
 int nf_time_kernel(nf_grid* g, int which) {
@@ -416,7 +535,8 @@ int nf_destroy_grid(nf_grid* g) {
   if (!g) return NF_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
-  void* bufs[] = {g->xh, g->rh, g->dh, g->qh, g->bh, g->mix[0], g->mix[1], g->mix[2], g->tw, g->part, g->st};
+  void* bufs[] = {g->xh,  g->rh,  g->dh,  g->qh,  g->bh,       g->mix[0],   g->mix[1], g->mix[2], g->tw,
+                  g->part, g->st, g->x32, g->r32, g->d32, g->q32, g->mix32[0], g->mix32[1], g->lo,    g->tw32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (g->hst) (void)hipHostFree(g->hst);

@@ -15,13 +15,16 @@ struct DevStatus {
   double rho[2];    // <r, M^-1 r> by iteration parity (expanded value used for beta)
   double rr[2];     // rr[0]: ||r||^2 of the residual at which the solve stopped
   double rr0;       // initial ||r||^2
+  double orr, obb;  // mixed-precision solve: FP64 ||r||^2 and ||b||^2 at the last correction start
+  double rscale;    // mixed-precision solve: ||r|| scaling the FP32 correction
   double out[16];   // results of the final reductions (energy terms, dm, ...)
   int conv_at;      // iteration at which PCG stopped (converged or max_iter); INT_MAX while running
   int converged;    // 1 if the stop was convergence
   int iters;        // PCG iterations done
   int flags;        // FLAG_* bits of the current PCG solve
   int sticky;       // FLAG_* bits raised since the last full reset (split update)
-  int pad[3];
+  int outer_done;   // mixed-precision solve: 1 once the FP64 residual test has ended it
+  int pad[2];
 };
 
 enum { FLAG_NONFINITE = 1, FLAG_INCOMPAT = 2 };
@@ -47,7 +50,7 @@ struct Geo {
   int nx, ny, h, twlog;
   double lx, ly;
   double inv_n;
-  const void* tw;     // cx<double>[2^twlog], tw[u] = exp(-2 pi i u / 2^twlog)
+  const void* tw;     // cx<double>[2^twlog] (cx<float> for the FP32 passes), tw[u] = exp(-2 pi i u / 2^twlog)
   DevStatus* st;
   double* part;       // NSLOTS * SLOT_K * MAX_WG doubles
 };
@@ -68,9 +71,10 @@ int col_nwg(const Geo& g);
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out_mixed, double* schk_slot, hipStream_t s);
 hipError_t launch_row_c2r(const Geo& g, const void* in_mixed, double* f, hipStream_t s);
 // e0/e1: optional start/stop events timestamped by the dispatch (nullptr = none)
+// lo: optional FP32 copies of m then r (3n floats), written when non-null
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
                            double* kbar_slot, double tol2, hipStream_t s, hipEvent_t e0 = nullptr,
-                           hipEvent_t e1 = nullptr);
+                           hipEvent_t e1 = nullptr, float* lo = nullptr);
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax_gamma1, hipStream_t s);
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dm_slot,
@@ -87,6 +91,20 @@ hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy
 hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
                              void* Gy, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);
+// FP32 instantiations of the PCG-loop passes (g.tw points at the FP32 table;
+// m32/r32 are the FP32 copies written by launch_row_flux)
+hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32, const float* r32, int it,
+                             double tol2, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_col_div32(const Geo& g, const void* Fx, const void* Fy, void* qh, const void* dh, void* rh, int it,
+                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const void* qh, void* Gx, void* Gy, int it,
+                               int max_iter, double tol2, hipStream_t s, hipEvent_t e0 = nullptr,
+                               hipEvent_t e1 = nullptr);
+// mixed-precision correction start / accumulation (g32: FP32 twiddles)
+hipError_t launch_col_refine_start(const Geo& g32, const void* r64, void* x64, void* x32, void* r32, void* d32,
+                                   void* Gx32, void* Gy32, double tol2, double floor_in, int budget, double rr_cap,
+                                   hipStream_t s);
+hipError_t launch_col_refine_acc(const Geo& g, void* x64, const void* x32, void* Gx, void* Gy, hipStream_t s);
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* egm_slot, hipStream_t s);
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* egm_slot, hipStream_t s);
 // adjoint passes

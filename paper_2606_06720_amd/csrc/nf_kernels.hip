@@ -90,17 +90,45 @@ __device__ __forceinline__ int xcd_block() {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
-__device__ __forceinline__ const cd* pick(int f, const cd* a, const cd* b, const cd* c) {
+template <typename V>
+__device__ __forceinline__ const V* pick(int f, const V* a, const V* b, const V* c) {
   return f == 0 ? a : (f == 1 ? b : c);
 }
-__device__ __forceinline__ cd* pickw(int f, cd* a, cd* b, cd* c) { return f == 0 ? a : (f == 1 ? b : c); }
+template <typename V>
+__device__ __forceinline__ V* pickw(int f, V* a, V* b, V* c) { return f == 0 ? a : (f == 1 ? b : c); }
+// non-deduced context: optional pointer arguments may be passed as nullptr
+template <typename V>
+struct same_t {
+  using type = V;
+};
+template <typename V>
+using same = typename same_t<V>::type;
+
+template <typename T>
+struct vec2;
+template <>
+struct vec2<double> {
+  using type = double2;
+};
+template <>
+struct vec2<float> {
+  using type = float2;
+};
+
+template <typename V>
+__device__ __forceinline__ V vzero() {
+  V v;
+  v.x = 0;
+  v.y = 0;
+  return v;
+}
 
 // ---------------------------------------------------------------- row images
 // "T" image: element e -> field e / RH, row (e % RH) % R, column (e % RH) / R;
 // coalesced over the column-major mixed layout M[kx][y].  LDS line of (field,
 // row) is field * R + row.
-template <int NX, int NF>
-__device__ __forceinline__ void rowT_gload(cd (&v)[(RowCfg<NX, NF>::ET)], const cd* s0, const cd* s1, const cd* s2,
+template <int NX, int NF, typename V>
+__device__ __forceinline__ void rowT_gload(V (&v)[(RowCfg<NX, NF>::ET)], const V* s0, const same<V>* s1, const same<V>* s2,
                                            int ny, int y0, int nrow) {
   using C = RowCfg<NX, NF>;
 #pragma unroll
@@ -108,11 +136,11 @@ __device__ __forceinline__ void rowT_gload(cd (&v)[(RowCfg<NX, NF>::ET)], const 
     const int e = threadIdx.x + i * C::NT;
     const int f = e / C::RH, ee = e % C::RH;
     const int rr = ee % C::R, kx = ee / C::R;
-    v[i] = (e < NF * C::RH && rr < nrow) ? pick(f, s0, s1, s2)[(size_t)kx * ny + y0 + rr] : mk<double>(0.0, 0.0);
+    v[i] = (e < NF * C::RH && rr < nrow) ? pick<V>(f, s0, s1, s2)[(size_t)kx * ny + y0 + rr] : vzero<V>();
   }
 }
-template <int NX, int NF>
-__device__ __forceinline__ void rowT_put(cd* buf, const cd (&v)[(RowCfg<NX, NF>::ET)]) {
+template <int NX, int NF, typename V>
+__device__ __forceinline__ void rowT_put(V* buf, const V (&v)[(RowCfg<NX, NF>::ET)]) {
   using C = RowCfg<NX, NF>;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
@@ -122,43 +150,42 @@ __device__ __forceinline__ void rowT_put(cd* buf, const cd (&v)[(RowCfg<NX, NF>:
   }
 }
 // store the first NFS fields of the block back to the mixed layout
-template <int NX, int NF, int NFS>
-__device__ __forceinline__ void rowT_store(const cd* buf, cd* d0, cd* d1, cd* d2, int ny, int y0, int nrow) {
+template <int NX, int NF, int NFS, typename V>
+__device__ __forceinline__ void rowT_store(const V* buf, same<V>* d0, same<V>* d1, same<V>* d2, int ny, int y0, int nrow) {
   using C = RowCfg<NX, NF>;
   for (int e = threadIdx.x; e < NFS * C::RH; e += C::NT) {
     const int f = e / C::RH, ee = e % C::RH;
     const int rr = ee % C::R, kx = ee / C::R;
-    if (rr < nrow) pickw(f, d0, d1, d2)[(size_t)kx * ny + y0 + rr] = buf[(f * C::R + rr) * C::LS + kx];
+    if (rr < nrow) pickw<V>(f, d0, d1, d2)[(size_t)kx * ny + y0 + rr] = buf[(f * C::R + rr) * C::LS + kx];
   }
 }
 // "P" image of a physical field: element p -> row p / H, pair p % H (the
 // grid points 2j, 2j+1 of the row), coalesced over the row-major layout
-template <int NX, int NF>
-__device__ __forceinline__ void rowP_gload(double2 (&v)[(RowCfg<NX, NF>::EP)], const double* __restrict__ f, int y0,
-                                           int nrow) {
+template <int NX, int NF, typename P, typename S>
+__device__ __forceinline__ void rowP_gload(P (&v)[(RowCfg<NX, NF>::EP)], const S* __restrict__ f, int y0, int nrow) {
   using C = RowCfg<NX, NF>;
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
     const int rr = p / C::H, j = p % C::H;
-    v[i] = (p < C::RH && rr < nrow) ? *(const double2*)(f + (size_t)(y0 + rr) * NX + 2 * j) : make_double2(0.0, 0.0);
+    v[i] = (p < C::RH && rr < nrow) ? *(const P*)(f + (size_t)(y0 + rr) * NX + 2 * j) : vzero<P>();
   }
 }
 
 // ---------------------------------------------------------------- column images
-template <int NY, int NF, int NFL>
-__device__ __forceinline__ void colT_gload(cd (&v)[(ColCfg<NY, NF>::ET)], const cd* s0, const cd* s1, int kx0, int h) {
+template <int NY, int NF, int NFL, typename V>
+__device__ __forceinline__ void colT_gload(V (&v)[(ColCfg<NY, NF>::ET)], const V* s0, const same<V>* s1, int kx0, int h) {
   using C = ColCfg<NY, NF>;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
     const int f = e / C::CN, ee = e % C::CN;
     const int c = ee / NY, ky = ee % NY;
-    v[i] = (e < NFL * C::CN && kx0 + c < h) ? (f == 0 ? s0 : s1)[(size_t)(kx0 + c) * NY + ky] : mk<double>(0.0, 0.0);
+    v[i] = (e < NFL * C::CN && kx0 + c < h) ? (f == 0 ? s0 : s1)[(size_t)(kx0 + c) * NY + ky] : vzero<V>();
   }
 }
-template <int NY, int NF, int NFL>
-__device__ __forceinline__ void colT_put(cd* buf, const cd (&v)[(ColCfg<NY, NF>::ET)]) {
+template <int NY, int NF, int NFL, typename V>
+__device__ __forceinline__ void colT_put(V* buf, const V (&v)[(ColCfg<NY, NF>::ET)]) {
   using C = ColCfg<NY, NF>;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
@@ -167,8 +194,8 @@ __device__ __forceinline__ void colT_put(cd* buf, const cd (&v)[(ColCfg<NY, NF>:
     if (e < NFL * C::CN) buf[(f * C::C + ee / NY) * C::LS + ee % NY] = v[i];
   }
 }
-template <int NY, int NF, int NFS>
-__device__ __forceinline__ void colT_store(const cd* buf, cd* d0, cd* d1, int kx0, int h) {
+template <int NY, int NF, int NFS, typename V>
+__device__ __forceinline__ void colT_store(const V* buf, same<V>* d0, same<V>* d1, int kx0, int h) {
   using C = ColCfg<NY, NF>;
   for (int e = threadIdx.x; e < NFS * C::CN; e += C::NT) {
     const int f = e / C::CN, ee = e % C::CN;
@@ -177,14 +204,14 @@ __device__ __forceinline__ void colT_store(const cd* buf, cd* d0, cd* d1, int kx
   }
 }
 // pointwise image of one field: p -> column p / NY, row p % NY
-template <int NY, int NF>
-__device__ __forceinline__ void colP_gload(cd (&v)[(ColCfg<NY, NF>::EP)], const cd* __restrict__ src, int kx0, int h) {
+template <int NY, int NF, typename V>
+__device__ __forceinline__ void colP_gload(V (&v)[(ColCfg<NY, NF>::EP)], const V* __restrict__ src, int kx0, int h) {
   using C = ColCfg<NY, NF>;
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
     const int c = p / NY, ky = p % NY;
-    v[i] = (p < C::CN && kx0 + c < h) ? src[(size_t)(kx0 + c) * NY + ky] : mk<double>(0.0, 0.0);
+    v[i] = (p < C::CN && kx0 + c < h) ? src[(size_t)(kx0 + c) * NY + ky] : vzero<V>();
   }
 }
 
@@ -204,6 +231,8 @@ __global__ void k_status_reset(DevStatus* st, int full) {
     st->rho[0] = st->rho[1] = 0.0;
     st->rr[0] = st->rr[1] = 0.0;
     st->rr0 = 0.0;
+    st->orr = st->obb = st->rscale = 0.0;
+    st->outer_done = 0;
     for (int i = 0; i < 16; ++i) st->out[i] = 0.0;
     st->conv_at = INT_MAX;
     st->converged = 0;
@@ -287,25 +316,30 @@ __global__ void __launch_bounds__(TPF) k_row_c2r(Geo g, const cd* __restrict__ i
 // Operator middle: gradient fields (mixed) -> physical g -> flux K g -> mixed,
 // both components in one batched transform each way.  In place: G0/G1 hold
 // grad_x/grad_y on entry and F_x/F_y on exit.  Optional partials: sum mx^2,
-// mx my, my^2, r (the preconditioner's Kbar).
+// mx my, my^2, r (the preconditioner's Kbar).  Optional lo: FP32 copies of
+// m (2n values) followed by r (n values) for the single-precision inner solve.
 // In the PCG loop (it >= 1) the pass first takes the stopping decision for the
 // residual r_it left by k_col_update: ||r_it||^2 (reduced directly from that
-// kernel's partials) <= tol2 ||b||^2 ends the solve at iteration it.
-template <int NX>
-__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cd* G0, cd* G1, const double* __restrict__ m,
-                                                  const double* __restrict__ r, int it, double* kslot, int nwg_col,
-                                                  double tol2) {
+// kernel's partials) <= tol2 * status.bb ends the solve at iteration it.
+// T is the arithmetic and storage type of the transforms and fields; the
+// reductions are FP64 in both instantiations.
+template <int NX, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
+                                                  const T* __restrict__ r, int it, double* kslot, int nwg_col,
+                                                  double tol2, float* lo) {
   using C = RowCfg<NX, 2>;
+  using V = cx<T>;
+  using P = typename vec2<T>::type;
   if (it >= 0 && g.st->conv_at <= it) return;
-  __shared__ cd buf[C::NB * C::LS];
+  __shared__ V buf[C::NB * C::LS];
   __shared__ double red[4 * (C::NT / 64)];
-  const cd* tw = (const cd*)g.tw;
+  const V* tw = (const V*)g.tw;
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
-  cd tv[C::ET];
+  V tv[C::ET];
   rowT_gload<NX, 2>(tv, G0, G1, nullptr, g.ny, y0, nrow);
-  double2 mx[C::EP], my[C::EP], rv[C::EP];
+  P mx[C::EP], my[C::EP], rv[C::EP];
   rowP_gload<NX, 2>(mx, m, y0, nrow);
   rowP_gload<NX, 2>(my, m + n, y0, nrow);
   rowP_gload<NX, 2>(rv, r, y0, nrow);
@@ -324,35 +358,48 @@ __global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cd* G0, cd* G1, con
       return;
     }
   }
+  if (lo) {
+#pragma unroll
+    for (int i = 0; i < C::EP; ++i) {
+      const int p = threadIdx.x + i * C::NT;
+      const int rr = p / C::H, j = p % C::H;
+      if (p < C::RH && rr < nrow) {
+        const size_t o = (size_t)(y0 + rr) * NX + 2 * j;
+        *(float2*)(lo + o) = make_float2((float)mx[i].x, (float)mx[i].y);
+        *(float2*)(lo + n + o) = make_float2((float)my[i].x, (float)my[i].y);
+        *(float2*)(lo + 2 * n + o) = make_float2((float)rv[i].x, (float)rv[i].y);
+      }
+    }
+  }
   rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double ks[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
     const int rr = p / C::H, j = p % C::H;
     if (p < C::RH && rr < nrow) {
-      cd* px = buf + rr * C::LS + j;
-      cd* py = buf + (C::R + rr) * C::LS + j;
-      const cd gx = *px, gy = *py;
+      V* px = buf + rr * C::LS + j;
+      V* py = buf + (C::R + rr) * C::LS + j;
+      const V gx = *px, gy = *py;
       // K g = (m.g) m + r g at the two grid points packed in this element
-      const double a0 = mx[i].x * gx.x + my[i].x * gy.x;
-      const double a1 = mx[i].y * gx.y + my[i].y * gy.y;
-      *px = mk<double>(fma(a0, mx[i].x, rv[i].x * gx.x), fma(a1, mx[i].y, rv[i].y * gx.y));
-      *py = mk<double>(fma(a0, my[i].x, rv[i].x * gy.x), fma(a1, my[i].y, rv[i].y * gy.y));
+      const T a0 = mx[i].x * gx.x + my[i].x * gy.x;
+      const T a1 = mx[i].y * gx.y + my[i].y * gy.y;
+      *px = mk<T>(fma(a0, mx[i].x, rv[i].x * gx.x), fma(a1, mx[i].y, rv[i].y * gx.y));
+      *py = mk<T>(fma(a0, my[i].x, rv[i].x * gy.x), fma(a1, my[i].y, rv[i].y * gy.y));
       if (kslot) {
-        ks[0] += mx[i].x * mx[i].x + mx[i].y * mx[i].y;
-        ks[1] += mx[i].x * my[i].x + mx[i].y * my[i].y;
-        ks[2] += my[i].x * my[i].x + my[i].y * my[i].y;
-        ks[3] += rv[i].x + rv[i].y;
+        ks[0] += (double)mx[i].x * mx[i].x + (double)mx[i].y * mx[i].y;
+        ks[1] += (double)mx[i].x * my[i].x + (double)mx[i].y * my[i].y;
+        ks[2] += (double)my[i].x * my[i].x + (double)my[i].y * my[i].y;
+        ks[3] += (double)rv[i].x + (double)rv[i].y;
       }
     }
   }
   __syncthreads();
-  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   rowT_store<NX, 2, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
@@ -701,12 +748,12 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj2(Geo g, const cd* __restric
 // ================================================================ column kernels
 // Write the gradient multipliers i xi_c f_hat / n of one spectral value into
 // the two gradient lines of the column block.
-template <int NY, int NF>
-__device__ __forceinline__ void put_grad(cd* buf, int c, int ky, int kx, const cd v, const Geo& g) {
+template <int NY, int NF, typename T>
+__device__ __forceinline__ void put_grad(cx<T>* buf, int c, int ky, int kx, const cx<T> v, const Geo& g) {
   using C = ColCfg<NY, NF>;
-  const double sx = xi_col(kx, g.lx) * g.inv_n, sy = xi_tilde(ky, NY, g.ly) * g.inv_n;
-  buf[c * C::LS + ky] = mk<double>(-sx * v.y, sx * v.x);
-  buf[(C::C + c) * C::LS + ky] = mk<double>(-sy * v.y, sy * v.x);
+  const T sx = (T)(xi_col(kx, g.lx) * g.inv_n), sy = (T)(xi_tilde(ky, NY, g.ly) * g.inv_n);
+  buf[c * C::LS + ky] = mk<T>(-sx * v.y, sx * v.x);
+  buf[(C::C + c) * C::LS + ky] = mk<T>(-sy * v.y, sy * v.x);
 }
 
 // mixed -> spectral (null modes zeroed unless bit 1 of mode is set); with bit 0
@@ -780,18 +827,22 @@ __device__ __forceinline__ double precond_symbol_inv(const double* K, double xx,
 //       also reduces the Kbar and compatibility partials of the row pass.
 // else: q_hat stored, partials <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>,
 //       <r,M^-1 r>, <r,r>.
-template <int NY, bool INIT>
-__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cd* __restrict__ Fx, const cd* __restrict__ Fy,
-                                                 cd* __restrict__ qh, const cd* __restrict__ dh, cd* rh,
-                                                 const cd* __restrict__ bh, int it, int nwg_row) {
+// INIT exists for T = double only (the residual of the refinement is FP64).
+template <int NY, bool INIT, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
+                                                 const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
+                                                 const cx<T>* __restrict__ dh, cx<T>* rh,
+                                                 const cx<T>* __restrict__ bh, int it, int nwg_row) {
   using C = ColCfg<NY, 2>;
+  using V = cx<T>;
+  static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
   if (!INIT && g.st->conv_at <= it) return;
-  __shared__ cd buf[C::NB * C::LS];
+  __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   __shared__ double Ks[4];
-  const cd* tw = (const cd*)g.tw;
+  const V* tw = (const V*)g.tw;
   const int kx0 = blockIdx.x * C::C;
-  cd tv[C::ET], av[C::EP], bv[C::EP];
+  V tv[C::ET], av[C::EP], bv[C::EP];
   colT_gload<NY, 2, 2>(tv, Fx, Fy, kx0, g.h);
   if (INIT) {
     colP_gload<NY, 2>(av, bh, kx0, g.h);
@@ -818,7 +869,7 @@ __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cd* __restrict
   }
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -826,34 +877,35 @@ __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cd* __restrict
     const int c = p / NY, ky = p % NY;
     const int kx = kx0 + c;
     if (p < C::CN && kx < g.h) {
-      const cd fx = buf[c * C::LS + ky], fy = buf[(C::C + c) * C::LS + ky];
+      const V fx = buf[c * C::LS + ky], fy = buf[(C::C + c) * C::LS + ky];
       const double xx = xi_col(kx, g.lx);
       const double yy = xi_tilde(ky, NY, g.ly);
       // q = -i (xx Fx + yy Fy)
-      const double ax = xx * fx.x + yy * fy.x, ay = xx * fx.y + yy * fy.y;
-      const cd q = mk<double>(ay, -ax);
+      const T ax = (T)xx * fx.x + (T)yy * fy.x, ay = (T)xx * fx.y + (T)yy * fy.y;
+      const V q = mk<T>(ay, -ax);
       const double w = kx == 0 ? 1.0 : 2.0;
       const double sig = precond_symbol_inv(Ks, xx, yy);
       const size_t idx = (size_t)kx * NY + ky;
+      const double qx = q.x, qy = q.y;
       if (INIT) {
-        const cd b = av[i];
-        const cd rn = sub(b, q);
+        const V b = av[i];
+        const V rn = sub(b, q);
         rh[idx] = rn;
-        const double rr = rn.x * rn.x + rn.y * rn.y;
+        const double rr = (double)rn.x * rn.x + (double)rn.y * rn.y;
         s[0] += w * sig * rr;
         s[1] += w * rr;
-        s[2] += w * (b.x * b.x + b.y * b.y);
+        s[2] += w * ((double)b.x * b.x + (double)b.y * b.y);
       } else {
         qh[idx] = q;
-        const cd d = av[i], rv = bv[i];
-        const double qq = q.x * q.x + q.y * q.y;
-        const double rq = rv.x * q.x + rv.y * q.y;
-        s[0] += w * (d.x * q.x + d.y * q.y);
+        const double dx = av[i].x, dy = av[i].y, rx = bv[i].x, ry = bv[i].y;
+        const double qq = qx * qx + qy * qy;
+        const double rq = rx * qx + ry * qy;
+        s[0] += w * (dx * qx + dy * qy);
         s[1] += w * sig * rq;
         s[2] += w * sig * qq;
         s[3] += w * rq;
         s[4] += w * qq;
-        const double r2 = rv.x * rv.x + rv.y * rv.y;
+        const double r2 = rx * rx + ry * ry;
         s[5] += w * sig * r2;
         s[6] += w * r2;
       }
@@ -869,23 +921,26 @@ __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cd* __restrict
 // around the directly computed old value; it is used for beta only), then
 // x += alpha d, r -= alpha q, d = M^-1 r + beta d.  The stopping test on the
 // new residual is taken by the next pass from its direct norm (SLOT_RR).
-template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cd* xh, cd* rh, cd* dh,
-                                                    const cd* __restrict__ qh, cd* Gx, cd* Gy, int it,
+// The scalars are FP64; the vector updates run in T.  `first` exists for
+// T = double only (the single-precision solve starts in k_col_refine_start).
+template <int NY, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
+                                                    const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
   using C = ColCfg<NY, 2>;
+  using V = cx<T>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
-  __shared__ cd buf[C::NB * C::LS];
+  __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
-  const cd* tw = (const cd*)g.tw;
+  const V* tw = (const V*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   const bool lead = (blockIdx.x == 0 && threadIdx.x == 0);
   double K[4];
   for (int i = 0; i < 4; ++i) K[i] = st->kbar[i];
   // vectors of the block, loaded before the scalar reduction so that both
   // latencies overlap
-  cd xv[C::EP], rv0[C::EP], dv0[C::EP], qv[C::EP];
+  V xv[C::EP], rv0[C::EP], dv0[C::EP], qv[C::EP];
   colP_gload<NY, 2>(rv0, rh, kx0, g.h);
   if (!first) {
     colP_gload<NY, 2>(xv, xh, kx0, g.h);
@@ -938,29 +993,30 @@ __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cd* xh
       }
     }
   }
+  const T a = (T)alpha, bt = (T)beta;
   double rrp[1] = {0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
     const int c = p / NY, ky = p % NY;
     const int kx = kx0 + c;
-    cd d = mk<double>(0.0, 0.0);
+    V d = vzero<V>();
     if (p < C::CN && kx < g.h) {
       const size_t idx = (size_t)kx * NY + ky;
       if (zero_x) {
-        xh[idx] = mk<double>(0.0, 0.0);
+        xh[idx] = vzero<V>();
       } else {
-        cd rv = rv0[i];
+        V rv = rv0[i];
         if (!first) {
           d = dv0[i];
-          xh[idx] = add(xv[i], scl(d, alpha));
-          rv = sub(rv, scl(qv[i], alpha));
+          xh[idx] = add(xv[i], scl(d, a));
+          rv = sub(rv, scl(qv[i], a));
           rh[idx] = rv;
-          rrp[0] += (kx == 0 ? 1.0 : 2.0) * (rv.x * rv.x + rv.y * rv.y);
+          rrp[0] += (kx == 0 ? 1.0 : 2.0) * ((double)rv.x * rv.x + (double)rv.y * rv.y);
         }
         if (!stop) {
-          const double sig = precond_symbol_inv(K, xi_col(kx, g.lx), xi_tilde(ky, NY, g.ly));
-          d = add(scl(rv, sig), scl(d, beta));
+          const T sig = (T)precond_symbol_inv(K, xi_col(kx, g.lx), xi_tilde(ky, NY, g.ly));
+          d = add(scl(rv, sig), scl(d, bt));
           dh[idx] = d;
         }
       }
@@ -972,6 +1028,135 @@ __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cd* xh
     write_partials<C::NT>(slot_ptr(g.part, SLOT_RR), rrp, 1);
   }
   if (stop) return;
+  __syncthreads();
+  lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+}
+
+// Start of one correction of the mixed-precision solve (iterative refinement
+// of A x = b: the inner solve A e = r runs in FP32, x and the residual
+// r = b - A x in FP64).  Reads the FP64 residual partials <r,M^-1 r>, <r,r>,
+// <b,b> left by the FP64 operator pass.  If ||r||^2 <= tol2 ||b||^2 (or b = 0,
+// or S is incompatible, or the values are not finite) the solve is over: the
+// status records the outcome and every later inner launch is a no-op.
+// Otherwise the inner right-hand side is r / ||r|| in FP32, the inner
+// iterate starts at 0, its first direction is M^-1 r with the gradient of it
+// in the FP32 mixed buffers, and the inner stopping threshold (a relative
+// residual of tol_in on the unit right-hand side, kept in status.bb for the
+// passes' test with tol2 = 1) asks for the reduction that reaches tol2 with a
+// margin of 2, but no less than `floor_in`.  A residual no smaller than
+// rr_cap (the previous correction's) means the refinement has stalled: the
+// solve ends unconverged, as it does when the iteration budget is spent.
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
+                                                          cx<float>* x32, cx<float>* r32, cx<float>* d32,
+                                                          cx<float>* Gx, cx<float>* Gy, double tol2,
+                                                          double floor_in, int budget, double rr_cap, int nwg_col) {
+  using C = ColCfg<NY, 2>;
+  using V = cx<float>;
+  DevStatus* st = g.st;
+  __shared__ V buf[C::NB * C::LS];
+  __shared__ double red[3 * (C::NT / 64)];
+  const V* tw = (const V*)g.tw;
+  const int kx0 = blockIdx.x * C::C;
+  const bool lead = (blockIdx.x == 0 && threadIdx.x == 0);
+  double K[4];
+  for (int i = 0; i < 4; ++i) K[i] = st->kbar[i];
+  cd rv[C::EP];
+  colP_gload<NY, 2>(rv, r64, kx0, g.h);
+  double s[3];
+  sum_partials<C::NT, 3>(slot_ptr(g.part, SLOT_P3INIT), nwg_col, MAX_WG, s, red);
+  const double rho = s[0], rr = s[1], bb = s[2];
+  const bool incompat = (st->flags & FLAG_INCOMPAT) != 0;
+  const bool bad = !isfinite(rr) || !isfinite(bb);
+  const bool zero_b = !bad && bb == 0.0;
+  const bool conv = !bad && (incompat || zero_b || rr <= tol2 * bb);
+  if (conv || bad || budget <= 0 || rr >= rr_cap) {
+    if (lead) {
+      st->rr[0] = zero_b ? 0.0 : rr;
+      st->bb = bb;
+      st->orr = zero_b ? 0.0 : rr;
+      st->obb = bb;
+      if (bad) st->flags |= FLAG_NONFINITE;
+      st->conv_at = 0;
+      st->converged = conv ? 1 : 0;
+      st->iters = 0;
+      st->outer_done = 1;
+    }
+    if (zero_b) {
+#pragma unroll
+      for (int i = 0; i < C::EP; ++i) {
+        const int p = threadIdx.x + i * C::NT;
+        const int kx = kx0 + p / NY;
+        if (p < C::CN && kx < g.h) x64[(size_t)kx * NY + p % NY] = mk<double>(0.0, 0.0);
+      }
+    }
+    return;
+  }
+  const double scale = 1.0 / sqrt(rr);
+  double tin = 0.5 * sqrt(tol2 * bb / rr);
+  tin = tin < floor_in ? floor_in : (tin > 0.5 ? 0.5 : tin);
+  if (lead) {
+    st->orr = rr;
+    st->obb = bb;
+    st->rscale = sqrt(rr);
+    st->bb = tin * tin;
+    st->rho[0] = rho * scale * scale;
+    st->rr[0] = 1.0;
+    st->rr0 = 1.0;
+    st->iters = 0;
+    st->converged = 0;
+    st->outer_done = 0;
+    st->conv_at = INT_MAX;
+  }
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
+    const int kx = kx0 + c;
+    V d = vzero<V>();
+    if (p < C::CN && kx < g.h) {
+      const size_t idx = (size_t)kx * NY + ky;
+      const double sig = precond_symbol_inv(K, xi_col(kx, g.lx), xi_tilde(ky, NY, g.ly));
+      const double ux = rv[i].x * scale, uy = rv[i].y * scale;
+      r32[idx] = mk<float>((float)ux, (float)uy);
+      d = mk<float>((float)(sig * ux), (float)(sig * uy));
+      d32[idx] = d;
+      x32[idx] = vzero<V>();
+    }
+    if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, d, g);
+  }
+  __syncthreads();
+  lds_fft<float, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+}
+
+// End of one correction: x64 += ||r|| e32 (status.rscale), then the gradient
+// of the new x64 into the FP64 mixed buffers for the next residual.
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
+                                                        cd* Gx, cd* Gy) {
+  using C = ColCfg<NY, 2>;
+  __shared__ cd buf[C::NB * C::LS];
+  const cd* tw = (const cd*)g.tw;
+  const int kx0 = blockIdx.x * C::C;
+  const double sc = g.st->rscale;
+  cd xv[C::EP];
+  cx<float> ev[C::EP];
+  colP_gload<NY, 2>(xv, x64, kx0, g.h);
+  colP_gload<NY, 2>(ev, x32, kx0, g.h);
+#pragma unroll
+  for (int i = 0; i < C::EP; ++i) {
+    const int p = threadIdx.x + i * C::NT;
+    const int c = p / NY, ky = p % NY;
+    const int kx = kx0 + c;
+    cd x = mk<double>(0.0, 0.0);
+    if (p < C::CN && kx < g.h) {
+      x = mk<double>(fma(sc, (double)ev[i].x, xv[i].x), fma(sc, (double)ev[i].y, xv[i].y));
+      x64[(size_t)kx * NY + ky] = x;
+    }
+    if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, x, g);
+  }
   __syncthreads();
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
@@ -1176,10 +1361,23 @@ hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s
   return hipGetLastError();
 }
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
-                           double* kslot, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                           double* kslot, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* lo) {
   const dim3 grid(row_nwg(g)), blk(2 * TPF);
   const int nwg_col = col_nwg(g);
-#define L_(N) NF_LAUNCH(k_row_flux<N>, grid, blk, s, e0, e1, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2)
+#define L_(N)                                                                                                    \
+  NF_LAUNCH((k_row_flux<N, double>), grid, blk, s, e0, e1, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2, \
+            lo)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32, const float* r32, int it,
+                             double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(row_nwg(g)), blk(2 * TPF);
+  const int nwg_col = col_nwg(g);
+#define L_(N)                                                                                                     \
+  NF_LAUNCH((k_row_flux<N, float>), grid, blk, s, e0, e1, g, (cx<float>*)G0, (cx<float>*)G1, m32, r32, it,        \
+            (double*)nullptr, nwg_col, tol2, (float*)nullptr)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();
@@ -1239,17 +1437,28 @@ hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy
   const dim3 grid(col_nwg(g)), blk(2 * TPF);
   if (init) {
 #define L_(N)                                                                                                 \
-  NF_LAUNCH((k_col_div<N, true>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,             \
+  NF_LAUNCH((k_col_div<N, true, double>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,     \
             (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   } else {
 #define L_(N)                                                                                                 \
-  NF_LAUNCH((k_col_div<N, false>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,            \
+  NF_LAUNCH((k_col_div<N, false, double>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,    \
             (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
+  return hipGetLastError();
+}
+hipError_t launch_col_div32(const Geo& g, const void* Fx, const void* Fy, void* qh, const void* dh, void* rh, int it,
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  typedef cx<float> cf;
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+#define L_(N)                                                                                                 \
+  NF_LAUNCH((k_col_div<N, false, float>), grid, blk, s, e0, e1, g, (const cf*)Fx, (const cf*)Fy, (cf*)qh,     \
+            (const cf*)dh, (cf*)rh, (const cf*)nullptr, it, 0)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
   return hipGetLastError();
 }
 hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
@@ -1258,8 +1467,41 @@ hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* 
   const dim3 grid(col_nwg(g)), blk(2 * TPF);
   const int nwg = col_nwg(g);
 #define L_(N)                                                                                                  \
-  NF_LAUNCH(k_col_update<N>, grid, blk, s, e0, e1, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, (cd*)Gx, \
-            (cd*)Gy, it, max_iter, tol2, nwg)
+  NF_LAUNCH((k_col_update<N, double>), grid, blk, s, e0, e1, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, \
+            (cd*)Gx, (cd*)Gy, it, max_iter, tol2, nwg)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const void* qh, void* Gx, void* Gy, int it,
+                               int max_iter, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  typedef cx<float> cf;
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const int nwg = col_nwg(g);
+#define L_(N)                                                                                                  \
+  NF_LAUNCH((k_col_update<N, float>), grid, blk, s, e0, e1, g, 0, (cf*)xh, (cf*)rh, (cf*)dh, (const cf*)qh,    \
+            (cf*)Gx, (cf*)Gy, it, max_iter, tol2, nwg)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_col_refine_start(const Geo& g, const void* r64, void* x64, void* x32, void* r32, void* d32,
+                                   void* Gx, void* Gy, double tol2, double floor_in, int budget, double rr_cap,
+                                   hipStream_t s) {
+  typedef cx<float> cf;
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const int nwg = col_nwg(g);
+#define L_(N)                                                                                                 \
+  hipLaunchKernelGGL(k_col_refine_start<N>, grid, blk, 0, s, g, (const cd*)r64, (cd*)x64, (cf*)x32, (cf*)r32,  \
+                     (cf*)d32, (cf*)Gx, (cf*)Gy, tol2, floor_in, budget, rr_cap, nwg)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launch_col_refine_acc(const Geo& g, void* x64, const void* x32, void* Gx, void* Gy, hipStream_t s) {
+  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+#define L_(N)                                                                                                 \
+  hipLaunchKernelGGL(k_col_refine_acc<N>, grid, blk, 0, s, g, (cd*)x64, (const cx<float>*)x32, (cd*)Gx, (cd*)Gy)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();

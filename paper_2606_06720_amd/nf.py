@@ -27,6 +27,7 @@ NF_ENOTCONV = -4
 NF_EINCOMPAT = -5
 NF_ENONFINITE = -6
 NF_F64 = 0
+NF_F32_REFINED = 1
 NF_STOP_MAX_STEPS = 0
 NF_STOP_DM_BELOW_EPS = 1
 NF_STOP_ENERGY_INCREASE = 2
@@ -94,6 +95,7 @@ def _load():
     lib.nf_transform_forward.argtypes = [vp, vp, vp]
     lib.nf_transform_inverse.argtypes = [vp, vp, vp]
     lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
+    lib.nf_set_inner_tolerance.argtypes = [vp, dp]
     lib.nf_time_kernel.argtypes = [vp, ctypes.c_int]
     lib.nf_time_kernel_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.nf_last_error.argtypes = [vp]
@@ -273,6 +275,9 @@ class Grid:
 
 
     # diagnostics -----------------------------------------------------------
+    def set_inner_tolerance(self, floor_rtol):
+        self._check(_lib.nf_set_inner_tolerance(self._h, float(floor_rtol)))
+
     def time_kernel(self, which):
         """nf_time_kernel: time launches of one PCG-loop kernel (-1 = off)."""
         self._check(_lib.nf_time_kernel(self._h, int(which)))
@@ -334,3 +339,7 @@ def nf_energy(g, c2, D2, gamma, m, r, S, p=None):
 def nf_step_adjoint(g, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol=1e-12,
                     max_iter=2000):
     return g.step_adjoint(c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol, max_iter)
+
+
+def nf_set_inner_tolerance(g, floor_rtol):
+    g.set_inner_tolerance(floor_rtol)

@@ -65,3 +65,5 @@ def test_null_handle_calls_are_rejected(lib):
     lib.nf_pressure_solve.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
     assert lib.nf_pressure_solve(None, None, None, None, None, 1e-10, 10, None) == -1
     assert lib.nf_destroy_grid(None) == 0
+    lib.nf_set_inner_tolerance.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    assert lib.nf_set_inner_tolerance(None, 1e-5) == -1
