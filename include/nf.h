@@ -223,6 +223,40 @@ int nf_transform_inverse(nf_grid *g, const double *spec, double *f);
 int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double *p, double *out);
 
 /*
+ * Ensembles: independent instances of the problem of Sec. 2 advanced together.
+ * Every pass of a time step is one launch per grid shape covering all the
+ * instances of that shape (the instance is the second grid dimension), and
+ * each PCG iteration is launched for all instances at once; an instance whose
+ * solve has stopped does no work in the later iterations of that solve.
+ *
+ * nf_batch_create: count >= 1 instances; n [count][2] grid sizes (Nx, Ny),
+ *   powers of two in [8, 4096]; L [count][2] box lengths (> 0); dtype
+ *   NF_F64 or NF_F32_REFINED for every instance; stream as for
+ *   nf_create_grid.  Each instance owns the workspace of one nf_grid.
+ *   Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure (*out is then NULL;
+ *   nf_batch_last_error(NULL) holds the message).
+ * nf_batch_run: for every instance i the computation of
+ *   nf_run(g_i, &prm[i], dt, steps, 0.0, 0, m[i], p[i], r[i], S[i], rtol,
+ *          max_iter, &info[i])
+ *   (fixed step count, no Delta m or energy stopping).  The fields written
+ *   are bitwise those of that single-instance call.  prm: count entries;
+ *   m, p, r, S: count device pointers each, with the layouts of nf_run;
+ *   info: count entries or NULL.  Returns NF_OK, NF_EINCOMPAT (some S_i
+ *   violates the solvability condition; nothing is advanced), NF_ENONFINITE
+ *   (the run stops for all instances after the step that produced it),
+ *   NF_EINVAL or NF_EDEVICE.  Unconverged solves are counted per instance as
+ *   in nf_run.
+ */
+typedef struct nf_batch nf_batch;
+int nf_batch_create(nf_batch **out, int count, const int64_t *n, const double *L, int dtype, void *stream);
+int nf_batch_destroy(nf_batch *b);
+/* Change the stream the batch enqueues on. */
+int nf_batch_set_stream(nf_batch *b, void *stream);
+int nf_batch_run(nf_batch *b, const nf_params *prm, double dt, int64_t steps, double *const *m, double *const *p,
+                 const double *const *r, const double *const *S, double rtol, int max_iter, nf_run_info *info);
+const char *nf_batch_last_error(const nf_batch *b);
+
+/*
  * Kernel timing: nf_time_kernel(g, k) makes the handle bracket every launch of
  * the PCG-loop kernel k (NF_KERNEL_*) with a pair of HIP events on its stream;
  * launches queued after the solver stopped (which do no work) are discarded.

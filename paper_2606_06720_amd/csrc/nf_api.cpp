@@ -11,53 +11,10 @@
 #include <vector>
 
 #include "nf.h"
+#include "nf_handle.h"
 #include "nf_internal.h"
 
 using namespace nf;
-
-struct nf_grid {
-  int nx = 0, ny = 0, h = 0;
-  double lx = 1.0, ly = 1.0;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  void* tw = nullptr;
-  int twlog = 0;
-  void* xh = nullptr;  // PCG iterate (spectral)
-  void* rh = nullptr;  // residual
-  void* dh = nullptr;  // search direction
-  void* qh = nullptr;  // A d
-  void* bh = nullptr;  // projected right-hand side
-  void* mix[3] = {nullptr, nullptr, nullptr};
-  double* part = nullptr;
-  DevStatus* st = nullptr;
-  DevStatus* hst = nullptr;  // pinned, 2 slots
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  int last_iters = 0;
-  std::string err;
-  Geo geo;
-  // mixed-precision solve (dtype NF_F32_REFINED): FP32 inner PCG state
-  int dtype = NF_F64;
-  void* tw32 = nullptr;
-  void* x32 = nullptr;  // inner iterate (correction e)
-  void* r32 = nullptr;
-  void* d32 = nullptr;
-  void* q32 = nullptr;
-  void* mix32[2] = {nullptr, nullptr};
-  float* lo = nullptr;  // FP32 copies of m (2n) and r (n)
-  double inner_floor = 1e-5;
-  int last_inner[4] = {0, 0, 0, 0};
-  Geo geo32;
-  // optional per-kernel timing of one PCG-loop kernel (events on the handle's stream)
-  struct TimedLaunch {
-    hipEvent_t a, b;
-    int it;
-  };
-  int timed = -1;
-  std::vector<TimedLaunch> pool;
-  size_t pool_used = 0;
-  double timed_ms = 0.0;
-  int64_t timed_count = 0;
-};
 
 namespace {
 
@@ -265,7 +222,9 @@ int prepare_iterate(nf_grid* g, XSource src, const double* p) {
 // products and scalars).  The solve stops on the FP64 residual, so rtol means
 // what it means for the FP64 solver.  max_iter bounds the sum of the inner
 // iterations; a correction that does not lower the FP64 residual ends the
-// solve as not converged.
+// solve as not converged.  The decisions are taken on the device (status
+// fields outer_done, itot, orr_prev); the host only repeats the passes until
+// the status reports the end.
 int pcg_refined(nf_grid* g, const double* m, const double* r, XSource src, const double* p, double rtol,
                 int max_iter, bool want_true, SolveOut* out) {
   const Geo& G = g->geo;
@@ -274,38 +233,29 @@ int pcg_refined(nf_grid* g, const double* m, const double* r, XSource src, const
   int rc = prepare_iterate(g, src, p);
   if (rc) return rc;
   const double tol2 = rtol * rtol;
-  int total = 0, outer = 0;
-  double rr_cap = INFINITY;
   DevStatus fin;
-  for (;;) {
+  for (int outer = 0;; ++outer) {
     // FP64 residual r = b - A x (and, on the first pass, the FP32 copies of m, r)
     LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, s, nullptr,
                             nullptr, outer == 0 ? g->lo : nullptr));
     LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), s));
-    const int budget = max_iter - total;
     LCHK(g, launch_col_refine_start(g->geo32, g->rh, g->xh, g->x32, g->r32, g->d32, g->mix32[0], g->mix32[1], tol2,
-                                    g->inner_floor, budget, rr_cap, s));
+                                    g->inner_floor, max_iter, s));
     const int slot = outer < 3 ? outer : 3;
-    rc = pcg_loop(g, true, m, r, budget > 0 ? budget : 0, 1.0, g->last_inner[slot], &fin);
+    rc = pcg_loop(g, true, m, r, max_iter, 1.0, g->last_inner[slot], &fin);
     if (rc) return rc;
     if (fin.outer_done) break;
-    total += fin.iters;
     if (fin.iters > 0) g->last_inner[slot] = fin.iters;
-    if (fin.flags & FLAG_NONFINITE) break;
-    rr_cap = fin.orr;
     // x += ||r|| e and the gradient of the new x for the next residual
     LCHK(g, launch_col_refine_acc(G, g->xh, g->x32, g->mix[0], g->mix[1], s));
-    ++outer;
   }
-  out->iters = total;
-  out->converged = fin.outer_done ? fin.converged : 0;
+  out->iters = fin.itot;
+  out->converged = fin.converged;
   out->flags = fin.flags;
   out->sticky = fin.sticky;
-  const double rrf = fin.outer_done ? fin.orr : fin.rr[0];
-  const double bbf = fin.outer_done ? fin.obb : fin.bb;
-  out->rel_res = bbf > 0.0 ? std::sqrt(rrf > 0.0 ? rrf : 0.0) / std::sqrt(bbf) : 0.0;
+  out->rel_res = fin.obb > 0.0 ? std::sqrt(fin.orr > 0.0 ? fin.orr : 0.0) / std::sqrt(fin.obb) : 0.0;
   // the stopping test is already on the FP64 residual of the returned iterate
-  out->true_rel_res = (want_true && fin.outer_done && !(fin.flags & FLAG_INCOMPAT)) ? out->rel_res : -1.0;
+  out->true_rel_res = (want_true && !(fin.flags & FLAG_INCOMPAT)) ? out->rel_res : -1.0;
   return NF_OK;
 }
 
@@ -466,6 +416,7 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   CREATE_CHK(hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)), NF_ENOMEM);
   CREATE_CHK(hipMalloc((void**)&g->part, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_ENOMEM);
   CREATE_CHK(hipMalloc((void**)&g->st, sizeof(DevStatus)), NF_ENOMEM);
+  g->st_own = g->st;
   CREATE_CHK(hipHostMalloc((void**)&g->hst, 2 * sizeof(DevStatus), hipHostMallocDefault), NF_ENOMEM);
   for (int i = 0; i < 2; ++i) CREATE_CHK(hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming), NF_EDEVICE);
   {
@@ -536,7 +487,7 @@ int nf_destroy_grid(nf_grid* g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
   void* bufs[] = {g->xh,  g->rh,  g->dh,  g->qh,  g->bh,       g->mix[0],   g->mix[1], g->mix[2], g->tw,
-                  g->part, g->st, g->x32, g->r32, g->d32, g->q32, g->mix32[0], g->mix32[1], g->lo,    g->tw32};
+                  g->part, g->st_own, g->x32, g->r32, g->d32, g->q32, g->mix32[0], g->mix32[1], g->lo, g->tw32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (g->hst) (void)hipHostFree(g->hst);

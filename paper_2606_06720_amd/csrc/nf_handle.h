@@ -1,0 +1,57 @@
+// Host-side solver handle (opaque to callers of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "nf.h"
+#include "nf_internal.h"
+
+struct nf_grid {
+  using DevStatus = nf::DevStatus;
+  using Geo = nf::Geo;
+  int nx = 0, ny = 0, h = 0;
+  double lx = 1.0, ly = 1.0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* tw = nullptr;
+  int twlog = 0;
+  void* xh = nullptr;  // PCG iterate (spectral)
+  void* rh = nullptr;  // residual
+  void* dh = nullptr;  // search direction
+  void* qh = nullptr;  // A d
+  void* bh = nullptr;  // projected right-hand side
+  void* mix[3] = {nullptr, nullptr, nullptr};
+  double* part = nullptr;
+  DevStatus* st = nullptr;
+  DevStatus* hst = nullptr;  // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int last_iters = 0;
+  DevStatus* st_own = nullptr;  // the handle's own status block (st may point into a batch's array)
+  std::string err;
+  Geo geo;
+  // mixed-precision solve (dtype NF_F32_REFINED): FP32 inner PCG state
+  int dtype = NF_F64;
+  void* tw32 = nullptr;
+  void* x32 = nullptr;  // inner iterate (correction e)
+  void* r32 = nullptr;
+  void* d32 = nullptr;
+  void* q32 = nullptr;
+  void* mix32[2] = {nullptr, nullptr};
+  float* lo = nullptr;  // FP32 copies of m (2n) and r (n)
+  double inner_floor = 1e-5;
+  int last_inner[4] = {0, 0, 0, 0};
+  Geo geo32;
+  // optional per-kernel timing of one PCG-loop kernel (events on the handle's stream)
+  struct TimedLaunch {
+    hipEvent_t a, b;
+    int it;
+  };
+  int timed = -1;
+  std::vector<TimedLaunch> pool;
+  size_t pool_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_count = 0;
+};

@@ -17,6 +17,7 @@ struct DevStatus {
   double rr0;       // initial ||r||^2
   double orr, obb;  // mixed-precision solve: FP64 ||r||^2 and ||b||^2 at the last correction start
   double rscale;    // mixed-precision solve: ||r|| scaling the FP32 correction
+  double orr_prev;  // mixed-precision solve: ||r||^2 at the previous correction start (+inf before the first)
   double out[16];   // results of the final reductions (energy terms, dm, ...)
   int conv_at;      // iteration at which PCG stopped (converged or max_iter); INT_MAX while running
   int converged;    // 1 if the stop was convergence
@@ -24,7 +25,8 @@ struct DevStatus {
   int flags;        // FLAG_* bits of the current PCG solve
   int sticky;       // FLAG_* bits raised since the last full reset (split update)
   int outer_done;   // mixed-precision solve: 1 once the FP64 residual test has ended it
-  int pad[2];
+  int itot;         // mixed-precision solve: FP32 iterations of the finished corrections
+  int budget;       // iteration limit of the current (inner) PCG run, INT_MAX when unused
 };
 
 enum { FLAG_NONFINITE = 1, FLAG_INCOMPAT = 2 };
@@ -58,6 +60,104 @@ struct Geo {
 __host__ __device__ inline double* slot_ptr(double* part, int slot) {
   return part + (size_t)slot * SLOT_K * MAX_WG;
 }
+
+// ---- per-instance arguments of the batched passes --------------------------------
+// A batched launch covers `count` instances of one grid shape: blockIdx.y picks
+// the instance, whose pointers and parameters are read from a device array of
+// these structs (same names and meaning as the single-instance launchers'
+// arguments; void* fields hold complex double, complex float or double data
+// as the pass expects).
+struct RowR2cArgs {
+  Geo g;
+  const double* f;
+  void* out;
+  double* schk;
+};
+struct ColFwdArgs {
+  Geo g;
+  void* in;
+  void* out;
+  void* Gx;
+  void* Gy;
+};
+struct ColGradArgs {
+  Geo g;
+  const void* xh;
+  void* P;
+  void* Gx;
+  void* Gy;
+};
+struct FluxArgs {
+  Geo g;
+  void* G0;
+  void* G1;
+  const void* m;
+  const void* r;
+  double* kslot;
+  float* lo;
+};
+struct DivArgs {
+  Geo g;
+  const void* Fx;
+  const void* Fy;
+  void* qh;
+  const void* dh;
+  void* rh;
+  const void* bh;
+};
+struct UpdArgs {
+  Geo g;
+  void* xh;
+  void* rh;
+  void* dh;
+  const void* qh;
+  void* Gx;
+  void* Gy;
+};
+struct SplitArgs {
+  Geo g;
+  void* P;
+  void* Gx;
+  const void* Gy;
+  const double* m;
+  double* p_out;
+  double c2dt, gamma, dt, relax1;
+};
+struct HeatArgs {
+  Geo g;
+  void* Mx;
+  void* My;
+  double D2dt;
+  double* eslot;
+};
+struct FinalArgs {
+  Geo g;
+  const void* Mx;
+  const void* My;
+  double* m;
+  double* dslot;
+};
+struct RefStartArgs {
+  Geo g;
+  const void* r64;
+  void* x64;
+  void* x32;
+  void* r32;
+  void* d32;
+  void* Gx;
+  void* Gy;
+};
+struct RefAccArgs {
+  Geo g;
+  void* x64;
+  const void* x32;
+  void* Gx;
+  void* Gy;
+};
+struct SumArgs {
+  const double* slot;
+  DevStatus* st;
+};
 
 // ---- host-callable launchers (defined in nf_kernels.hip) --------------------------
 // All take the stream last and return hipError_t of the launch.
@@ -102,8 +202,7 @@ hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const
                                hipEvent_t e1 = nullptr);
 // mixed-precision correction start / accumulation (g32: FP32 twiddles)
 hipError_t launch_col_refine_start(const Geo& g32, const void* r64, void* x64, void* x32, void* r32, void* d32,
-                                   void* Gx32, void* Gy32, double tol2, double floor_in, int budget, double rr_cap,
-                                   hipStream_t s);
+                                   void* Gx32, void* Gy32, double tol2, double floor_in, int max_iter, hipStream_t s);
 hipError_t launch_col_refine_acc(const Geo& g, void* x64, const void* x32, void* Gx, void* Gy, hipStream_t s);
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* egm_slot, hipStream_t s);
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* egm_slot, hipStream_t s);
@@ -117,5 +216,26 @@ hipError_t launch_col_divrhs(const Geo& g, const void* V0, const void* V1, void*
 hipError_t launch_zero_doubles(double* p, size_t n, hipStream_t s);
 // reduce K arrays of n partials of a slot into st->out[o..o+K)
 hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o, hipStream_t s);
+
+// Batched launchers: `shape` gives the grid shape shared by the instances
+// (sizes only), A points at `count` device-resident argument structs; the
+// remaining arguments are common to the batch.  st0: `count` contiguous statuses.
+hipError_t launchb_status_reset(DevStatus* st0, int count, int full, hipStream_t s);
+hipError_t launchb_sum_slot(const SumArgs* A, int count, int K, int n, int o, hipStream_t s);
+hipError_t launchb_row_r2c(const Geo& shape, const RowR2cArgs* A, int count, hipStream_t s);
+hipError_t launchb_col_fwd(const Geo& shape, const ColFwdArgs* A, int count, int mode, hipStream_t s);
+hipError_t launchb_col_grad(const Geo& shape, const ColGradArgs* A, int count, bool grad, hipStream_t s);
+hipError_t launchb_row_flux(const Geo& shape, bool f32, const FluxArgs* A, int count, int it, double tol2,
+                            hipStream_t s);
+hipError_t launchb_col_div(const Geo& shape, bool f32, bool init, const DivArgs* A, int count, int it,
+                           hipStream_t s);
+hipError_t launchb_col_update(const Geo& shape, bool f32, const UpdArgs* A, int count, int first, int it,
+                              int max_iter, double tol2, hipStream_t s);
+hipError_t launchb_row_split(const Geo& shape, const SplitArgs* A, int count, hipStream_t s);
+hipError_t launchb_col_heat(const Geo& shape, const HeatArgs* A, int count, hipStream_t s);
+hipError_t launchb_row_final(const Geo& shape, const FinalArgs* A, int count, hipStream_t s);
+hipError_t launchb_col_refine_start(const Geo& shape, const RefStartArgs* A, int count, double tol2,
+                                    double floor_in, int max_iter, hipStream_t s);
+hipError_t launchb_col_refine_acc(const Geo& shape, const RefAccArgs* A, int count, hipStream_t s);
 
 }  // namespace nf

@@ -223,8 +223,8 @@ __device__ __forceinline__ void write_partials(double* slot, const double* v, in
 }
 
 // ================================================================ small kernels
-__global__ void k_status_reset(DevStatus* st, int full) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__device__ __forceinline__ void k_status_reset_one(DevStatus* st, int full) {
+  if (threadIdx.x == 0) {
     if (full) st->sticky = 0;
     for (int i = 0; i < 4; ++i) st->kbar[i] = 0.0;
     st->bb = 0.0;
@@ -232,7 +232,10 @@ __global__ void k_status_reset(DevStatus* st, int full) {
     st->rr[0] = st->rr[1] = 0.0;
     st->rr0 = 0.0;
     st->orr = st->obb = st->rscale = 0.0;
+    st->orr_prev = __builtin_inf();
     st->outer_done = 0;
+    st->itot = 0;
+    st->budget = INT_MAX;
     for (int i = 0; i < 16; ++i) st->out[i] = 0.0;
     st->conv_at = INT_MAX;
     st->converged = 0;
@@ -241,12 +244,16 @@ __global__ void k_status_reset(DevStatus* st, int full) {
   }
 }
 
+__global__ void k_status_reset(DevStatus* st, int full) {
+  if (blockIdx.x == 0) k_status_reset_one(st, full);
+}
+__global__ void kb_status_reset(DevStatus* st0, int full) { k_status_reset_one(st0 + blockIdx.x, full); }
 __global__ void k_zero(cd* p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = mk<double>(0.0, 0.0);
 }
 
-__global__ void __launch_bounds__(256) k_sum_slot(const double* __restrict__ slot, int K, int n, int o, DevStatus* st) {
+__device__ __forceinline__ void sum_slot_body(const double* __restrict__ slot, int K, int n, int o, DevStatus* st) {
   __shared__ double scratch[8 * 4];
   double v[8];
   for (int k = 0; k < 8; ++k) v[k] = 0.0;
@@ -256,11 +263,17 @@ __global__ void __launch_bounds__(256) k_sum_slot(const double* __restrict__ slo
   if (threadIdx.x == 0)
     for (int k = 0; k < K; ++k) st->out[o + k] = v[k];
 }
+__global__ void __launch_bounds__(256) k_sum_slot(const double* __restrict__ slot, int K, int n, int o, DevStatus* st) {
+  sum_slot_body(slot, K, n, o, st);
+}
+__global__ void __launch_bounds__(256) kb_sum_slot(const SumArgs* __restrict__ A, int K, int n, int o) {
+  sum_slot_body(A[blockIdx.y].slot, K, n, o, A[blockIdx.y].st);
+}
 
 // ================================================================ row kernels
 // physical -> mixed; optional partials sum f, sum |f| (compatibility of S)
 template <int NX>
-__global__ void __launch_bounds__(TPF) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
+__device__ __forceinline__ void row_r2c_body(Geo g, const double* __restrict__ f, cd* __restrict__ out,
                                                  double* schk) {
   using C = RowCfg<NX, 1>;
   __shared__ cd buf[C::NB * C::LS];
@@ -288,6 +301,16 @@ __global__ void __launch_bounds__(TPF) k_row_r2c(Geo g, const double* __restrict
     block_sum<C::NT, 2>(s, red);
     write_partials<C::NT>(schk, s, 2);
   }
+}
+template <int NX>
+__global__ void __launch_bounds__(TPF) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
+                                                 double* schk) {
+  row_r2c_body<NX>(g, f, out, schk);
+}
+template <int NX>
+__global__ void __launch_bounds__(TPF) kb_row_r2c(const RowR2cArgs* __restrict__ A) {
+  const RowR2cArgs& a = A[blockIdx.y];
+  row_r2c_body<NX>(a.g, (const double*)a.f, (cd*)a.out, (double*)a.schk);
 }
 
 // mixed -> physical (unnormalised inverse: the caller folds 1/n into the spectral side)
@@ -324,13 +347,13 @@ __global__ void __launch_bounds__(TPF) k_row_c2r(Geo g, const cd* __restrict__ i
 // T is the arithmetic and storage type of the transforms and fields; the
 // reductions are FP64 in both instantiations.
 template <int NX, typename T>
-__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
+__device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
                                                   const T* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2, float* lo) {
   using C = RowCfg<NX, 2>;
   using V = cx<T>;
   using P = typename vec2<T>::type;
-  if (it >= 0 && g.st->conv_at <= it) return;
+  if (it >= 0 ? g.st->conv_at <= it : g.st->outer_done != 0) return;
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[4 * (C::NT / 64)];
   const V* tw = (const V*)g.tw;
@@ -406,12 +429,23 @@ __global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G
     write_partials<C::NT>(kslot, ks, 4);
   }
 }
+template <int NX, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
+                                                  const T* __restrict__ r, int it, double* kslot, int nwg_col,
+                                                  double tol2, float* lo) {
+  row_flux_body<NX, T>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo);
+}
+template <int NX, typename T>
+__global__ void __launch_bounds__(2 * TPF) kb_row_flux(const FluxArgs* __restrict__ A, int it, int nwg_col, double tol2) {
+  const FluxArgs& a = A[blockIdx.y];
+  row_flux_body<NX, T>(a.g, (cx<T>*)a.G0, (cx<T>*)a.G1, (const T*)a.m, (const T*)a.r, it, (double*)a.kslot, nwg_col, tol2, (float*)a.lo);
+}
 
 // Split update, pointwise part: p = F^-1 x_hat (written out), g = grad p,
 // exact activation then exact relaxation of m, forward x transform of the
 // result.  In place: P, Gx hold the transformed m_x, m_y on exit.
 template <int NX>
-__global__ void __launch_bounds__(3 * TPF) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
+__device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
   using C = RowCfg<NX, 3>;
@@ -482,11 +516,22 @@ __global__ void __launch_bounds__(3 * TPF) k_row_split(Geo g, cd* P, cd* Gx, con
   rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
   rowT_store<NX, 3, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
 }
+template <int NX>
+__global__ void __launch_bounds__(3 * TPF) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
+                                                   const double* __restrict__ m, double* __restrict__ p_out,
+                                                   double c2dt, double gamma, double dt, double relax1) {
+  row_split_body<NX>(g, P, Gx, Gy, m, p_out, c2dt, gamma, dt, relax1);
+}
+template <int NX>
+__global__ void __launch_bounds__(3 * TPF) kb_row_split(const SplitArgs* __restrict__ A) {
+  const SplitArgs& a = A[blockIdx.y];
+  row_split_body<NX>(a.g, (cd*)a.P, (cd*)a.Gx, (const cd*)a.Gy, (const double*)a.m, (double*)a.p_out, a.c2dt, a.gamma, a.dt, a.relax1);
+}
 
 // Last pass of the step: inverse x transform of the diffused m, written over
 // m; partials sum (m_new - m_old)^2 and sum m_old^2.
 template <int NX>
-__global__ void __launch_bounds__(2 * TPF) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+__device__ __forceinline__ void row_final_body(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                    double* m, double* dslot) {
   using C = RowCfg<NX, 2>;
   __shared__ cd buf[C::NB * C::LS];
@@ -524,6 +569,16 @@ __global__ void __launch_bounds__(2 * TPF) k_row_final(Geo g, const cd* __restri
     block_sum<C::NT, 2>(s, red);
     write_partials<C::NT>(dslot, s, 2);
   }
+}
+template <int NX>
+__global__ void __launch_bounds__(2 * TPF) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+                                                   double* m, double* dslot) {
+  row_final_body<NX>(g, Mx, My, m, dslot);
+}
+template <int NX>
+__global__ void __launch_bounds__(2 * TPF) kb_row_final(const FinalArgs* __restrict__ A) {
+  const FinalArgs& a = A[blockIdx.y];
+  row_final_body<NX>(a.g, (const cd*)a.Mx, (const cd*)a.My, (double*)a.m, (double*)a.dslot);
 }
 
 // Pointwise energy terms: sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
@@ -760,7 +815,7 @@ __device__ __forceinline__ void put_grad(cx<T>* buf, int c, int ky, int kx, cons
 // of mode also the gradient of the result back to mixed:
 // Gx = F_y^-1(i xi_x f_hat / n), Gy likewise.
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
+__device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
   using C = ColCfg<NY, 2>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
@@ -791,11 +846,20 @@ __global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restri
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
+  col_fwd_body<NY>(g, in, out, mode, Gx, Gy);
+}
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) kb_col_fwd(const ColFwdArgs* __restrict__ A, int mode) {
+  const ColFwdArgs& a = A[blockIdx.y];
+  col_fwd_body<NY>(a.g, (cd*)a.in, (cd*)a.out, mode, (cd*)a.Gx, (cd*)a.Gy);
+}
 
 // spectral -> mixed: P = F_y^-1(x_hat / n)  (GRAD false)  or
 //                    Gx, Gy as in k_col_fwd (GRAD true)
 template <int NY, bool GRAD>
-__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
+__device__ __forceinline__ void col_grad_body(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
                                                                cd* Gy) {
   using C = ColCfg<NY, GRAD ? 2 : 1>;
   __shared__ cd buf[C::NB * C::LS];
@@ -816,6 +880,16 @@ __global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const 
   if (GRAD) colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
   else colT_store<NY, 1, 1>(buf, P, nullptr, kx0, g.h);
 }
+template <int NY, bool GRAD>
+__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
+                                                               cd* Gy) {
+  col_grad_body<NY, GRAD>(g, xh, P, Gx, Gy);
+}
+template <int NY, bool GRAD>
+__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) kb_col_grad(const ColGradArgs* __restrict__ A) {
+  const ColGradArgs& a = A[blockIdx.y];
+  col_grad_body<NY, GRAD>(a.g, (const cd*)a.xh, (cd*)a.P, (cd*)a.Gx, (cd*)a.Gy);
+}
 
 __device__ __forceinline__ double precond_symbol_inv(const double* K, double xx, double yy) {
   const double s = K[0] * xx * xx + 2.0 * K[1] * xx * yy + K[2] * yy * yy;
@@ -829,14 +903,14 @@ __device__ __forceinline__ double precond_symbol_inv(const double* K, double xx,
 //       <r,M^-1 r>, <r,r>.
 // INIT exists for T = double only (the residual of the refinement is FP64).
 template <int NY, bool INIT, typename T>
-__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
+__device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx,
                                                  const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
                                                  const cx<T>* __restrict__ dh, cx<T>* rh,
                                                  const cx<T>* __restrict__ bh, int it, int nwg_row) {
   using C = ColCfg<NY, 2>;
   using V = cx<T>;
   static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
-  if (!INIT && g.st->conv_at <= it) return;
+  if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   __shared__ double Ks[4];
@@ -914,6 +988,18 @@ __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restr
   block_sum<C::NT, 7>(s, red);
   write_partials<C::NT>(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
 }
+template <int NY, bool INIT, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
+                                                 const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
+                                                 const cx<T>* __restrict__ dh, cx<T>* rh,
+                                                 const cx<T>* __restrict__ bh, int it, int nwg_row) {
+  col_div_body<NY, INIT, T>(g, Fx, Fy, qh, dh, rh, bh, it, nwg_row);
+}
+template <int NY, bool INIT, typename T>
+__global__ void __launch_bounds__(2 * TPF) kb_col_div(const DivArgs* __restrict__ A, int it, int nwg_row) {
+  const DivArgs& a = A[blockIdx.y];
+  col_div_body<NY, INIT, T>(a.g, (const cx<T>*)a.Fx, (const cx<T>*)a.Fy, (cx<T>*)a.qh, (const cx<T>*)a.dh, (cx<T>*)a.rh, (const cx<T>*)a.bh, it, nwg_row);
+}
 
 // PCG scalar step + vector update + next direction + its gradient (mixed).
 // first: d = M^-1 r.  else: alpha, beta from the partials of k_col_div (the
@@ -924,7 +1010,7 @@ __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restr
 // The scalars are FP64; the vector updates run in T.  `first` exists for
 // T = double only (the single-precision solve starts in k_col_refine_start).
 template <int NY, typename T>
-__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
+__device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
                                                     const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
   using C = ColCfg<NY, 2>;
@@ -982,7 +1068,7 @@ __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>*
     const double rhon = rho - 2.0 * alpha * s[1] + alpha * alpha * s[2];
     beta = rhon / rho;
     const bool bad = !isfinite(rhon) || !isfinite(alpha);
-    stop = bad || it >= max_iter;
+    stop = bad || it >= max_iter || it >= st->budget;
     if (lead) {
       if (bad) st->flags |= FLAG_NONFINITE;
       st->rho[it & 1] = rhon;
@@ -1032,6 +1118,17 @@ __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>*
   lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
+template <int NY, typename T>
+__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
+                                                    const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
+                                                    int max_iter, double tol2, int nwg_col) {
+  col_update_body<NY, T>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg_col);
+}
+template <int NY, typename T>
+__global__ void __launch_bounds__(2 * TPF) kb_col_update(const UpdArgs* __restrict__ A, int first, int it, int max_iter, double tol2, int nwg_col) {
+  const UpdArgs& a = A[blockIdx.y];
+  col_update_body<NY, T>(a.g, first, (cx<T>*)a.xh, (cx<T>*)a.rh, (cx<T>*)a.dh, (const cx<T>*)a.qh, (cx<T>*)a.Gx, (cx<T>*)a.Gy, it, max_iter, tol2, nwg_col);
+}
 
 // Start of one correction of the mixed-precision solve (iterative refinement
 // of A x = b: the inner solve A e = r runs in FP32, x and the residual
@@ -1044,14 +1141,17 @@ __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>*
 // in the FP32 mixed buffers, and the inner stopping threshold (a relative
 // residual of tol_in on the unit right-hand side, kept in status.bb for the
 // passes' test with tol2 = 1) asks for the reduction that reaches tol2 with a
-// margin of 2, but no less than `floor_in`.  A residual no smaller than
-// rr_cap (the previous correction's) means the refinement has stalled: the
-// solve ends unconverged, as it does when the iteration budget is spent.
+// margin of 2, but no less than `floor_in`.  A residual no smaller than the
+// previous correction's means the refinement has stalled: the solve ends
+// unconverged, as it does when max_iter FP32 iterations have been spent.
+// Instances that have finished repeat their final decision unchanged (their
+// residual passes are skipped), so a batch can run until all have finished.
+// Status fields read here are written only by other launches.
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
+__device__ __forceinline__ void col_refine_start_body(Geo g, const cd* __restrict__ r64, cd* x64,
                                                           cx<float>* x32, cx<float>* r32, cx<float>* d32,
                                                           cx<float>* Gx, cx<float>* Gy, double tol2,
-                                                          double floor_in, int budget, double rr_cap, int nwg_col) {
+                                                          double floor_in, int max_iter, int nwg_col) {
   using C = ColCfg<NY, 2>;
   using V = cx<float>;
   DevStatus* st = g.st;
@@ -1067,6 +1167,8 @@ __global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* _
   double s[3];
   sum_partials<C::NT, 3>(slot_ptr(g.part, SLOT_P3INIT), nwg_col, MAX_WG, s, red);
   const double rho = s[0], rr = s[1], bb = s[2];
+  const int budget = max_iter - st->itot;
+  const double rr_cap = st->orr_prev;
   const bool incompat = (st->flags & FLAG_INCOMPAT) != 0;
   const bool bad = !isfinite(rr) || !isfinite(bb);
   const bool zero_b = !bad && bb == 0.0;
@@ -1105,8 +1207,8 @@ __global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* _
     st->rr[0] = 1.0;
     st->rr0 = 1.0;
     st->iters = 0;
+    st->budget = budget;
     st->converged = 0;
-    st->outer_done = 0;
     st->conv_at = INT_MAX;
   }
 #pragma unroll
@@ -1130,17 +1232,36 @@ __global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* _
   lds_fft<float, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
+                                                          cx<float>* x32, cx<float>* r32, cx<float>* d32,
+                                                          cx<float>* Gx, cx<float>* Gy, double tol2,
+                                                          double floor_in, int max_iter, int nwg_col) {
+  col_refine_start_body<NY>(g, r64, x64, x32, r32, d32, Gx, Gy, tol2, floor_in, max_iter, nwg_col);
+}
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) kb_col_refine_start(const RefStartArgs* __restrict__ A, double tol2, double floor_in, int max_iter, int nwg_col) {
+  const RefStartArgs& a = A[blockIdx.y];
+  col_refine_start_body<NY>(a.g, (const cd*)a.r64, (cd*)a.x64, (cx<float>*)a.x32, (cx<float>*)a.r32, (cx<float>*)a.d32, (cx<float>*)a.Gx, (cx<float>*)a.Gy, tol2, floor_in, max_iter, nwg_col);
+}
 
 // End of one correction: x64 += ||r|| e32 (status.rscale), then the gradient
-// of the new x64 into the FP64 mixed buffers for the next residual.
+// of the new x64 into the FP64 mixed buffers for the next residual; the
+// correction's FP32 iterations are added to the total.  No-op for a finished
+// solve.
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
+__device__ __forceinline__ void col_refine_acc_body(Geo g, cd* x64, const cx<float>* __restrict__ x32,
                                                         cd* Gx, cd* Gy) {
   using C = ColCfg<NY, 2>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
+  if (g.st->outer_done) return;
   const double sc = g.st->rscale;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    g.st->itot += g.st->iters;
+    g.st->orr_prev = g.st->orr;
+  }
   cd xv[C::EP];
   cx<float> ev[C::EP];
   colP_gload<NY, 2>(xv, x64, kx0, g.h);
@@ -1161,13 +1282,23 @@ __global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, cons
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
+                                                        cd* Gx, cd* Gy) {
+  col_refine_acc_body<NY>(g, x64, x32, Gx, Gy);
+}
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) kb_col_refine_acc(const RefAccArgs* __restrict__ A) {
+  const RefAccArgs& a = A[blockIdx.y];
+  col_refine_acc_body<NY>(a.g, (cd*)a.x64, (const cx<float>*)a.x32, (cd*)a.Gx, (cd*)a.Gy);
+}
 
 // Diffusion: forward y transform, multiply by exp(-D^2 |xi|^2 dt) / n (the
 // packed column is unpacked into its kx = 0 and kx = Nx/2 halves for this),
 // inverse y transform; both components batched.  Optional partial sum
 // w |xi_tilde|^2 |m_hat_new|^2.
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
+__device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
   using C = ColCfg<NY, 2>;
   __shared__ cd buf[C::NB * C::LS];
   __shared__ double red[1 * (C::NT / 64)];
@@ -1227,6 +1358,15 @@ __global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, dou
     block_sum<C::NT, 1>(s, red);
     write_partials<C::NT>(eslot, s, 1);
   }
+}
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
+  col_heat_body<NY>(g, Mx, My, D2dt, eslot);
+}
+template <int NY>
+__global__ void __launch_bounds__(2 * TPF) kb_col_heat(const HeatArgs* __restrict__ A) {
+  const HeatArgs& a = A[blockIdx.y];
+  col_heat_body<NY>(a.g, (cd*)a.Mx, (cd*)a.My, a.D2dt, (double*)a.eslot);
 }
 
 // Adjoint right-hand side: b_hat = Pi F(G^T v) = -i xi_tilde . F(v) for the
@@ -1486,14 +1626,13 @@ hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const
   return hipGetLastError();
 }
 hipError_t launch_col_refine_start(const Geo& g, const void* r64, void* x64, void* x32, void* r32, void* d32,
-                                   void* Gx, void* Gy, double tol2, double floor_in, int budget, double rr_cap,
-                                   hipStream_t s) {
+                                   void* Gx, void* Gy, double tol2, double floor_in, int max_iter, hipStream_t s) {
   typedef cx<float> cf;
   const dim3 grid(col_nwg(g)), blk(2 * TPF);
   const int nwg = col_nwg(g);
 #define L_(N)                                                                                                 \
   hipLaunchKernelGGL(k_col_refine_start<N>, grid, blk, 0, s, g, (const cd*)r64, (cd*)x64, (cf*)x32, (cf*)r32,  \
-                     (cf*)d32, (cf*)Gx, (cf*)Gy, tol2, floor_in, budget, rr_cap, nwg)
+                     (cf*)d32, (cf*)Gx, (cf*)Gy, tol2, floor_in, max_iter, nwg)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();
@@ -1516,6 +1655,128 @@ hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* eslot, hipStream_t s) {
   const dim3 grid(col_nwg(g)), blk(2 * TPF);
 #define L_(N) hipLaunchKernelGGL(k_col_gradnorm<N>, grid, blk, 0, s, g, (const cd*)Mx, (const cd*)My, eslot)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched launchers
+hipError_t launchb_status_reset(DevStatus* st0, int count, int full, hipStream_t s) {
+  hipLaunchKernelGGL(kb_status_reset, dim3(count), dim3(64), 0, s, st0, full);
+  return hipGetLastError();
+}
+hipError_t launchb_sum_slot(const SumArgs* A, int count, int K, int n, int o, hipStream_t s) {
+  hipLaunchKernelGGL(kb_sum_slot, dim3(1, count), dim3(256), 0, s, A, K, n, o);
+  return hipGetLastError();
+}
+hipError_t launchb_row_r2c(const Geo& g, const RowR2cArgs* A, int count, hipStream_t s) {
+  const dim3 grid(row_nwg(g), count), blk(TPF);
+#define L_(N) hipLaunchKernelGGL(kb_row_r2c<N>, grid, blk, 0, s, A)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_col_fwd(const Geo& g, const ColFwdArgs* A, int count, int mode, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+#define L_(N) hipLaunchKernelGGL(kb_col_fwd<N>, grid, blk, 0, s, A, mode)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_col_grad(const Geo& g, const ColGradArgs* A, int count, bool grad, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count);
+  if (grad) {
+#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, true>), grid, dim3(2 * TPF), 0, s, A)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  } else {
+#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, false>), grid, dim3(TPF), 0, s, A)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  }
+  return hipGetLastError();
+}
+hipError_t launchb_row_flux(const Geo& g, bool f32, const FluxArgs* A, int count, int it, double tol2,
+                            hipStream_t s) {
+  const dim3 grid(row_nwg(g), count), blk(2 * TPF);
+  const int nwg_col = col_nwg(g);
+  if (f32) {
+#define L_(N) hipLaunchKernelGGL((kb_row_flux<N, float>), grid, blk, 0, s, A, it, nwg_col, tol2)
+    NF_DISPATCH(g.nx, L_)
+#undef L_
+  } else {
+#define L_(N) hipLaunchKernelGGL((kb_row_flux<N, double>), grid, blk, 0, s, A, it, nwg_col, tol2)
+    NF_DISPATCH(g.nx, L_)
+#undef L_
+  }
+  return hipGetLastError();
+}
+hipError_t launchb_col_div(const Geo& g, bool f32, bool init, const DivArgs* A, int count, int it, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const int nwg_row = row_nwg(g);
+  if (init) {
+#define L_(N) hipLaunchKernelGGL((kb_col_div<N, true, double>), grid, blk, 0, s, A, it, nwg_row)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  } else if (f32) {
+#define L_(N) hipLaunchKernelGGL((kb_col_div<N, false, float>), grid, blk, 0, s, A, it, nwg_row)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  } else {
+#define L_(N) hipLaunchKernelGGL((kb_col_div<N, false, double>), grid, blk, 0, s, A, it, nwg_row)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  }
+  return hipGetLastError();
+}
+hipError_t launchb_col_update(const Geo& g, bool f32, const UpdArgs* A, int count, int first, int it, int max_iter,
+                              double tol2, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const int nwg = col_nwg(g);
+  if (f32) {
+#define L_(N) hipLaunchKernelGGL((kb_col_update<N, float>), grid, blk, 0, s, A, 0, it, max_iter, tol2, nwg)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  } else {
+#define L_(N) hipLaunchKernelGGL((kb_col_update<N, double>), grid, blk, 0, s, A, first, it, max_iter, tol2, nwg)
+    NF_DISPATCH(g.ny, L_)
+#undef L_
+  }
+  return hipGetLastError();
+}
+hipError_t launchb_row_split(const Geo& g, const SplitArgs* A, int count, hipStream_t s) {
+  const dim3 grid(row_nwg(g), count), blk(3 * TPF);
+#define L_(N) hipLaunchKernelGGL(kb_row_split<N>, grid, blk, 0, s, A)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_col_heat(const Geo& g, const HeatArgs* A, int count, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+#define L_(N) hipLaunchKernelGGL(kb_col_heat<N>, grid, blk, 0, s, A)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_row_final(const Geo& g, const FinalArgs* A, int count, hipStream_t s) {
+  const dim3 grid(row_nwg(g), count), blk(2 * TPF);
+#define L_(N) hipLaunchKernelGGL(kb_row_final<N>, grid, blk, 0, s, A)
+  NF_DISPATCH(g.nx, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_col_refine_start(const Geo& g, const RefStartArgs* A, int count, double tol2, double floor_in,
+                                    int max_iter, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const int nwg = col_nwg(g);
+#define L_(N) hipLaunchKernelGGL(kb_col_refine_start<N>, grid, blk, 0, s, A, tol2, floor_in, max_iter, nwg)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipGetLastError();
+}
+hipError_t launchb_col_refine_acc(const Geo& g, const RefAccArgs* A, int count, hipStream_t s) {
+  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+#define L_(N) hipLaunchKernelGGL(kb_col_refine_acc<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();

@@ -98,12 +98,22 @@ def _load():
     lib.nf_set_inner_tolerance.argtypes = [vp, dp]
     lib.nf_time_kernel.argtypes = [vp, ctypes.c_int]
     lib.nf_time_kernel_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.nf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_int, vp]
+    lib.nf_batch_destroy.argtypes = [vp]
+    lib.nf_batch_set_stream.argtypes = [vp, vp]
+    lib.nf_batch_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, ctypes.POINTER(vp),
+                                 ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ctypes.c_int,
+                                 ctypes.POINTER(nf_run_info)]
+    lib.nf_batch_last_error.argtypes = [vp]
+    lib.nf_batch_last_error.restype = ctypes.c_char_p
     lib.nf_last_error.argtypes = [vp]
     lib.nf_last_error.restype = ctypes.c_char_p
     lib.nf_version.restype = ctypes.c_char_p
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
-              "nf_time_kernel_read"):
+              "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_batch_create", "nf_batch_destroy",
+              "nf_batch_set_stream", "nf_batch_run"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -310,6 +320,72 @@ class Grid:
                                            _ptr(p, self.sshape, "p"), _ptr(out, self.sshape, "out")))
 
 
+def _ri(x):
+    return RunInfo(int(x.steps), int(x.stop_reason), float(x.last_dm), float(x.last_energy), float(x.prev_energy),
+                   int(x.total_cg_iters), int(x.unconverged_solves))
+
+
+class Batch:
+    """An ensemble handle (``nf_batch_create``): independent instances with
+    their own grid sizes (Nx, Ny) and boxes, advanced together by
+    ``nf_batch_run``."""
+
+    def __init__(self, shapes, L=None, dtype=NF_F64):
+        shapes = [tuple(int(v) for v in n) for n in shapes]
+        if not shapes or any(len(n) != 2 for n in shapes):
+            raise ValueError("a non-empty list of 2D grid shapes is required")
+        L = [(1.0, 1.0)] * len(shapes) if L is None else [tuple(float(v) for v in l) for l in L]
+        if len(L) != len(shapes):
+            raise ValueError("one box per instance")
+        self.shapes, self.L, self.count = shapes, L, len(shapes)
+        nn = (ctypes.c_int64 * (2 * self.count))(*[v for n in shapes for v in n])
+        LL = (ctypes.c_double * (2 * self.count))(*[v for l in L for v in l])
+        self._h = ctypes.c_void_p()
+        rc = _lib.nf_batch_create(ctypes.byref(self._h), self.count, nn, LL, int(dtype), _current_stream())
+        if rc != NF_OK:
+            raise NfError(rc, "nf_batch_create failed: %s" % _lib.nf_batch_last_error(None).decode())
+
+    def close(self):
+        if self._h:
+            _lib.nf_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def run(self, params, dt, steps, m, p, r, S, rtol=1e-10, max_iter=1000):
+        """nf_batch_run: params is a list of (c2, D2, gamma); m, p, r, S lists of
+        device tensors (one per instance, shapes as for Grid.run).  Returns the
+        list of RunInfo."""
+        c = self.count
+        if not (len(params) == len(m) == len(p) == len(r) == len(S) == c):
+            raise ValueError("one entry per instance is required")
+        _lib.nf_batch_set_stream(self._h, _current_stream())
+        prm = (nf_params * c)(*[nf_params(float(a), float(b), float(g)) for a, b, g in params])
+        ptrs = []
+        for name, lst, vec in (("m", m, True), ("p", p, False), ("r", r, False), ("S", S, False)):
+            arr = (ctypes.c_void_p * c)()
+            for i, t in enumerate(lst):
+                nx, ny = self.shapes[i]
+                arr[i] = _ptr(t, (2, ny, nx) if vec else (ny, nx), "%s[%d]" % (name, i)).value
+            ptrs.append(arr)
+        info = (nf_run_info * c)()
+        rc = _lib.nf_batch_run(self._h, prm, float(dt), int(steps), ptrs[0], ptrs[1], ptrs[2], ptrs[3], float(rtol),
+                               int(max_iter), info)
+        if rc != NF_OK:
+            raise NfError(rc, _lib.nf_batch_last_error(self._h).decode())
+        return [_ri(x) for x in info]
+
+
 # C-ABI-named aliases ------------------------------------------------------------
 def nf_create_grid(n, L=(1.0, 1.0), dtype=NF_F64):
     return Grid(n, L, dtype)
@@ -343,3 +419,15 @@ def nf_step_adjoint(g, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, g
 
 def nf_set_inner_tolerance(g, floor_rtol):
     g.set_inner_tolerance(floor_rtol)
+
+
+def nf_batch_create(shapes, L=None, dtype=NF_F64):
+    return Batch(shapes, L, dtype)
+
+
+def nf_batch_destroy(b):
+    b.close()
+
+
+def nf_batch_run(b, params, dt, steps, m, p, r, S, rtol=1e-10, max_iter=1000):
+    return b.run(params, dt, steps, m, p, r, S, rtol, max_iter)

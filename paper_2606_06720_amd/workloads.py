@@ -146,6 +146,41 @@ def dipole_workload(N=1024, gamma=0.75, seed_r=1, seed_m0=2, ndim=2):
     )
 
 
+ENSEMBLE_MIX = ((256, 16), (512, 32), (1024, 16))
+
+
+def ensemble_workload(mix=ENSEMBLE_MIX, seed0=1000):
+    """Ensemble of independent instances: for each (N, count) in `mix`, `count`
+    instances on an N x N grid, instance i (numbered across the mix) drawing
+    from default_rng(seed0 + i): first the smooth random field of r (as in
+    dipole_workload), then m0, then c^2 log-uniform in [5, 100], D^2
+    log-uniform in [1e-5, 1e-3] and gamma uniform in [0.5, 1.25].  S is the
+    Gaussian source/sink pair of dipole_workload.  dt = 5e-4, 500 steps,
+    relative PCG tolerance 1e-10.  Returns a list of per-instance dicts with
+    keys n, L, r, S, m0, c2, D2, gamma.
+    """
+    out = []
+    i = 0
+    for N, count in mix:
+        n = (N, N)
+        X = grid_coords(n, 1.0)
+        S = gaussian(X, (0.25, 0.5), 0.02) - gaussian(X, (0.75, 0.5), 0.02)
+        S = np.ascontiguousarray(S - S.mean())
+        for _ in range(count):
+            rng = np.random.default_rng(seed0 + i)
+            r = 0.05 + 0.05 * smooth_random_field(rng, n, 1.0)
+            m0 = _uniform_m0(rng, n)
+            c2 = float(np.exp(rng.uniform(np.log(5.0), np.log(100.0))))
+            D2 = float(np.exp(rng.uniform(np.log(1e-5), np.log(1e-3))))
+            gamma = float(rng.uniform(0.5, 1.25))
+            out.append(dict(n=n, L=(1.0, 1.0), r=np.ascontiguousarray(r), S=S, m0=m0, c2=c2, D2=D2, gamma=gamma))
+            i += 1
+    return out
+
+
+ENSEMBLE_RUN = dict(dt=5e-4, steps=500, rtol=1e-10)
+
+
 # ---- analytic data printed in the paper (Sec. 3.1-3.3) --------------------------------
 
 def paper_m_A(N, factor=1.0e4):
