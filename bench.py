@@ -33,6 +33,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
 #   col_update: reads x, d, r, q (32); writes x, r, d (24) and grad_x, grad_y (16)
 KERNEL_BYTES_PER_POINT = {"row_flux": 56.0, "col_div": 40.0, "col_update": 72.0}
 KERNEL_IDS = {"row_flux": 0, "col_div": 1, "col_update": 2}
+# algorithmic bytes per grid point of the passes of one time step outside the
+# PCG loop: gradient of the warm start (24), initial operator apply (56 + 32),
+# first update (32), split: p and gradient (16 + 24), activation/relaxation
+# pass (64), heat multiplier (32), final row pass with Delta m (48)
+STEP_BYTES_PER_POINT = 328.0
 KERNEL_SOURCES = ("paper_2606_06720_amd/csrc/nf_kernels.hip", "paper_2606_06720_amd/csrc/nf_fft.hpp")
 
 
@@ -156,6 +161,107 @@ def adjoint_cost(N, steps):
     }
 
 
+def precision_form(sizes, steps, warmup=3):
+    """FP64 and FP32-refined pressure solves on the same GPU: ms per time step
+    of the dipole case (gamma 0.75) at each size, and the relative L2
+    difference of m and p after the same steps from the same state (the FP64
+    form is held to the oracle at 1e-10)."""
+    import numpy as np
+    import torch
+
+    from paper_2606_06720_amd import nf as NF
+    from paper_2606_06720_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = {}
+    for N in sizes:
+        w = W.dipole_workload(N, 0.75)
+        res = {}
+        for dt_, name in ((NF.NF_F64, "f64"), (NF.NF_F32_REFINED, "f32_refined")):
+            m, r, S = T(w["m0"]), T(w["r"]), T(w["S"])
+            p = torch.zeros_like(r)
+            with NF.Grid(w["n"], w["L"], dtype=dt_) as g:
+                g.run(w["c2"], w["D2"], w["gamma"], w["dt"], warmup, m, p, r, S, rtol=w["rtol"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = g.run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, m, p, r, S, rtol=w["rtol"])
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            res[name] = dict(ms_per_step=1e3 * t / steps, pcg_iters_per_step=info.total_cg_iters / steps,
+                             m=m.cpu().numpy(), p=p.cpu().numpy())
+            del m, r, S, p
+            torch.cuda.empty_cache()
+        a, b = res["f32_refined"], res["f64"]
+        out["%d^2" % N] = {
+            "f64_ms_per_step": b["ms_per_step"],
+            "f32_refined_ms_per_step": a["ms_per_step"],
+            "speedup": b["ms_per_step"] / a["ms_per_step"],
+            "f64_pcg_iters_per_step": b["pcg_iters_per_step"],
+            "f32_inner_iters_per_step": a["pcg_iters_per_step"],
+            "rel_diff_m": float(np.linalg.norm(a["m"] - b["m"]) / np.linalg.norm(b["m"])),
+            "rel_diff_p": float(np.linalg.norm(a["p"] - b["p"]) / np.linalg.norm(b["p"])),
+        }
+    return {"workload": "dipole case, gamma 0.75, PCG rtol 1e-10, %d steps after %d" % (steps, warmup),
+            "sizes": out}
+
+
+def ensemble_cost(steps, mix=None):
+    """The ensemble of independent instances (grid mix as given) advanced by one
+    batch (nf_batch_run) against the same instances run one after another
+    (nf_run), FP64 and FP32-refined, from the same states."""
+    import numpy as np
+    import torch
+
+    from paper_2606_06720_amd import nf as NF
+    from paper_2606_06720_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inst = W.ensemble_workload(mix or W.ENSEMBLE_MIX)
+    npts = sum(w["n"][0] * w["n"][1] for w in inst)
+    prm = [(w["c2"], w["D2"], w["gamma"]) for w in inst]
+    dt = W.ENSEMBLE_RUN["dt"]
+    rtol = W.ENSEMBLE_RUN["rtol"]
+    out = {"workload": "%d instances %s, per-instance (c2, D2, gamma) draws, dt %g, rtol %g, %d steps after 2"
+                       % (len(inst), [list(x) for x in (mix or W.ENSEMBLE_MIX)], dt, rtol, steps)}
+    rs = [T(w["r"]) for w in inst]
+    Ss = [T(w["S"]) for w in inst]
+    for dt_, name in ((NF.NF_F64, "f64"), (NF.NF_F32_REFINED, "f32_refined")):
+        ms = [T(w["m0"]) for w in inst]
+        ps = [torch.zeros_like(x) for x in rs]
+        with NF.Batch([w["n"] for w in inst], dtype=dt_) as b:
+            b.run(prm, dt, 2, ms, ps, rs, Ss, rtol=rtol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = b.run(prm, dt, steps, ms, ps, rs, Ss, rtol=rtol)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+        ms2 = [T(w["m0"]) for w in inst]
+        ps2 = [torch.zeros_like(x) for x in rs]
+        gs = [NF.Grid(w["n"], dtype=dt_) for w in inst]
+        for i, g in enumerate(gs):
+            g.run(*prm[i], dt, 2, ms2[i], ps2[i], rs[i], Ss[i], rtol=rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, g in enumerate(gs):
+            g.run(*prm[i], dt, steps, ms2[i], ps2[i], rs[i], Ss[i], rtol=rtol)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for g in gs:
+            g.close()
+        out[name] = {
+            "batch_grid_point_steps_per_s": npts * steps / tb,
+            "one_by_one_grid_point_steps_per_s": npts * steps / ts,
+            "batch_speedup": ts / tb,
+            "bitwise_equal_to_one_by_one": all(torch.equal(a, c) for a, c in zip(ms, ms2)),
+            "pcg_iters_per_solve": sum(i.total_cg_iters for i in infos) / (len(inst) * steps),
+        }
+        del ms, ps, ms2, ps2
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(nbytes):
     """A plain device-to-device copy of known size, for scaling HBM counters."""
     import torch
@@ -180,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the reverse-mode cost run (0 = skip)")
     ap.add_argument("--sequential", action="store_true", help="run the instances one after another on one stream")
+    ap.add_argument("--precision-steps", type=int, default=10, help="steps per form of the precision comparison (0 = skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=20, help="steps of the ensemble comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     args = ap.parse_args()
 
@@ -263,6 +371,7 @@ def main():
     alg_bytes = KERNEL_BYTES_PER_POINT[args.kernel] * N * N
     achieved = alg_bytes / avg_s / 1e9 if kcount else None
     traffic = load_traffic(args.kernel, N)
+    step_bytes = (sum(KERNEL_BYTES_PER_POINT.values()) * cg_iters + STEP_BYTES_PER_POINT * len(GAMMAS) * args.steps) * N * N
     roofline = {
         "bound": "hbm",
         "kernel": args.kernel,
@@ -274,6 +383,9 @@ def main():
         "algorithmic_bytes_per_launch": alg_bytes,
         "avg_launch_us": avg_s * 1e6,
         "launches": kcount,
+        # all passes of the timed steps: algorithmic bytes over the wall time
+        "step_achieved": step_bytes / elapsed / 1e9,
+        "step_frac": step_bytes / elapsed / 1e9 / HBM_PEAK_GBS,
     }
     finite = all(torch.isfinite(it["m"]).all().item() for it in inst)
 
@@ -304,6 +416,10 @@ def main():
     }
     if args.adjoint_steps > 0:
         out["adjoint_cost"] = adjoint_cost(N, args.adjoint_steps)
+    if args.precision_steps > 0:
+        out["precision_form"] = precision_form((N, 4096), args.precision_steps)
+    if args.ensemble_steps > 0:
+        out["ensemble"] = ensemble_cost(args.ensemble_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
     for it in inst:
