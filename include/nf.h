@@ -95,15 +95,21 @@ typedef struct {
 } nf_run_info;
 
 /*
- * Create a solver handle for a 2D periodic grid.
- *   ndim    must be 2;
- *   n       grid sizes (Nx, Ny[, unused]), powers of two in [8, 4096];
- *   L       box lengths (Lx, Ly[, unused]), > 0;
+ * Create a solver handle for a 2D or 3D periodic grid (the scheme is the same
+ * in 3D, with m in R^3 and the 3x3 tensor m m^T + r I; Sec. 2 and Sec. 5).
+ *   ndim    2 or 3;
+ *   n       grid sizes (Nx, Ny[, Nz]), powers of two in [8, 4096] (2D) or
+ *           [8, 1024] (3D);
+ *   L       box lengths (Lx, Ly[, Lz]), > 0;
  *   dtype   NF_F64 or NF_F32_REFINED;
  *   stream  hipStream_t to enqueue on (NULL = default stream).
- * Allocates the workspace (8 complex half-spectrum fields plus tables; with
- * NF_F32_REFINED also 6 single-precision half-spectrum fields and FP32 copies
- * of m and r) on the current HIP device.  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
+ * Allocates the workspace (8 complex half-spectrum fields plus tables, 9 in
+ * 3D; with NF_F32_REFINED also 6 (3D: 7) single-precision half-spectrum
+ * fields and FP32 copies of m and r) on the current HIP device.
+ * Layouts of the caller's fields: 2D p, r, S [Ny][Nx], m [2][Ny][Nx]; 3D
+ * p, r, S [Nz][Ny][Nx], m [3][Nz][Ny][Nx]; x fastest.  On 3D handles
+ * nf_energy, the energy stopping of nf_run and nf_step_adjoint return
+ * NF_EINVAL (they are implemented for 2D grids only).  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
  * (*out is then NULL).
  */
 int nf_create_grid(nf_grid **out, int ndim, const int64_t n[3], const double L[3], int dtype, void *stream);
@@ -212,7 +218,9 @@ int nf_step_adjoint(nf_grid *g, const nf_params *prm, double dt, const double *m
  *   complex (interleaved re, im; 2 * Nx/2 * Ny doubles), entry [kx][ky] =
  *   F(kx, ky) for 1 <= kx < Nx/2, and column kx = 0 holds
  *   F(0, ky) + i F(Nx/2, ky) (both columns are spectra of real sequences).
- * nf_transform_inverse: f = inverse DFT (normalised by 1/(Nx Ny)) of a packed
+ *   3D: out is [Nx/2][Ny][Nz] complex, entry [kx][ky][kz] = F(kx, ky, kz) for
+ *   1 <= kx < Nx/2 and slot kx = 0 holds F(0, ky, kz) + i F(Nx/2, ky, kz).
+ * nf_transform_inverse: f = inverse DFT (normalised by 1/n) of a packed
  *   half spectrum in the same layout.
  * nf_apply_operator: out = A p, the left-hand side of eq. p_discrete for the
  *   given m and r, p [Ny][Nx], out [Ny][Nx].

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnf.so")
 
-SOURCES = ["nf_kernels.hip", "nf_api.cpp", "nf_batch.cpp"]
+SOURCES = ["nf_kernels.hip", "nf_kernels3d.hip", "nf_api.cpp", "nf_batch.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -38,13 +38,18 @@ def build(verbose=False):
     objs = []
     cc = hipcc()
     tmp = LIB + ".tmp"
+    procs = []
+    # the translation units are independent: compile them concurrently
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    for pr, cmd in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -85,6 +85,12 @@ int read_status(nf_grid* g, DevStatus* dst) {
 // b_hat = F(Pi S) and the compatibility partials of S
 int compute_rhs(nf_grid* g, const double* S) {
   const Geo& G = g->geo;
+  if (g->dim == 3) {
+    LCHK(g, launch3_row_r2c(G, S, g->mix[0], 1, g->stream));
+    LCHK(g, launch3_ypass(G, false, 1, -1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, g->stream));
+    LCHK(g, launch3_zfwd(G, g->mix[0], g->bh, 1, g->stream));
+    return NF_OK;
+  }
   LCHK(g, launch_row_r2c(G, S, g->mix[0], slot_ptr(g->part, SLOT_SCHK), g->stream));
   LCHK(g, launch_col_fwd(G, g->mix[0], g->bh, 0, nullptr, nullptr, g->stream));
   return NF_OK;
@@ -133,10 +139,19 @@ struct SolveOut {
 
 // Operator apply on the current iterate x_hat: leaves r_hat = b_hat - A x_hat,
 // partials <r,M^-1 r>, <r,r>, <b,b> in SLOT_P3INIT and Kbar in the status.
-int init_residual(nf_grid* g, const double* m, const double* r) {
+// lo: also write the FP32 copies of m and r (mixed-precision solve).
+int init_residual(nf_grid* g, const double* m, const double* r, float* lo = nullptr) {
   const Geo& G = g->geo;
-  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, g->stream));
-  LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), g->stream));
+  hipStream_t s = g->stream;
+  if (g->dim == 3) {
+    LCHK(g, launch3_row_flux(G, false, g->mix[0], g->mix[1], g->mix[2], m, r, -1, 1, lo, s));
+    LCHK(g, launch3_ypass(G, false, 3, -1, g->mix[0], g->mix[1], g->mix[2], nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_zdiv(G, false, 1, g->mix[0], g->mix[1], g->mix[2], g->qh, g->dh, g->rh, g->bh, 0, s));
+    return NF_OK;
+  }
+  LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, s, nullptr, nullptr,
+                          lo));
+  LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), s));
   return NF_OK;
 }
 
@@ -150,7 +165,7 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
              DevStatus* fin) {
   const Geo& G = f32 ? g->geo32 : g->geo;
   hipStream_t s = g->stream;
-  const size_t n = (size_t)g->nx * g->ny;
+  const size_t n = (size_t)g->nx * g->ny * g->nz;
   int rc = NF_OK;
   g->pool_used = 0;
   int it = 0;
@@ -162,6 +177,22 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
     if (nk > max_iter - it) nk = max_iter - it;
     for (int k = 0; k < nk; ++k) {
       hipEvent_t e0, e1;
+      if (g->dim == 3) {
+        void* const* F = f32 ? g->mix32 : g->mix;
+        LCHK(g, launch3_ypass(G, f32, 3, +1, F[0], F[1], F[2], nullptr, it, 1, tol2, -1.0, s));
+        if ((rc = timed_events(g, NF_KERNEL_ROW_FLUX, it, &e0, &e1))) return rc;
+        LCHK(g, launch3_row_flux(G, f32, F[0], F[1], F[2], f32 ? (const void*)g->lo : (const void*)m,
+                                 f32 ? (const void*)(g->lo + 3 * n) : (const void*)r, it, 0, nullptr, s, e0, e1));
+        LCHK(g, launch3_ypass(G, f32, 3, -1, F[0], F[1], F[2], nullptr, it, 0, 0.0, -1.0, s));
+        if ((rc = timed_events(g, NF_KERNEL_COL_DIV, it, &e0, &e1))) return rc;
+        LCHK(g, launch3_zdiv(G, f32, 0, F[0], F[1], F[2], f32 ? g->q32 : g->qh, f32 ? g->d32 : g->dh,
+                             f32 ? g->r32 : g->rh, g->bh, it, s, e0, e1));
+        if ((rc = timed_events(g, NF_KERNEL_COL_UPDATE, it, &e0, &e1))) return rc;
+        LCHK(g, launch3_zupdate(G, f32, 0, f32 ? g->x32 : g->xh, f32 ? g->r32 : g->rh, f32 ? g->d32 : g->dh,
+                                f32 ? g->q32 : g->qh, F[0], F[1], F[2], it + 1, max_iter, tol2, s, e0, e1));
+        ++it;
+        continue;
+      }
       if ((rc = timed_events(g, NF_KERNEL_ROW_FLUX, it, &e0, &e1))) return rc;
       if (f32)
         LCHK(g, launch_row_flux32(G, g->mix32[0], g->mix32[1], g->lo, g->lo + 2 * n, it, tol2, s, e0, e1));
@@ -201,11 +232,45 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
   return NF_OK;
 }
 
+// 3D: gradient of x_hat through the inverse z and y transforms into mix[0..2]
+int grad_to_mixed3(nf_grid* g) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  LCHK(g, launch3_zinv(G, 2, g->xh, nullptr, g->mix[0], g->mix[1], g->mix[2], s));
+  LCHK(g, launch3_ypass(G, false, 3, +1, g->mix[0], g->mix[1], g->mix[2], nullptr, -1, 0, 0.0, -1.0, s));
+  return NF_OK;
+}
+
+// p = F^-1 x_hat
+int write_p(nf_grid* g, double* p) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  if (g->dim == 3) {
+    LCHK(g, launch3_zinv(G, 1, g->xh, g->mix[0], nullptr, nullptr, nullptr, s));
+    LCHK(g, launch3_ypass(G, false, 1, +1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_row_c2r(G, g->mix[0], p, s));
+    return NF_OK;
+  }
+  LCHK(g, launch_col_grad(G, g->xh, g->mix[0], nullptr, nullptr, s));
+  LCHK(g, launch_row_c2r(G, g->mix[0], p, s));
+  return NF_OK;
+}
+
 // Initial iterate x_hat from p (X_FROM_P), kept (X_FROM_XH) or zero, and its
 // gradient in the mixed buffers for the first operator pass.
 int prepare_iterate(nf_grid* g, XSource src, const double* p) {
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
+  if (g->dim == 3) {
+    if (src == X_FROM_P) {
+      LCHK(g, launch3_row_r2c(G, p, g->mix[0], 0, s));
+      LCHK(g, launch3_ypass(G, false, 1, -1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+      LCHK(g, launch3_zfwd(G, g->mix[0], g->xh, 1, s));
+    } else if (src == X_ZERO) {
+      LCHK(g, launch_zero_spec(G, g->xh, s));
+    }
+    return grad_to_mixed3(g);
+  }
   if (src == X_FROM_P) {
     LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
     LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
@@ -236,18 +301,26 @@ int pcg_refined(nf_grid* g, const double* m, const double* r, XSource src, const
   DevStatus fin;
   for (int outer = 0;; ++outer) {
     // FP64 residual r = b - A x (and, on the first pass, the FP32 copies of m, r)
-    LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, slot_ptr(g->part, SLOT_KBAR), 0.0, s, nullptr,
-                            nullptr, outer == 0 ? g->lo : nullptr));
-    LCHK(g, launch_col_div(G, 1, g->mix[0], g->mix[1], g->qh, g->dh, g->rh, g->bh, 0, row_nwg(G), s));
-    LCHK(g, launch_col_refine_start(g->geo32, g->rh, g->xh, g->x32, g->r32, g->d32, g->mix32[0], g->mix32[1], tol2,
-                                    g->inner_floor, max_iter, s));
+    rc = init_residual(g, m, r, outer == 0 ? g->lo : nullptr);
+    if (rc) return rc;
+    if (g->dim == 3)
+      LCHK(g, launch3_zrefine_start(g->geo32, g->rh, g->xh, g->x32, g->r32, g->d32, g->mix32[0], g->mix32[1],
+                                    g->mix32[2], tol2, g->inner_floor, max_iter, s));
+    else
+      LCHK(g, launch_col_refine_start(g->geo32, g->rh, g->xh, g->x32, g->r32, g->d32, g->mix32[0], g->mix32[1],
+                                      tol2, g->inner_floor, max_iter, s));
     const int slot = outer < 3 ? outer : 3;
     rc = pcg_loop(g, true, m, r, max_iter, 1.0, g->last_inner[slot], &fin);
     if (rc) return rc;
     if (fin.outer_done) break;
     if (fin.iters > 0) g->last_inner[slot] = fin.iters;
     // x += ||r|| e and the gradient of the new x for the next residual
-    LCHK(g, launch_col_refine_acc(G, g->xh, g->x32, g->mix[0], g->mix[1], s));
+    if (g->dim == 3) {
+      LCHK(g, launch3_zrefine_acc(G, g->xh, g->x32, g->mix[0], g->mix[1], g->mix[2], s));
+      LCHK(g, launch3_ypass(G, false, 3, +1, g->mix[0], g->mix[1], g->mix[2], nullptr, -1, 0, 0.0, -1.0, s));
+    } else {
+      LCHK(g, launch_col_refine_acc(G, g->xh, g->x32, g->mix[0], g->mix[1], s));
+    }
   }
   out->iters = fin.itot;
   out->converged = fin.converged;
@@ -271,13 +344,20 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
   rc = init_residual(g, m, r);
   if (rc) return rc;
   const double tol2 = rtol * rtol;
-  LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
+  if (g->dim == 3)
+    LCHK(g, launch3_zupdate(G, false, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], g->mix[2], 0, max_iter,
+                            tol2, s));
+  else
+    LCHK(g, launch_col_update(G, 1, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], 0, max_iter, tol2, s));
   DevStatus fin;
   rc = pcg_loop(g, false, m, r, max_iter, tol2, g->last_iters, &fin);
   if (rc) return rc;
   if (!fin.converged && fin.conv_at == max_iter && max_iter > 0 && !(fin.flags & (FLAG_NONFINITE | FLAG_INCOMPAT))) {
     // stopped by max_iter: take the stopping test on the final residual here
-    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, col_nwg(G), 11, s));
+    if (g->dim == 3)
+      LCHK(g, launch3_copy_tot(G, SLOT_RR, 1, 11, s));
+    else
+      LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, col_nwg(G), 11, s));
     rc = read_status(g, &fin);
     if (rc) return rc;
     fin.rr[0] = fin.out[11];
@@ -292,10 +372,18 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
   out->true_rel_res = -1.0;
   if (fin.iters > 0 || fin.converged) g->last_iters = fin.iters;
   if (want_true && !(fin.flags & FLAG_INCOMPAT)) {
-    LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+    if (g->dim == 3) {
+      rc = grad_to_mixed3(g);
+      if (rc) return rc;
+    } else {
+      LCHK(g, launch_col_grad(G, g->xh, nullptr, g->mix[0], g->mix[1], s));
+    }
     rc = init_residual(g, m, r);
     if (rc) return rc;
-    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_P3INIT), 3, col_nwg(G), 0, s));
+    if (g->dim == 3)
+      LCHK(g, launch3_copy_tot(G, SLOT_P3INIT, 3, 0, s));
+    else
+      LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_P3INIT), 3, col_nwg(G), 0, s));
     DevStatus t;
     rc = read_status(g, &t);
     if (rc) return rc;
@@ -332,10 +420,32 @@ int solve_status_code(nf_grid* g, const SolveOut& so) {
 int split_update(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, bool egm) {
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
+  if (g->dim == 3) {
+    void* const* M = g->mix;
+    const double D2dt = prm->D2 * dt;
+    LCHK(g, launch3_zinv(G, 3, g->xh, M[0], M[1], M[2], M[3], s));
+    LCHK(g, launch3_ypass(G, false, 4, +1, M[0], M[1], M[2], M[3], -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_row_split(G, M[0], M[1], M[2], M[3], m, p, prm->c2 * dt, prm->gamma, dt, std::exp(-dt), D2dt, s));
+    LCHK(g, launch3_ypass(G, false, 3, -1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, D2dt, s));
+    LCHK(g, launch3_zheat(G, M[0], M[1], M[2], D2dt, s));
+    LCHK(g, launch3_ypass(G, false, 3, +1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_row_final(G, M[0], M[1], M[2], m, s));
+    return NF_OK;
+  }
   LCHK(g, launch_col_grad(G, g->xh, g->mix[0], g->mix[1], g->mix[2], s));
   LCHK(g, launch_row_split(G, g->mix[0], g->mix[1], g->mix[2], m, p, prm->c2 * dt, prm->gamma, dt, std::exp(-dt), s));
   LCHK(g, launch_col_heat(G, g->mix[0], g->mix[1], prm->D2 * dt, egm ? slot_ptr(g->part, SLOT_EGM) : nullptr, s));
   LCHK(g, launch_row_final(G, g->mix[0], g->mix[1], m, slot_ptr(g->part, SLOT_DM), s));
+  return NF_OK;
+}
+
+// partials of Delta m of the last split update into status.out[8..9]
+int dm_to_status(nf_grid* g) {
+  if (g->dim == 3) {
+    LCHK(g, launch3_copy_tot(g->geo, SLOT_DM, 2, 8, g->stream));
+  } else {
+    LCHK(g, launch_sum_slot(g->geo, slot_ptr(g->part, SLOT_DM), 2, row_nwg(g->geo), 8, g->stream));
+  }
   return NF_OK;
 }
 
@@ -384,15 +494,22 @@ int nf_set_stream(nf_grid* g, void* stream) {
 int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3], int dtype, void* stream) {
   if (!out) return NF_EINVAL;
   *out = nullptr;
-  if (ndim != 2 || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) return NF_EINVAL;
-  if (!is_pow2_in_range(n[0]) || !is_pow2_in_range(n[1])) return NF_EINVAL;
-  if (!(L[0] > 0.0) || !(L[1] > 0.0)) return NF_EINVAL;
+  if ((ndim != 2 && ndim != 3) || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) return NF_EINVAL;
+  if (ndim == 2 && (!is_pow2_in_range(n[0]) || !is_pow2_in_range(n[1]))) return NF_EINVAL;
+  if (ndim == 3)
+    for (int c = 0; c < 3; ++c)
+      if (!is_pow2_in_range(n[c]) || n[c] > 1024) return NF_EINVAL;
+  for (int c = 0; c < ndim; ++c)
+    if (!(L[c] > 0.0)) return NF_EINVAL;
   nf_grid* g = new nf_grid();
+  g->dim = ndim;
   g->nx = (int)n[0];
   g->ny = (int)n[1];
+  g->nz = ndim == 3 ? (int)n[2] : 1;
   g->h = g->nx / 2;
   g->lx = L[0];
   g->ly = L[1];
+  g->lz = ndim == 3 ? L[2] : 1.0;
   g->stream = (hipStream_t)stream;
   g->dtype = dtype;
   int rc = NF_OK;
@@ -408,13 +525,31 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
     if ((herr = (expr)) != hipSuccess) return bail(code, #expr); \
   } while (0)
   CREATE_CHK(hipGetDevice(&g->device), NF_EDEVICE);
-  const int twn = g->nx > g->ny ? g->nx : g->ny;
+  int twn = g->nx > g->ny ? g->nx : g->ny;
+  if (g->nz > twn) twn = g->nz;
   g->twlog = ilog2i(twn);
-  const size_t spec_bytes = (size_t)g->h * g->ny * 2 * sizeof(double);
-  void** bufs[] = {&g->xh, &g->rh, &g->dh, &g->qh, &g->bh, &g->mix[0], &g->mix[1], &g->mix[2]};
+  const size_t npts = (size_t)g->nx * g->ny * g->nz;
+  const size_t spec_bytes = (size_t)g->h * g->ny * g->nz * 2 * sizeof(double);
+  const int nmix = ndim == 3 ? 4 : 3;
+  void** bufs[] = {&g->xh, &g->rh, &g->dh, &g->qh, &g->bh};
   for (void** b : bufs) CREATE_CHK(hipMalloc(b, spec_bytes), NF_ENOMEM);
+  for (int i = 0; i < nmix; ++i) CREATE_CHK(hipMalloc(&g->mix[i], spec_bytes), NF_ENOMEM);
   CREATE_CHK(hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)), NF_ENOMEM);
-  CREATE_CHK(hipMalloc((void**)&g->part, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_ENOMEM);
+  // partial sums: 2D keeps MAX_WG per array; 3D sizes them to the largest pass
+  // and appends the reduced totals and the arrival counters
+  int pstride = MAX_WG;
+  if (ndim == 3) {
+    Geo tmp{};
+    tmp.nx = g->nx;
+    tmp.ny = g->ny;
+    tmp.nz = g->nz;
+    tmp.h = g->h;
+    pstride = nwg3_row(tmp);
+    if (nwg3_y(tmp) > pstride) pstride = nwg3_y(tmp);
+    if (nwg3_z(tmp) > pstride) pstride = nwg3_z(tmp);
+  }
+  const size_t part_doubles = (size_t)NSLOTS * SLOT_K * pstride + NSLOTS * SLOT_K + NSLOTS;
+  CREATE_CHK(hipMalloc((void**)&g->part, part_doubles * sizeof(double)), NF_ENOMEM);
   CREATE_CHK(hipMalloc((void**)&g->st, sizeof(DevStatus)), NF_ENOMEM);
   g->st_own = g->st;
   CREATE_CHK(hipHostMalloc((void**)&g->hst, 2 * sizeof(DevStatus), hipHostMallocDefault), NF_ENOMEM);
@@ -426,14 +561,15 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
     delete[] h;
     if (herr != hipSuccess) return bail(NF_EDEVICE, "hipMemcpy(twiddles)");
   }
-  CREATE_CHK(hipMemset(g->part, 0, (size_t)NSLOTS * SLOT_K * MAX_WG * sizeof(double)), NF_EDEVICE);
+  CREATE_CHK(hipMemset(g->part, 0, part_doubles * sizeof(double)), NF_EDEVICE);
   CREATE_CHK(hipMemset(g->st, 0, sizeof(DevStatus)), NF_EDEVICE);
   CREATE_CHK(hipMemset(g->xh, 0, spec_bytes), NF_EDEVICE);
   if (dtype == NF_F32_REFINED) {
-    const size_t spec32 = (size_t)g->h * g->ny * 2 * sizeof(float);
-    void** b32[] = {&g->x32, &g->r32, &g->d32, &g->q32, &g->mix32[0], &g->mix32[1]};
+    const size_t spec32 = spec_bytes / 2;
+    void** b32[] = {&g->x32, &g->r32, &g->d32, &g->q32};
     for (void** b : b32) CREATE_CHK(hipMalloc(b, spec32), NF_ENOMEM);
-    CREATE_CHK(hipMalloc((void**)&g->lo, 3 * (size_t)g->nx * g->ny * sizeof(float)), NF_ENOMEM);
+    for (int i = 0; i < ndim; ++i) CREATE_CHK(hipMalloc(&g->mix32[i], spec32), NF_ENOMEM);
+    CREATE_CHK(hipMalloc((void**)&g->lo, (size_t)(ndim + 1) * npts * sizeof(float)), NF_ENOMEM);
     CREATE_CHK(hipMalloc(&g->tw32, (size_t)twn * 2 * sizeof(float)), NF_ENOMEM);
     float* h = new float[2 * (size_t)twn];
     make_twiddles(twn, h);
@@ -449,10 +585,15 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.twlog = g->twlog;
   G.lx = g->lx;
   G.ly = g->ly;
-  G.inv_n = 1.0 / ((double)g->nx * (double)g->ny);
+  G.inv_n = 1.0 / ((double)g->nx * (double)g->ny * (double)g->nz);
   G.tw = g->tw;
   G.st = g->st;
   G.part = g->part;
+  G.nz = g->nz;
+  G.lz = g->lz;
+  G.pstride = pstride;
+  G.tot = g->part + (size_t)NSLOTS * SLOT_K * pstride;
+  G.cnt = (unsigned*)(G.tot + NSLOTS * SLOT_K);
   g->geo32 = G;
   g->geo32.tw = g->tw32;
   *out = g;
@@ -486,8 +627,9 @@ int nf_destroy_grid(nf_grid* g) {
   if (!g) return NF_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
-  void* bufs[] = {g->xh,  g->rh,  g->dh,  g->qh,  g->bh,       g->mix[0],   g->mix[1], g->mix[2], g->tw,
-                  g->part, g->st_own, g->x32, g->r32, g->d32, g->q32, g->mix32[0], g->mix32[1], g->lo, g->tw32};
+  void* bufs[] = {g->xh,     g->rh,     g->dh,   g->qh,  g->bh,  g->mix[0],  g->mix[1],  g->mix[2],
+                  g->mix[3], g->tw,     g->part, g->st_own, g->x32, g->r32, g->d32, g->q32,
+                  g->mix32[0], g->mix32[1], g->mix32[2], g->lo, g->tw32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (g->hst) (void)hipHostFree(g->hst);
@@ -506,6 +648,13 @@ int nf_transform_forward(nf_grid* g, const double* f, double* out) {
   g->err.clear();
   int rc = check_fields(g, {f, out});
   if (rc) return rc;
+  if (g->dim == 3) {
+    LCHK(g, launch3_row_r2c(g->geo, f, g->mix[0], 0, g->stream));
+    LCHK(g, launch3_ypass(g->geo, false, 1, -1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, g->stream));
+    LCHK(g, launch3_zfwd(g->geo, g->mix[0], out, 0, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return NF_OK;
+  }
   LCHK(g, launch_row_r2c(g->geo, f, g->mix[0], nullptr, g->stream));
   LCHK(g, launch_col_fwd(g->geo, g->mix[0], out, 2, nullptr, nullptr, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -517,6 +666,13 @@ int nf_transform_inverse(nf_grid* g, const double* spec, double* f) {
   g->err.clear();
   int rc = check_fields(g, {spec, f});
   if (rc) return rc;
+  if (g->dim == 3) {
+    LCHK(g, launch3_zinv(g->geo, 1, spec, g->mix[0], nullptr, nullptr, nullptr, g->stream));
+    LCHK(g, launch3_ypass(g->geo, false, 1, +1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, g->stream));
+    LCHK(g, launch3_row_c2r(g->geo, g->mix[0], f, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return NF_OK;
+  }
   LCHK(g, launch_col_grad(g->geo, spec, g->mix[0], nullptr, nullptr, g->stream));
   LCHK(g, launch_row_c2r(g->geo, g->mix[0], f, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -531,6 +687,19 @@ int nf_apply_operator(nf_grid* g, const double* m, const double* r, const double
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
   LCHK(g, launch_status_reset(G, 1, s));
+  if (g->dim == 3) {
+    rc = prepare_iterate(g, X_FROM_P, p);
+    if (rc) return rc;
+    void* const* M = g->mix;
+    LCHK(g, launch3_row_flux(G, false, M[0], M[1], M[2], m, r, -1, 0, nullptr, s));
+    LCHK(g, launch3_ypass(G, false, 3, -1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_zdiv(G, false, 0, M[0], M[1], M[2], g->qh, g->xh, g->xh, g->bh, 0, s));
+    LCHK(g, launch3_zinv(G, 1, g->qh, M[0], nullptr, nullptr, nullptr, s));
+    LCHK(g, launch3_ypass(G, false, 1, +1, M[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_row_c2r(G, M[0], out, s));
+    HIPCHK(g, hipStreamSynchronize(s));
+    return NF_OK;
+  }
   LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
   LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 1, g->mix[0], g->mix[1], s));
   LCHK(g, launch_row_flux(G, g->mix[0], g->mix[1], m, r, -1, nullptr, 0.0, s));
@@ -555,9 +724,8 @@ int nf_pressure_solve(nf_grid* g, const double* m, const double* r, const double
   rc = pcg(g, m, r, X_FROM_P, p, rtol, max_iter, info != nullptr, &so);
   if (rc) return rc;
   if (so.flags & FLAG_INCOMPAT) return solve_status_code(g, so);
-  // p = F^-1 x_hat
-  LCHK(g, launch_col_grad(g->geo, g->xh, g->mix[0], nullptr, nullptr, g->stream));
-  LCHK(g, launch_row_c2r(g->geo, g->mix[0], p, g->stream));
+  rc = write_p(g, p);
+  if (rc) return rc;
   if (info) {
     info->iters = so.iters;
     info->converged = so.converged;
@@ -586,7 +754,8 @@ int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, c
   if (so.flags & FLAG_INCOMPAT) return solve_status_code(g, so);
   rc = split_update(g, prm, dt, m, p, false);
   if (rc) return rc;
-  LCHK(g, launch_sum_slot(g->geo, slot_ptr(g->part, SLOT_DM), 2, row_nwg(g->geo), 8, g->stream));
+  rc = dm_to_status(g);
+  if (rc) return rc;
   DevStatus fin;
   rc = read_status(g, &fin);
   if (rc) return rc;
@@ -612,6 +781,7 @@ int nf_step_adjoint(nf_grid* g, const nf_params* prm, double dt, const double* m
   rc = check_params(g, prm, dt);
   if (rc) return rc;
   if (!(rtol >= 0.0) || max_iter < 0) return fail(g, NF_EINVAL, "rtol must be >= 0 and max_iter >= 0");
+  if (g->dim != 2) return fail(g, NF_EINVAL, "nf_step_adjoint is available for 2D grids only");
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
   const size_t n = (size_t)g->nx * g->ny;
@@ -660,6 +830,7 @@ int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p
   int rc = check_fields(g, {m, r, S, out});
   if (rc) return rc;
   if (!prm || !(prm->gamma > 0.0)) return fail(g, NF_EINVAL, "invalid params");
+  if (g->dim != 2) return fail(g, NF_EINVAL, "nf_energy is available for 2D grids only");
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
   if (p) {
@@ -713,6 +884,7 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
   ri.total_cg_iters = 0;
   ri.unconverged_solves = 0;
   const bool en = stop_on_energy_increase != 0;
+  if (en && g->dim != 2) return fail(g, NF_EINVAL, "energy stopping is available for 2D grids only");
   const bool need_sync = en || eps_dm > 0.0;
 
   rc = compute_rhs(g, S);
@@ -749,7 +921,8 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
     rc = split_update(g, prm, dt, m, p, en);
     if (rc) return rc;
     // keep Delta m and ||grad m_new||^2 before the solve reuses the status block
-    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_DM), 2, row_nwg(G), 8, s));
+    rc = dm_to_status(g);
+    if (rc) return rc;
     if (en) LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 10, s));
     DevStatus pre;
     if (need_sync) {
@@ -802,7 +975,8 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
   }
   if (!need_sync) {
     // Delta m of the last step (its partials are still in place)
-    LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_DM), 2, row_nwg(G), 8, s));
+    rc = dm_to_status(g);
+    if (rc) return rc;
     DevStatus t;
     rc = read_status(g, &t);
     if (rc) return rc;
@@ -814,8 +988,8 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
     }
   }
   // p = p[m_final]
-  LCHK(g, launch_col_grad(G, g->xh, g->mix[0], nullptr, nullptr, s));
-  LCHK(g, launch_row_c2r(G, g->mix[0], p, s));
+  rc = write_p(g, p);
+  if (rc) return rc;
   HIPCHK(g, hipStreamSynchronize(s));
   if (info) *info = ri;
   return NF_OK;

@@ -12,8 +12,9 @@
 struct nf_grid {
   using DevStatus = nf::DevStatus;
   using Geo = nf::Geo;
-  int nx = 0, ny = 0, h = 0;
-  double lx = 1.0, ly = 1.0;
+  int dim = 2;  // 2 or 3
+  int nx = 0, ny = 0, nz = 1, h = 0;
+  double lx = 1.0, ly = 1.0, lz = 1.0;
   hipStream_t stream = nullptr;
   int device = 0;
   void* tw = nullptr;
@@ -23,7 +24,7 @@ struct nf_grid {
   void* dh = nullptr;  // search direction
   void* qh = nullptr;  // A d
   void* bh = nullptr;  // projected right-hand side
-  void* mix[3] = {nullptr, nullptr, nullptr};
+  void* mix[4] = {nullptr, nullptr, nullptr, nullptr};  // 2D uses 3, 3D uses 4
   double* part = nullptr;
   DevStatus* st = nullptr;
   DevStatus* hst = nullptr;  // pinned, 2 slots
@@ -39,8 +40,8 @@ struct nf_grid {
   void* r32 = nullptr;
   void* d32 = nullptr;
   void* q32 = nullptr;
-  void* mix32[2] = {nullptr, nullptr};
-  float* lo = nullptr;  // FP32 copies of m (2n) and r (n)
+  void* mix32[3] = {nullptr, nullptr, nullptr};  // 2D uses 2, 3D uses 3
+  float* lo = nullptr;  // FP32 copies of m (d n) and r (n)
   double inner_floor = 1e-5;
   int last_inner[4] = {0, 0, 0, 0};
   Geo geo32;

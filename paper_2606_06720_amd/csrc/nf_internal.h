@@ -10,7 +10,7 @@ namespace nf {
 // of the kernel that owns each field; read by later launches and copied to the
 // host for convergence checks.
 struct DevStatus {
-  double kbar[4];   // grid mean of K = m m^T + r I: Kxx, Kxy, Kyy, (unused)
+  double kbar[8];   // grid mean of K = m m^T + r I: 2D Kxx, Kxy, Kyy; 3D Kxx, Kxy, Kxz, Kyy, Kyz, Kzz
   double bb;        // weighted ||b_hat||^2 of the projected right-hand side
   double rho[2];    // <r, M^-1 r> by iteration parity (expanded value used for beta)
   double rr[2];     // rr[0]: ||r||^2 of the residual at which the solve stopped
@@ -51,10 +51,16 @@ enum {
 struct Geo {
   int nx, ny, h, twlog;
   double lx, ly;
-  double inv_n;
+  double inv_n;       // 1 / (number of grid points)
   const void* tw;     // cx<double>[2^twlog] (cx<float> for the FP32 passes), tw[u] = exp(-2 pi i u / 2^twlog)
   DevStatus* st;
-  double* part;       // NSLOTS * SLOT_K * MAX_WG doubles
+  double* part;       // 2D: NSLOTS * SLOT_K * MAX_WG doubles; 3D: NSLOTS * SLOT_K * pstride doubles
+  // 3D only (nz = 1 in 2D)
+  int nz;
+  double lz;
+  int pstride;        // stride of the partial-sum arrays of one slot
+  double* tot;        // NSLOTS * SLOT_K reduced totals (last-workgroup reduction)
+  unsigned* cnt;      // NSLOTS arrival counters of that reduction (zero between launches)
 };
 
 __host__ __device__ inline double* slot_ptr(double* part, int slot) {
@@ -164,6 +170,44 @@ struct SumArgs {
 struct Bufs;
 
 hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s);
+
+// ---- 3D passes (nf_kernels3d.hip).  g: the 3D geometry (ny = Ny, nz = Nz);
+// row passes take the same geometry and treat the Ny*Nz lines (z, y) as rows.
+// Mixed buffers hold [kx][z][y] (after x) or, in place, [kx][z][ky] (after
+// x and y); spectral buffers hold [kx][ky][kz].
+int nwg3_row(const Geo& g);
+int nwg3_y(const Geo& g);
+int nwg3_z(const Geo& g);
+hipError_t launch3_row_r2c(const Geo& g, const double* f, void* out, int schk, hipStream_t s);
+hipError_t launch3_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s);
+// lo: FP32 copies of m (3n) then r (n), written when non-null; kbar: write the Kbar partials
+hipError_t launch3_row_flux(const Geo& g, bool f32, void* G0, void* G1, void* G2, const void* m, const void* r, int it,
+                            int kbar, float* lo, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch3_row_split(const Geo& g, void* P, void* G0, void* G1, void* G2, const double* m, double* p_out,
+                             double c2dt, double gamma, double dt, double relax1, double D2dt, hipStream_t s);
+hipError_t launch3_row_final(const Geo& g, const void* M0, const void* M1, const void* M2, double* m, hipStream_t s);
+// y passes over nf fields (1..4) in place; dir -1 forward, +1 inverse; stop_test: PCG
+// stopping decision of iteration it (it >= 1); heat_D2dt >= 0: multiply by exp(-D2dt xi_y^2)
+hipError_t launch3_ypass(const Geo& g, bool f32, int nf, int dir, void* F0, void* F1, void* F2, void* F3, int it,
+                         int stop_test, double tol2, double heat_D2dt, hipStream_t s);
+// z passes
+hipError_t launch3_zfwd(const Geo& g, const void* in, void* out, int project, hipStream_t s);
+// mode 1: P = x/n; 2: gradient (G0..G2); 3: both
+hipError_t launch3_zinv(const Geo& g, int mode, const void* xh, void* P, void* G0, void* G1, void* G2, hipStream_t s);
+hipError_t launch3_zdiv(const Geo& g, bool f32, int init, const void* F0, const void* F1, const void* F2, void* qh,
+                        const void* dh, void* rh, const void* bh, int it, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch3_zupdate(const Geo& g, bool f32, int first, void* xh, void* rh, void* dh, const void* qh, void* G0,
+                           void* G1, void* G2, int it, int max_iter, double tol2, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch3_zheat(const Geo& g, void* M0, void* M1, void* M2, double D2dt, hipStream_t s);
+hipError_t launch3_zrefine_start(const Geo& g32, const void* r64, void* x64, void* x32, void* r32, void* d32,
+                                 void* G0, void* G1, void* G2, double tol2, double floor_in, int max_iter,
+                                 hipStream_t s);
+hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G0, void* G1, void* G2,
+                               hipStream_t s);
+// reduced totals of a slot into st->out[o..o+K)
+hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s);
 hipError_t launch_zero_spec(const Geo& g, void* xh, hipStream_t s);
 // row passes (physical <-> mixed)
 int row_nwg(const Geo& g);

@@ -25,208 +25,15 @@
 
 #include "nf_fft.hpp"
 #include "nf_internal.h"
+#include "nf_tiles.hpp"
 
 namespace nf {
-
-typedef cx<double> cd;
-
-static constexpr double TWO_PI = 6.283185307179586476925286766559;
-
-// ---------------------------------------------------------------- tile configs
-// A row pass works on R physical rows of NX points (R*H complex pairs per
-// field, H = NX/2) and transforms NF fields of the block together in one
-// batched LDS FFT of NF*R lines; a column pass works on C columns of NY
-// complex values, NF fields at once.
-// Elements of one field held by a workgroup.  At 1024^2 this gives 512
-// workgroups per pass, two per CU, so that one workgroup's transform overlaps
-// the other's memory phase.
-static constexpr int TILE = 1024;
-static constexpr int TPF = TILE / 8;  // threads per field: one radix-8 butterfly per stage
-
-template <int NX, int NF>
-struct RowCfg {
-  static constexpr int H = NX / 2;
-  static constexpr int R0 = TILE / H;
-  static constexpr int R = R0 < 1 ? 1 : (R0 > 64 ? 64 : R0);  // rows per workgroup
-  static constexpr int NT = TPF * NF;
-  static constexpr int LS = H + 2;                              // padded LDS line stride
-  static constexpr int RH = R * H;                              // pairs per field in the block
-  static constexpr int NB = NF * R;                             // LDS lines
-  static constexpr int ET = (NF * RH + NT - 1) / NT;            // transposed-image elements per thread
-  static constexpr int EP = (RH + NT - 1) / NT;                 // pointwise elements per thread
-};
-
-template <int NY, int NF>
-struct ColCfg {
-  static constexpr int C0 = TILE / NY;
-  static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
-  static constexpr int NT = TPF * NF;
-  static constexpr int LS = NY;
-  static constexpr int CN = C * NY;                             // elements per field in the block
-  static constexpr int NB = NF * C;                             // LDS lines
-  static constexpr int ET = (NF * CN + NT - 1) / NT;
-  static constexpr int EP = (CN + NT - 1) / NT;
-};
-
-// first-derivative wavenumber (Nyquist zeroed) and full wavenumber
-__device__ __forceinline__ double xi_tilde(int k, int n, double L) {
-  if (2 * k == n) return 0.0;
-  const int kk = (2 * k < n) ? k : k - n;
-  return TWO_PI * (double)kk / L;
-}
-__device__ __forceinline__ double xi_full(int k, int n, double L) {
-  const int kk = (2 * k <= n) ? k : k - n;
-  return TWO_PI * (double)kk / L;
-}
-// x wavenumber of packed column kx (zero on the packed kx = 0 / Nx/2 column)
-__device__ __forceinline__ double xi_col(int kx, double lx) { return kx == 0 ? 0.0 : TWO_PI * kx / lx; }
-
-// Workgroups are dealt round-robin over the 8 XCDs; map them so that
-// consecutive logical blocks (adjacent row blocks, which share cache lines of
-// the column-major mixed layout) run on the same XCD and share its L2.
-__device__ __forceinline__ int xcd_block() {
-  const int b = blockIdx.x, nb = gridDim.x;
-  if (nb % 8 != 0) return b;
-  return (b % 8) * (nb / 8) + b / 8;
-}
-
-template <typename V>
-__device__ __forceinline__ const V* pick(int f, const V* a, const V* b, const V* c) {
-  return f == 0 ? a : (f == 1 ? b : c);
-}
-template <typename V>
-__device__ __forceinline__ V* pickw(int f, V* a, V* b, V* c) { return f == 0 ? a : (f == 1 ? b : c); }
-// non-deduced context: optional pointer arguments may be passed as nullptr
-template <typename V>
-struct same_t {
-  using type = V;
-};
-template <typename V>
-using same = typename same_t<V>::type;
-
-template <typename T>
-struct vec2;
-template <>
-struct vec2<double> {
-  using type = double2;
-};
-template <>
-struct vec2<float> {
-  using type = float2;
-};
-
-template <typename V>
-__device__ __forceinline__ V vzero() {
-  V v;
-  v.x = 0;
-  v.y = 0;
-  return v;
-}
-
-// ---------------------------------------------------------------- row images
-// "T" image: element e -> field e / RH, row (e % RH) % R, column (e % RH) / R;
-// coalesced over the column-major mixed layout M[kx][y].  LDS line of (field,
-// row) is field * R + row.
-template <int NX, int NF, typename V>
-__device__ __forceinline__ void rowT_gload(V (&v)[(RowCfg<NX, NF>::ET)], const V* s0, const same<V>* s1, const same<V>* s2,
-                                           int ny, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
-#pragma unroll
-  for (int i = 0; i < C::ET; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int f = e / C::RH, ee = e % C::RH;
-    const int rr = ee % C::R, kx = ee / C::R;
-    v[i] = (e < NF * C::RH && rr < nrow) ? pick<V>(f, s0, s1, s2)[(size_t)kx * ny + y0 + rr] : vzero<V>();
-  }
-}
-template <int NX, int NF, typename V>
-__device__ __forceinline__ void rowT_put(V* buf, const V (&v)[(RowCfg<NX, NF>::ET)]) {
-  using C = RowCfg<NX, NF>;
-#pragma unroll
-  for (int i = 0; i < C::ET; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int f = e / C::RH, ee = e % C::RH;
-    if (e < NF * C::RH) buf[(f * C::R + ee % C::R) * C::LS + ee / C::R] = v[i];
-  }
-}
-// store the first NFS fields of the block back to the mixed layout
-template <int NX, int NF, int NFS, typename V>
-__device__ __forceinline__ void rowT_store(const V* buf, same<V>* d0, same<V>* d1, same<V>* d2, int ny, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
-  for (int e = threadIdx.x; e < NFS * C::RH; e += C::NT) {
-    const int f = e / C::RH, ee = e % C::RH;
-    const int rr = ee % C::R, kx = ee / C::R;
-    if (rr < nrow) pickw<V>(f, d0, d1, d2)[(size_t)kx * ny + y0 + rr] = buf[(f * C::R + rr) * C::LS + kx];
-  }
-}
-// "P" image of a physical field: element p -> row p / H, pair p % H (the
-// grid points 2j, 2j+1 of the row), coalesced over the row-major layout
-template <int NX, int NF, typename P, typename S>
-__device__ __forceinline__ void rowP_gload(P (&v)[(RowCfg<NX, NF>::EP)], const S* __restrict__ f, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
-#pragma unroll
-  for (int i = 0; i < C::EP; ++i) {
-    const int p = threadIdx.x + i * C::NT;
-    const int rr = p / C::H, j = p % C::H;
-    v[i] = (p < C::RH && rr < nrow) ? *(const P*)(f + (size_t)(y0 + rr) * NX + 2 * j) : vzero<P>();
-  }
-}
-
-// ---------------------------------------------------------------- column images
-template <int NY, int NF, int NFL, typename V>
-__device__ __forceinline__ void colT_gload(V (&v)[(ColCfg<NY, NF>::ET)], const V* s0, const same<V>* s1, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
-#pragma unroll
-  for (int i = 0; i < C::ET; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int f = e / C::CN, ee = e % C::CN;
-    const int c = ee / NY, ky = ee % NY;
-    v[i] = (e < NFL * C::CN && kx0 + c < h) ? (f == 0 ? s0 : s1)[(size_t)(kx0 + c) * NY + ky] : vzero<V>();
-  }
-}
-template <int NY, int NF, int NFL, typename V>
-__device__ __forceinline__ void colT_put(V* buf, const V (&v)[(ColCfg<NY, NF>::ET)]) {
-  using C = ColCfg<NY, NF>;
-#pragma unroll
-  for (int i = 0; i < C::ET; ++i) {
-    const int e = threadIdx.x + i * C::NT;
-    const int f = e / C::CN, ee = e % C::CN;
-    if (e < NFL * C::CN) buf[(f * C::C + ee / NY) * C::LS + ee % NY] = v[i];
-  }
-}
-template <int NY, int NF, int NFS, typename V>
-__device__ __forceinline__ void colT_store(const V* buf, same<V>* d0, same<V>* d1, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
-  for (int e = threadIdx.x; e < NFS * C::CN; e += C::NT) {
-    const int f = e / C::CN, ee = e % C::CN;
-    const int c = ee / NY, ky = ee % NY;
-    if (kx0 + c < h) (f == 0 ? d0 : d1)[(size_t)(kx0 + c) * NY + ky] = buf[(f * C::C + c) * C::LS + ky];
-  }
-}
-// pointwise image of one field: p -> column p / NY, row p % NY
-template <int NY, int NF, typename V>
-__device__ __forceinline__ void colP_gload(V (&v)[(ColCfg<NY, NF>::EP)], const V* __restrict__ src, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
-#pragma unroll
-  for (int i = 0; i < C::EP; ++i) {
-    const int p = threadIdx.x + i * C::NT;
-    const int c = p / NY, ky = p % NY;
-    v[i] = (p < C::CN && kx0 + c < h) ? src[(size_t)(kx0 + c) * NY + ky] : vzero<V>();
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void write_partials(double* slot, const double* v, int K) {
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < K; ++k) slot[(size_t)k * MAX_WG + blockIdx.x] = v[k];
-  }
-}
 
 // ================================================================ small kernels
 __device__ __forceinline__ void k_status_reset_one(DevStatus* st, int full) {
   if (threadIdx.x == 0) {
     if (full) st->sticky = 0;
-    for (int i = 0; i < 4; ++i) st->kbar[i] = 0.0;
+    for (int i = 0; i < 8; ++i) st->kbar[i] = 0.0;
     st->bb = 0.0;
     st->rho[0] = st->rho[1] = 0.0;
     st->rr[0] = st->rr[1] = 0.0;
@@ -891,10 +698,6 @@ __global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) kb_col_grad(const ColGra
   col_grad_body<NY, GRAD>(a.g, (const cd*)a.xh, (cd*)a.P, (cd*)a.Gx, (cd*)a.Gy);
 }
 
-__device__ __forceinline__ double precond_symbol_inv(const double* K, double xx, double yy) {
-  const double s = K[0] * xx * xx + 2.0 * K[1] * xx * yy + K[2] * yy * yy;
-  return s > 0.0 ? 1.0 / s : 0.0;
-}
 
 // Operator end: forward y transform of the fluxes, q_hat = -i xi . F_hat.
 // INIT: r_hat = b_hat - q_hat (stored), partials <r,M^-1 r>, <r,r>, <b,b>;

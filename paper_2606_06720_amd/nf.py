@@ -174,18 +174,21 @@ def _current_stream():
 
 
 class Grid:
-    """A solver handle (``nf_create_grid``) for an Nx x Ny periodic box."""
+    """A solver handle (``nf_create_grid``) for an Nx x Ny (x Nz) periodic box."""
 
-    def __init__(self, n, L=(1.0, 1.0), dtype=NF_F64):
+    def __init__(self, n, L=None, dtype=NF_F64):
         n = tuple(int(v) for v in n)
-        if len(n) != 2:
-            raise ValueError("2D grids only")
+        if len(n) not in (2, 3):
+            raise ValueError("2D or 3D grids only")
         self.n = n
-        self.L = tuple(float(v) for v in L)
+        self.dim = len(n)
+        self.L = tuple(float(v) for v in (L if L is not None else (1.0,) * self.dim))
+        if len(self.L) != self.dim:
+            raise ValueError("one box length per axis")
         self._h = ctypes.c_void_p()
-        nn = (ctypes.c_int64 * 3)(n[0], n[1], 1)
-        LL = (ctypes.c_double * 3)(self.L[0], self.L[1], 1.0)
-        rc = _lib.nf_create_grid(ctypes.byref(self._h), 2, nn, LL, int(dtype), _current_stream())
+        nn = (ctypes.c_int64 * 3)(*(n + (1,) * (3 - self.dim)))
+        LL = (ctypes.c_double * 3)(*(self.L + (1.0,) * (3 - self.dim)))
+        rc = _lib.nf_create_grid(ctypes.byref(self._h), self.dim, nn, LL, int(dtype), _current_stream())
         if rc != NF_OK:
             raise NfError(rc, "nf_create_grid failed for n=%s L=%s: %s"
                           % (n, self.L, _lib.nf_last_error(None).decode()))
@@ -193,11 +196,11 @@ class Grid:
     # shapes
     @property
     def sshape(self):
-        return (self.n[1], self.n[0])
+        return tuple(self.n[::-1])
 
     @property
     def vshape(self):
-        return (2, self.n[1], self.n[0])
+        return (self.dim,) + tuple(self.n[::-1])
 
     def _check(self, rc, allow=()):
         if rc != NF_OK and rc not in allow:
@@ -301,10 +304,10 @@ class Grid:
 
     @property
     def spec_shape(self):
-        return (self.n[0] // 2, self.n[1], 2)
+        return (self.n[0] // 2,) + tuple(self.n[1:]) + (2,)
 
     def transform_forward(self, f, out):
-        """nf_transform_forward: packed half spectrum [Nx/2][Ny] (re, im) of f."""
+        """nf_transform_forward: packed half spectrum [Nx/2][Ny]([Nz]) (re, im) of f."""
         self._sync_stream()
         self._check(_lib.nf_transform_forward(self._h, _ptr(f, self.sshape, "f"), _ptr(out, self.spec_shape, "out")))
 
@@ -387,7 +390,7 @@ class Batch:
 
 
 # C-ABI-named aliases ------------------------------------------------------------
-def nf_create_grid(n, L=(1.0, 1.0), dtype=NF_F64):
+def nf_create_grid(n, L=None, dtype=NF_F64):
     return Grid(n, L, dtype)
 
 
