@@ -163,7 +163,7 @@ def adjoint_cost(N, steps):
 
 def precision_form(sizes, steps, warmup=3):
     """FP64 and FP32-refined pressure solves on the same GPU: ms per time step
-    of the dipole case (gamma 0.75) at each size, and the relative L2
+    of the dipole case (gamma 0.75) at each (N, ndim), and the relative L2
     difference of m and p after the same steps from the same state (the FP64
     form is held to the oracle at 1e-10)."""
     import numpy as np
@@ -175,8 +175,8 @@ def precision_form(sizes, steps, warmup=3):
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     out = {}
-    for N in sizes:
-        w = W.dipole_workload(N, 0.75)
+    for N, ndim in sizes:
+        w = W.dipole_workload(N, 0.75, ndim=ndim)
         res = {}
         for dt_, name in ((NF.NF_F64, "f64"), (NF.NF_F32_REFINED, "f32_refined")):
             m, r, S = T(w["m0"]), T(w["r"]), T(w["S"])
@@ -193,7 +193,10 @@ def precision_form(sizes, steps, warmup=3):
             del m, r, S, p
             torch.cuda.empty_cache()
         a, b = res["f32_refined"], res["f64"]
-        out["%d^2" % N] = {
+        npts = float(N) ** ndim
+        out["%d^%d" % (N, ndim)] = {
+            "f64_grid_point_steps_per_s": npts / (1e-3 * b["ms_per_step"]),
+            "f32_refined_grid_point_steps_per_s": npts / (1e-3 * a["ms_per_step"]),
             "f64_ms_per_step": b["ms_per_step"],
             "f32_refined_ms_per_step": a["ms_per_step"],
             "speedup": b["ms_per_step"] / a["ms_per_step"],
@@ -417,7 +420,7 @@ def main():
     if args.adjoint_steps > 0:
         out["adjoint_cost"] = adjoint_cost(N, args.adjoint_steps)
     if args.precision_steps > 0:
-        out["precision_form"] = precision_form((N, 4096), args.precision_steps)
+        out["precision_form"] = precision_form(((N, 2), (4096, 2), (256, 3)), args.precision_steps)
     if args.ensemble_steps > 0:
         out["ensemble"] = ensemble_cost(args.ensemble_steps)
     if not args.no_cpu_baseline:
