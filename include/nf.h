@@ -98,8 +98,9 @@ typedef struct {
  * Create a solver handle for a 2D or 3D periodic grid (the scheme is the same
  * in 3D, with m in R^3 and the 3x3 tensor m m^T + r I; Sec. 2 and Sec. 5).
  *   ndim    2 or 3;
- *   n       grid sizes (Nx, Ny[, Nz]), powers of two in [8, 4096] (2D) or
- *           [8, 1024] (3D);
+ *   n       grid sizes (Nx, Ny[, Nz]): 2D powers of two in [8, 4096] or
+ *           50 * 2^k in [50, 1600] (the paper's grids; radix-5 stages);
+ *           3D powers of two in [8, 1024];
  *   L       box lengths (Lx, Ly[, Lz]), > 0;
  *   dtype   NF_F64 or NF_F32_REFINED;
  *   stream  hipStream_t to enqueue on (NULL = default stream).

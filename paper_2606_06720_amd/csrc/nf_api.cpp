@@ -36,6 +36,14 @@ int fail(nf_grid* g, int code, const std::string& msg) {
   } while (0)
 
 bool is_pow2_in_range(int64_t v) { return v >= 8 && v <= 4096 && (v & (v - 1)) == 0; }
+// 2D sizes: powers of two in [8, 4096] and 50 * 2^k in [50, 1600] (mixed radix 2, 5)
+bool is_2d_size(int64_t v) {
+  if (is_pow2_in_range(v)) return true;
+  for (int64_t s = 50; s <= 1600; s *= 2)
+    if (v == s) return true;
+  return false;
+}
+int64_t gcd64(int64_t a, int64_t b) { return b == 0 ? a : gcd64(b, a % b); }
 
 int ilog2i(int v) {
   int p = 0;
@@ -495,7 +503,7 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   if (!out) return NF_EINVAL;
   *out = nullptr;
   if ((ndim != 2 && ndim != 3) || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) return NF_EINVAL;
-  if (ndim == 2 && (!is_pow2_in_range(n[0]) || !is_pow2_in_range(n[1]))) return NF_EINVAL;
+  if (ndim == 2 && (!is_2d_size(n[0]) || !is_2d_size(n[1]))) return NF_EINVAL;
   if (ndim == 3)
     for (int c = 0; c < 3; ++c)
       if (!is_pow2_in_range(n[c]) || n[c] > 1024) return NF_EINVAL;
@@ -525,9 +533,12 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
     if ((herr = (expr)) != hipSuccess) return bail(code, #expr); \
   } while (0)
   CREATE_CHK(hipGetDevice(&g->device), NF_EDEVICE);
-  int twn = g->nx > g->ny ? g->nx : g->ny;
-  if (g->nz > twn) twn = g->nz;
-  g->twlog = ilog2i(twn);
+  // twiddle table length: the least common multiple of the axis lengths, so
+  // that every stage's angle unit is a whole number of table steps
+  int64_t twl = g->nx / gcd64(g->nx, g->ny) * g->ny;
+  twl = twl / gcd64(twl, g->nz) * g->nz;
+  const int twn = (int)twl;
+  g->twn = twn;
   const size_t npts = (size_t)g->nx * g->ny * g->nz;
   const size_t spec_bytes = (size_t)g->h * g->ny * g->nz * 2 * sizeof(double);
   const int nmix = ndim == 3 ? 4 : 3;
@@ -582,7 +593,7 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.nx = g->nx;
   G.ny = g->ny;
   G.h = g->h;
-  G.twlog = g->twlog;
+  G.twn = g->twn;
   G.lx = g->lx;
   G.ly = g->ly;
   G.inv_n = 1.0 / ((double)g->nx * (double)g->ny * (double)g->nz);

@@ -93,10 +93,31 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
   v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
   v[1] = a4; v[3] = a5; v[5] = a6; v[7] = a7;
 }
+// 5-point DFT: with t1 = v1 + v4, t2 = v2 + v3, t3 = v1 - v4, t4 = v2 - v3 the
+// outputs are X0 = v0 + t1 + t2, X1,4 = a1 +- DIR i b1, X2,3 = a2 +- DIR i b2 where
+// a1 = v0 + c1 t1 + c2 t2, a2 = v0 + c2 t1 + c1 t2, b1 = s1 t3 + s2 t4,
+// b2 = s2 t3 - s1 t4 (c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5)).
+template <int DIR, typename T>
+__device__ __forceinline__ void dft5(cx<T>* v) {
+  const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+  const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+  const cx<T> t1 = add(v[1], v[4]), t2 = add(v[2], v[3]);
+  const cx<T> t3 = sub(v[1], v[4]), t4 = sub(v[2], v[3]);
+  const cx<T> a1 = add(v[0], add(scl(t1, c1), scl(t2, c2)));
+  const cx<T> a2 = add(v[0], add(scl(t1, c2), scl(t2, c1)));
+  const cx<T> b1 = mul_i<DIR>(add(scl(t3, s1), scl(t4, s2)));
+  const cx<T> b2 = mul_i<DIR>(sub(scl(t3, s2), scl(t4, s1)));
+  v[0] = add(v[0], add(t1, t2));
+  v[1] = add(a1, b1);
+  v[4] = sub(a1, b1);
+  v[2] = add(a2, b2);
+  v[3] = sub(a2, b2);
+}
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 5) dft5<DIR>(v);
   else dft8<DIR>(v);
 }
 
@@ -117,18 +138,30 @@ constexpr int plan_radix(int p, int s) {
 constexpr int plan_ns(int p, int s) {  // product of radices before stage s
   return s == 0 ? 1 : plan_ns(p, s - 1) * plan_radix(p, s - 1);
 }
+// Lengths n = 5^k 2^p: k radix-5 stages first, then the power-of-two plan above.
+constexpr int f5(int n) { return n % 5 == 0 ? 1 + f5(n / 5) : 0; }
+constexpr int pow5(int k) { return k == 0 ? 1 : 5 * pow5(k - 1); }
+constexpr int mplan_nstages(int n) {
+  return f5(n) + (n / pow5(f5(n)) == 1 ? 0 : plan_nstages(ilog2(n / pow5(f5(n)))));
+}
+constexpr int mplan_radix(int n, int s) {
+  return s < f5(n) ? 5 : plan_radix(ilog2(n / pow5(f5(n))), s - f5(n));
+}
+constexpr int mplan_ns(int n, int s) { return s == 0 ? 1 : mplan_ns(n, s - 1) * mplan_radix(n, s - 1); }
+constexpr bool plan_ok(int n) { return pow5(f5(n)) * (1 << ilog2(n / pow5(f5(n)))) == n; }
 
-// Twiddle e^{DIR 2 pi i t / M} from the table tw[u] = e^{-2 pi i u / TWN}.
+// Twiddle e^{DIR 2 pi i t / M} from the table tw[u] = e^{-2 pi i u / TWN}, where
+// mult = TWN / M (TWN is a common multiple of every transform length).
 template <int DIR, typename T>
-__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int t, int shift) {
-  cx<T> w = tw[t << shift];
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int t, int mult) {
+  cx<T> w = tw[t * mult];
   return DIR > 0 ? conj(w) : w;
 }
 
 // One Stockham stage over B lines of length L stored at buf + line*LS.
 // Inputs are read at stride L/R, outputs written in autosort order.
 template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
   constexpr int Q = L / R;          // butterflies per line
   constexpr int NBF = B * Q;        // butterflies in the batch
   constexpr int PER = (NBF + NT - 1) / NT;
@@ -136,10 +169,10 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
   const int tid = threadIdx.x;
   cx<T> v[PER][R];
   cx<T> w[PER][R];
-  // twiddle index shift: the table has TWN = 2^twlog entries, this stage needs
-  // angles in units of 2 pi / (NS R).  The table loads are issued before the
-  // barrier so that their latency overlaps the LDS traffic.
-  const int shift = twlog - ilog2(NS * R);
+  // the table has twn entries, this stage needs angles in units of
+  // 2 pi / (NS R).  The table loads are issued before the barrier so that
+  // their latency overlaps the LDS traffic.
+  const int mult = twn / (NS * R);
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int f = tid + b * NT;
@@ -148,7 +181,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
       if constexpr (NS > 1) {
         const int k = j % NS;
 #pragma unroll
-        for (int q = 1; q < R; ++q) w[b][q] = twiddle<DIR>(tw, q * k, shift);
+        for (int q = 1; q < R; ++q) w[b][q] = twiddle<DIR>(tw, q * k, mult);
       }
       const cx<T>* src = buf + line * LS + j;
 #pragma unroll
@@ -176,19 +209,19 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
 }
 
 template <typename T, int DIR, int L, int B, int LS, int NT, int S>
-__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
-  constexpr int P = ilog2(L);
-  if constexpr (S < plan_nstages(P)) {
-    fft_stage<T, DIR, L, B, LS, NT, plan_radix(P, S), plan_ns(P, S)>(buf, tw, twlog);
-    fft_stages<T, DIR, L, B, LS, NT, S + 1>(buf, tw, twlog);
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
+  static_assert(plan_ok(L), "transform lengths are 5^k 2^p");
+  if constexpr (S < mplan_nstages(L)) {
+    fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S), mplan_ns(L, S)>(buf, tw, twn);
+    fft_stages<T, DIR, L, B, LS, NT, S + 1>(buf, tw, twn);
   }
 }
 
 // In-LDS FFT of B lines of length L (line stride LS), all NT threads taking part.
 // Caller must __syncthreads() before (data written) -- the routine ends with a barrier.
 template <typename T, int DIR, int L, int B, int LS, int NT>
-__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
-  fft_stages<T, DIR, L, B, LS, NT, 0>(buf, tw, twlog);
+__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
+  fft_stages<T, DIR, L, B, LS, NT, 0>(buf, tw, twn);
 }
 
 // ------------------------------------------------- real <-> half-complex (x axis)
@@ -198,26 +231,27 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw
 // packed into slot 0 as X[0] + i X[H].  irfft_pre is its inverse (up to the
 // factor N of an unnormalised inverse): it rebuilds 2 Z from the packed X, so
 // that an unnormalised length-H inverse FFT gives N (f[2j] + i f[2j+1]).
-// Both work on B lines in place; one thread per pair (k, H-k), k in [0, H/2).
+// Both work on B lines in place; one thread per pair (k, H-k), k in [1, H/2),
+// and one for slot 0 (which also handles the self-paired k = H/2 when H is even).
 template <typename T, int H, int B, int LS, int NT>
-__device__ __forceinline__ void rfft_post(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
-  constexpr int NP = H / 2;  // pairs per line (pair 0 also handles k = H/2)
+__device__ __forceinline__ void rfft_post(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
+  constexpr int NP = (H + 1) / 2;
   constexpr int NTASK = B * NP;
-  const int shift = twlog - ilog2(2 * H);
+  const int mult = twn / (2 * H);
   for (int t = threadIdx.x; t < NTASK; t += NT) {
     const int line = t / NP, k = t % NP;
     cx<T>* l = buf + line * LS;
     if (k == 0) {
       cx<T> z0 = l[0];
       l[0] = mk<T>(z0.x + z0.y, z0.x - z0.y);
-      if (H >= 2) {
+      if (H % 2 == 0) {
         // self-paired k = H/2: w^{H/2} = -i, X = conj(Z)
         cx<T> zh = l[H / 2];
         l[H / 2] = conj(zh);
       }
     } else {
       cx<T> zk = l[k], zm = l[H - k];
-      cx<T> w = tw[k << shift];                      // e^{-2 pi i k / N}
+      cx<T> w = tw[k * mult];                        // e^{-2 pi i k / N}
       // X[k]   = (zk + conj zm)/2 - (i/2) w (zk - conj zm)
       // X[H-k] = (zm + conj zk)/2 + (i/2) conj(w) (zm - conj zk)
       cx<T> e1 = add(zk, conj(zm)), o1 = sub(zk, conj(zm));
@@ -232,24 +266,24 @@ __device__ __forceinline__ void rfft_post(cx<T>* buf, const cx<T>* __restrict__ 
 }
 
 template <typename T, int H, int B, int LS, int NT>
-__device__ __forceinline__ void irfft_pre(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog) {
-  constexpr int NP = H / 2;
+__device__ __forceinline__ void irfft_pre(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
+  constexpr int NP = (H + 1) / 2;
   constexpr int NTASK = B * NP;
-  const int shift = twlog - ilog2(2 * H);
+  const int mult = twn / (2 * H);
   for (int t = threadIdx.x; t < NTASK; t += NT) {
     const int line = t / NP, k = t % NP;
     cx<T>* l = buf + line * LS;
     if (k == 0) {
       cx<T> p = l[0];  // X[0] + i X[H]
       l[0] = mk<T>(p.x + p.y, p.x - p.y);
-      if (H >= 2) {
+      if (H % 2 == 0) {
         // self-paired k = H/2: 2 Z = 2 conj(X)
         cx<T> xh = l[H / 2];
         l[H / 2] = mk<T>(xh.x + xh.x, -(xh.y + xh.y));
       }
     } else {
       cx<T> xk = l[k], xm = l[H - k];
-      cx<T> w = tw[k << shift];  // e^{-2 pi i k / N}
+      cx<T> w = tw[k * mult];  // e^{-2 pi i k / N}
       // 2Z[k]   = (xk + conj xm) + i conj(w) (xk - conj xm)
       // 2Z[H-k] = (xm + conj xk) - i w (xm - conj xk)
       cx<T> e1 = add(xk, conj(xm)), o1 = sub(xk, conj(xm));

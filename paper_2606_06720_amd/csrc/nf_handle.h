@@ -18,7 +18,7 @@ struct nf_grid {
   hipStream_t stream = nullptr;
   int device = 0;
   void* tw = nullptr;
-  int twlog = 0;
+  int twn = 0;  // twiddle table length
   void* xh = nullptr;  // PCG iterate (spectral)
   void* rh = nullptr;  // residual
   void* dh = nullptr;  // search direction

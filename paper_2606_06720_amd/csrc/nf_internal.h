@@ -49,10 +49,11 @@ enum {
 
 // Geometry and workspace pointers passed by value to every kernel.
 struct Geo {
-  int nx, ny, h, twlog;
+  int nx, ny, h, twn;
   double lx, ly;
   double inv_n;       // 1 / (number of grid points)
-  const void* tw;     // cx<double>[2^twlog] (cx<float> for the FP32 passes), tw[u] = exp(-2 pi i u / 2^twlog)
+  const void* tw;     // cx<double>[twn] (cx<float> for the FP32 passes), tw[u] = exp(-2 pi i u / twn);
+                      // twn is a common multiple of every transform length
   DevStatus* st;
   double* part;       // 2D: NSLOTS * SLOT_K * MAX_WG doubles; 3D: NSLOTS * SLOT_K * pstride doubles
   // 3D only (nz = 1 in 2D)

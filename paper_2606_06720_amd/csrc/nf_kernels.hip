@@ -101,8 +101,8 @@ __device__ __forceinline__ void row_r2c_body(Geo g, const double* __restrict__ f
     }
   }
   __syncthreads();
-  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, g.ny, y0, nrow);
   if (schk) {
     block_sum<C::NT, 2>(s, red);
@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(TPF) k_row_c2r(Geo g, const cd* __restrict__ i
   rowT_gload<NX, 1>(tv, in, nullptr, nullptr, g.ny, y0, nrow);
   rowT_put<NX, 1>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int p = threadIdx.x; p < C::RH; p += C::NT) {
     const int rr = p / C::H, j = p % C::H;
     if (rr < nrow) {
@@ -203,8 +203,8 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   }
   rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double ks[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -228,8 +228,8 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
     }
   }
   __syncthreads();
-  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 2, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
@@ -268,8 +268,8 @@ __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* _
   rowP_gload<NX, 3>(myv, m + n, y0, nrow);
   rowT_put<NX, 3>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
 
   const double e1 = 1.0 - gamma;
   bool bad = false;
@@ -319,8 +319,8 @@ __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* _
   }
   if (bad) atomicOr(&g.st->sticky, (int)FLAG_NONFINITE);
   __syncthreads();
-  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 3, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
 }
 template <int NX>
@@ -354,8 +354,8 @@ __device__ __forceinline__ void row_final_body(Geo g, const cd* __restrict__ Mx,
   rowP_gload<NX, 2>(o1, m + n, y0, nrow);
   rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -408,8 +408,8 @@ __global__ void __launch_bounds__(2 * TPF) k_row_energy(Geo g, const cd* __restr
   rowP_gload<NX, 2>(rv, r, y0, nrow);
   rowT_put<NX, 2>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -517,8 +517,8 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, con
   rowP_gload<NX, 4>(my, m + n, y0, nrow);
   rowT_put<NX, 4>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -541,8 +541,8 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, con
     }
   }
   __syncthreads();
-  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 4, 2>(buf, A0, A1, nullptr, g.ny, y0, nrow);
 }
 
@@ -575,8 +575,8 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj2(Geo g, const cd* __restric
   rowP_gload<NX, 4>(muv, mu, y0, nrow);
   rowT_put<NX, 4>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -631,7 +631,7 @@ __device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out
   colT_gload<NY, 2, 1>(tv, in, nullptr, kx0, g.h);
   colT_put<NY, 2, 1>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twn);
   cd v[C::EP];
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -650,7 +650,7 @@ __device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out
     if (p < C::CN) put_grad<NY, 2>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
   }
   __syncthreads();
-  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
@@ -683,7 +683,7 @@ __device__ __forceinline__ void col_grad_body(Geo g, const cd* __restrict__ xh, 
     }
   }
   __syncthreads();
-  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   if (GRAD) colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
   else colT_store<NY, 1, 1>(buf, P, nullptr, kx0, g.h);
 }
@@ -746,7 +746,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   }
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<T, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -918,7 +918,7 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
   }
   if (stop) return;
   __syncthreads();
-  lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY, typename T>
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ void col_refine_start_body(Geo g, const cd* __restric
     if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, d, g);
   }
   __syncthreads();
-  lds_fft<float, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<float, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
@@ -1082,7 +1082,7 @@ __device__ __forceinline__ void col_refine_acc_body(Geo g, cd* x64, const cx<flo
     if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, x, g);
   }
   __syncthreads();
-  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
@@ -1112,7 +1112,7 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
   colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[1] = {0.0};
   cd v[2][C::EP];
 #pragma unroll
@@ -1128,7 +1128,7 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
       const cd a = line[ky];
       cd out;
       if (kx == 0) {
-        const cd b = line[(NY - ky) & (NY - 1)];
+        const cd b = line[ky == 0 ? 0 : NY - ky];
         const double hA = exp(-D2dt * (yf * yf)) * g.inv_n;
         const double hB = exp(-D2dt * (xnyq * xnyq + yf * yf)) * g.inv_n;
         // P' = (hA+hB)/2 P(ky) + (hA-hB)/2 conj P(-ky)
@@ -1155,7 +1155,7 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
     }
   }
   __syncthreads();
-  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Mx, My, kx0, g.h);
   if (eslot) {
     block_sum<C::NT, 1>(s, red);
@@ -1185,7 +1185,7 @@ __global__ void __launch_bounds__(2 * TPF) k_col_divrhs(Geo g, const cd* __restr
   colT_gload<NY, 2, 2>(tv, V0, V1, kx0, g.h);
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int p = threadIdx.x; p < C::CN; p += C::NT) {
     const int c = p / NY, ky = p % NY;
     const int kx = kx0 + c;
@@ -1216,7 +1216,7 @@ __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __res
   colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[1] = {0.0};
   for (int e = threadIdx.x; e < 2 * C::CN; e += C::NT) {
     const int f = e / C::CN, ee = e % C::CN;
@@ -1246,6 +1246,12 @@ __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __res
     case 1024: MACRO(1024); break;           \
     case 2048: MACRO(2048); break;           \
     case 4096: MACRO(4096); break;           \
+    case 50: MACRO(50); break;               \
+    case 100: MACRO(100); break;             \
+    case 200: MACRO(200); break;             \
+    case 400: MACRO(400); break;             \
+    case 800: MACRO(800); break;             \
+    case 1600: MACRO(1600); break;           \
     default: return hipErrorInvalidValue;    \
   }
 

@@ -185,8 +185,8 @@ __global__ void __launch_bounds__(TPF) k3_row_r2c(Geo g, const double* __restric
     }
   }
   __syncthreads();
-  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, rows, y0, nrow);
   if (schk) reduce_last<C::NT, 2>(s, g, SLOT_SCHK, red);
 }
@@ -203,8 +203,8 @@ __global__ void __launch_bounds__(TPF) k3_row_c2r(Geo g, const cd* __restrict__ 
   rowT_gload<NX, 1>(tv, in, nullptr, nullptr, rows, y0, nrow);
   rowT_put<NX, 1>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int p = threadIdx.x; p < C::RH; p += C::NT) {
     const int rr = p / C::H, j = p % C::H;
     if (rr < nrow) {
@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   }
   rowT_put<NX, 3>(buf, tv);
   __syncthreads();
-  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double ks[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -287,8 +287,8 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
     }
   }
   __syncthreads();
-  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 3, 3>(buf, G0, G1, G2, rows, y0, nrow);
   if (kbar) reduce_last<C::NT, 7>(ks, g, SLOT_KBAR, red);
 }
@@ -324,8 +324,8 @@ __global__ void __launch_bounds__(4 * TPF) k3_row_split(Geo g, cd* P, cd* G0, cd
   rowP_gload<NX, 4>(m2v, m + 2 * n, y0, nrow);
   rowT_put<NX, 4>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   const double e1 = 1.0 - gamma;
   bool bad = false;
 #pragma unroll
@@ -376,8 +376,8 @@ __global__ void __launch_bounds__(4 * TPF) k3_row_split(Geo g, cd* P, cd* G0, cd
   }
   if (bad) atomicOr(&g.st->sticky, (int)FLAG_NONFINITE);
   __syncthreads();
-  lds_fft<double, -1, C::H, 3 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
-  rfft_post<double, C::H, 3 * C::R, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, C::H, 3 * C::R, C::LS, C::NT>(buf, tw, g.twn);
+  rfft_post<double, C::H, 3 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   // x factor of the heat kernel; slot 0 holds the kx = 0 (real part) and kx = Nx/2
   // (imaginary part) coefficients
   for (int t = threadIdx.x; t < 3 * C::R * C::H; t += C::NT) {
@@ -416,8 +416,8 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_final(Geo g, const cd* __restr
   rowP_gload<NX, 3>(o2, m + 2 * n, y0, nrow);
   rowT_put<NX, 3>(buf, tv);
   __syncthreads();
-  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
-  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(NF * TPF) k3_ypass(Geo g, cx<T>* F0, cx<T>* F1
     if (e < NF * C::CN) buf[(e / C::CN * C::C + (e % C::CN) / NY) * C::LS + e % NY] = tv[i];
   }
   __syncthreads();
-  lds_fft<T, DIR, NY, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, DIR, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int e = threadIdx.x; e < NF * C::CN; e += C::NT) {
     const int f = e / C::CN, ee = e % C::CN;
     const int c = ee / NY, ky = ee % NY;
@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(TPF) k3_zfwd(Geo g, const cd* __restrict__ in,
   zT_gload<NZ, 1, 1>(tv, in, nullptr, nullptr, nullptr, lam0, nlam, g.ny);
   zT_put<NZ, 1, 1>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__((MODE == 1 ? 1 : (MODE == 2 ? 3 : 4)) * TPF)
     }
   }
   __syncthreads();
-  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   if (MODE == 1) zT_store<NZ, NF, 1>(buf, P, nullptr, nullptr, nullptr, lam0, nlam, g.ny);
   if (MODE == 2) zT_store<NZ, NF, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
   if (MODE == 3) zT_store<NZ, NF, 4>(buf, P, G0, G1, G2, lam0, nlam, g.ny);
@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
   }
   zT_put<NZ, 3, 3>(buf, tv);
   __syncthreads();
-  lds_fft<T, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -757,7 +757,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zupdate(Geo g, int first, cx<T>* x
   if (!first && !zero_x) reduce_last<C::NT, 1>(rrp, g, SLOT_RR, red);
   if (stop) return;
   __syncthreads();
-  lds_fft<T, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<T, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   zT_store<NZ, 3, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
 }
 
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zheat(Geo g, cd* M0, cd* M1, cd* M
   zT_gload<NZ, 3, 3>(tv, M0, M1, M2, nullptr, lam0, nlam, g.ny);
   zT_put<NZ, 3, 3>(buf, tv);
   __syncthreads();
-  lds_fft<double, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int e = threadIdx.x; e < 3 * C::CN; e += C::NT) {
     const int line = e / NZ, kz = e % NZ;
     const double zk = xi_full(kz, NZ, g.lz);
@@ -782,7 +782,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zheat(Geo g, cd* M0, cd* M1, cd* M
     *v = scl(*v, exp(-D2dt * zk * zk) * g.inv_n);
   }
   __syncthreads();
-  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   zT_store<NZ, 3, 3>(buf, M0, M1, M2, nullptr, lam0, nlam, g.ny);
 }
 
@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zrefine_start(Geo g, const cd* __r
     if (p < C::CN) put_grad3<NZ, 3, float>(buf, 0, c, kz, d, xx, yy, zz, g.inv_n);
   }
   __syncthreads();
-  lds_fft<float, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<float, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   zT_store<NZ, 3, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
 }
 
@@ -909,7 +909,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zrefine_acc(Geo g, cd* x64, const 
     if (p < C::CN) put_grad3<NZ, 3, double>(buf, 0, c, kz, x, xx, yy, xi_tilde(kz, NZ, g.lz), g.inv_n);
   }
   __syncthreads();
-  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twlog);
+  lds_fft<double, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   zT_store<NZ, 3, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
 }
 

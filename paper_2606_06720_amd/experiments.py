@@ -1,0 +1,114 @@
+"""The paper's own workloads run through the C ABI.
+
+Grid convergence (Sec. Grid Convergence): observed orders
+
+    q_f = ln(||f_h - f_{h/2}|| / ||f_{h/2} - f_{h/4}||) / ln 2
+
+for f = |m|, |grad p| and p at fixed times, on the grids N = 50, 100, ..., with
+the first setup of that section: Omega = [0,1)^2, r = 0.1, S = S_int,
+c = 100 (c^2 = 1e4), gamma = 0.75, D = 0.01 (D^2 = 1e-4), dt = 0.05, m0 = m^A.
+Differences are taken on the nodes of the coarser grid of each pair (they
+coincide with every other node of the finer grid), in the grid L2 norm
+(h^2 sum).  The discrete S_int is made exactly mean-free (its constant pi/1000
+is the continuum integral of the Gaussian).
+
+Run as ``python -m paper_2606_06720_amd.experiments`` to print the table.
+The solver runs on the GPU; |grad p| for the norms is formed on the host with
+numpy (analysis only).
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import sys
+
+import numpy as np
+
+from . import workloads as W
+
+TABLE1 = dict(c2=1.0e4, D2=1.0e-4, gamma=0.75, dt=0.05, r=0.1, mA_factor=1.0e4)
+
+
+def _grad_norm(p):
+    """|grad p| by spectral differentiation (Nyquist entry zeroed) on [0,1)^2."""
+    N = p.shape[0]
+    k = np.fft.fftfreq(N, 1.0 / N) * 2.0 * np.pi
+    k[N // 2] = 0.0
+    P = np.fft.fft2(p)
+    gx = np.fft.ifft2(1j * k[None, :] * P).real
+    gy = np.fft.ifft2(1j * k[:, None] * P).real
+    return np.sqrt(gx * gx + gy * gy)
+
+
+def _fields(m, p):
+    return {"m": np.sqrt((m * m).sum(0)), "gradp": _grad_norm(p), "p": p}
+
+
+def _diff_norm(coarse, fine):
+    N = coarse.shape[0]
+    d = coarse - fine[::2, ::2]
+    return math.sqrt((d * d).sum()) / N
+
+
+def run_grids(Ns, times, prm=TABLE1, rtol=1e-10, dtype=None):
+    """Fields |m|, |grad p|, p at each time on each grid (GPU, nf_run)."""
+    import torch
+
+    from . import nf as NF
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for N in Ns:
+        S = W.paper_Sint(N)
+        S = S - S.mean()
+        m0 = W.paper_m_A(N, prm["mA_factor"])
+        m = torch.from_numpy(np.ascontiguousarray(m0)).to(dev)
+        p = torch.zeros((N, N), dtype=torch.float64, device=dev)
+        r = torch.full((N, N), prm["r"], dtype=torch.float64, device=dev)
+        St = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
+        done = 0
+        with NF.Grid((N, N), dtype=dtype if dtype is not None else NF.NF_F64) as g:
+            for t in times:
+                target = int(round(t / prm["dt"]))
+                if target > done:
+                    g.run(prm["c2"], prm["D2"], prm["gamma"], prm["dt"], target - done, m, p, r, St, rtol=rtol,
+                          max_iter=5000)
+                    done = target
+                out[(N, t)] = _fields(m.cpu().numpy(), p.cpu().numpy())
+    return out
+
+
+def orders(fields, Ns, times):
+    """Observed orders of each consecutive triple (N, 2N, 4N) at each time."""
+    res = {}
+    for t in times:
+        for a, b, c in zip(Ns, Ns[1:], Ns[2:]):
+            if b != 2 * a or c != 2 * b:
+                continue
+            q = {}
+            for key in ("m", "gradp", "p"):
+                e1 = _diff_norm(fields[(a, t)][key], fields[(b, t)][key])
+                e2 = _diff_norm(fields[(b, t)][key], fields[(c, t)][key])
+                q[key] = math.log(e1 / e2) / math.log(2.0) if e1 > 0 and e2 > 0 else float("nan")
+            res[(t, (a, b, c))] = q
+    return res
+
+
+def grid_convergence(Ns=(50, 100, 200, 400, 800), times=(5.0, 10.0), prm=TABLE1, rtol=1e-10):
+    return orders(run_grids(Ns, times, prm, rtol), Ns, times)
+
+
+def main(argv):
+    Ns = tuple(int(v) for v in argv[1].split(",")) if len(argv) > 1 else (50, 100, 200, 400, 800)
+    times = tuple(float(v) for v in argv[2].split(",")) if len(argv) > 2 else (5.0, 10.0)
+    res = grid_convergence(Ns, times)
+    print("observed orders q_|m|, q_|grad p|, q_p (c=100, gamma=0.75, D=0.01, dt=0.05, m^A, S_int)")
+    for (t, tri), q in sorted(res.items()):
+        print("t=%-5g N=%-15s q_m %7.4f  q_gradp %7.4f  q_p %7.4f" % (t, ",".join(map(str, tri)), q["m"], q["gradp"],
+                                                                      q["p"]))
+    print(json.dumps({"%g:%s" % (t, ",".join(map(str, tri))): q for (t, tri), q in res.items()}))
+
+
+if __name__ == "__main__":
+    main(sys.argv)
