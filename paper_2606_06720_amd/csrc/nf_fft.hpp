@@ -160,8 +160,20 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int t, in
 
 // One Stockham stage over B lines of length L stored at buf + line*LS.
 // Inputs are read at stride L/R, outputs written in autosort order.
-template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS>
+// Intermediate results between stages live in a padded line layout (one
+// spare slot after every 8 elements, lpad below): the first stage's outputs,
+// 8 consecutive elements per butterfly, then fall on distinct LDS banks.  The
+// first stage reads and the last stage writes the natural layout, so a line
+// needs LS >= lpad_len(L) slots (the padding is used when it has them).
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lpad_len(int L) { return L + (L >> 3) + 1; }
+// Lines longer than 1024 keep the natural layout: there the extra index
+// arithmetic costs more registers than the bank conflicts cost time.
+__host__ __device__ constexpr bool lpad_use(int L) { return L <= 1024; }
+
+template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS, bool PIN, bool POUT>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
+  static_assert(!(PIN || POUT) || LS >= lpad_len(L), "line stride too small for the padded layout");
   constexpr int Q = L / R;          // butterflies per line
   constexpr int NBF = B * Q;        // butterflies in the batch
   constexpr int PER = (NBF + NT - 1) / NT;
@@ -183,9 +195,15 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
 #pragma unroll
         for (int q = 1; q < R; ++q) w[b][q] = twiddle<DIR>(tw, q * k, mult);
       }
-      const cx<T>* src = buf + line * LS + j;
+      if constexpr (PIN) {
+        const cx<T>* src = buf + line * LS;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[b][q] = src[q * Q];
+        for (int q = 0; q < R; ++q) v[b][q] = src[lpad(j + q * Q)];
+      } else {
+        const cx<T>* src = buf + line * LS + j;
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[b][q] = src[q * Q];
+      }
     }
   }
   __syncthreads();
@@ -200,9 +218,16 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
         for (int q = 1; q < R; ++q) v[b][q] = mul(v[b][q], w[b][q]);
       }
       dft<R, DIR>(v[b]);
-      cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;
+      if constexpr (POUT) {
+        cx<T>* dst = buf + line * LS;
+        const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) dst[q * NS] = v[b][q];
+        for (int q = 0; q < R; ++q) dst[lpad(o + q * NS)] = v[b][q];
+      } else {
+        cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[q * NS] = v[b][q];
+      }
     }
   }
   __syncthreads();
@@ -212,7 +237,9 @@ template <typename T, int DIR, int L, int B, int LS, int NT, int S>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
   static_assert(plan_ok(L), "transform lengths are 5^k 2^p");
   if constexpr (S < mplan_nstages(L)) {
-    fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S), mplan_ns(L, S)>(buf, tw, twn);
+    constexpr bool PAD = lpad_use(L) && LS >= lpad_len(L);
+    fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S), mplan_ns(L, S), PAD && (S > 0),
+              PAD && (S + 1 < mplan_nstages(L))>(buf, tw, twn);
     fft_stages<T, DIR, L, B, LS, NT, S + 1>(buf, tw, twn);
   }
 }

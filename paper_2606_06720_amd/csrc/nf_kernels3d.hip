@@ -70,7 +70,7 @@ struct ZCfg {
   static constexpr int C0 = TILE / NZ;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);  // lines (kx, ky) per workgroup
   static constexpr int NT = TPF * NF;
-  static constexpr int LS = NZ + 1;                            // padded LDS line stride
+  static constexpr int LS = lpad_use(NZ) ? lpad_len(NZ) : NZ + 1;  // room for the FFT's padded layout
   static constexpr int CN = C * NZ;
   static constexpr int NB = NF * C;
   static constexpr int ET = (NF * CN + NT - 1) / NT;

@@ -32,7 +32,7 @@ struct RowCfg {
   static constexpr int R0 = TILE / H;
   static constexpr int R = R0 < 1 ? 1 : (R0 > 64 ? 64 : R0);  // rows per workgroup
   static constexpr int NT = TPF * NF;
-  static constexpr int LS = H + 2;                              // padded LDS line stride
+  static constexpr int LS = lpad_use(H) ? lpad_len(H) + 1 : H + 2;  // LDS line stride (room for the FFT's padded layout)
   static constexpr int RH = R * H;                              // pairs per field in the block
   static constexpr int NB = NF * R;                             // LDS lines
   static constexpr int ET = (NF * RH + NT - 1) / NT;            // transposed-image elements per thread
@@ -44,7 +44,7 @@ struct ColCfg {
   static constexpr int C0 = TILE / NY;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
   static constexpr int NT = TPF * NF;
-  static constexpr int LS = NY;
+  static constexpr int LS = lpad_use(NY) ? lpad_len(NY) : NY;   // room for the FFT's padded layout
   static constexpr int CN = C * NY;                             // elements per field in the block
   static constexpr int NB = NF * C;                             // LDS lines
   static constexpr int ET = (NF * CN + NT - 1) / NT;
