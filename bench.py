@@ -9,8 +9,9 @@ split update), so a step processes 3 * 1024^2 grid points.  All inputs are
 resident in device memory before the timed region.
 
 Prints one JSON line (metric: grid-point-steps/s) with a roofline entry for the
-dominant kernel (average duration from HIP events on the library's stream over
-the timed region) and a CPU-oracle baseline on a bounded sample.
+dominant kernel (average execution span of its launches in the timed region,
+stamped by the kernel itself on the device wall clock: first workgroup start
+to last workgroup end) and a CPU-oracle baseline on a bounded sample.
 """
 
 import argparse
@@ -38,7 +39,8 @@ KERNEL_IDS = {"row_flux": 0, "col_div": 1, "col_update": 2}
 # first update (32), split: p and gradient (16 + 24), activation/relaxation
 # pass (64), heat multiplier (32), final row pass with Delta m (48)
 STEP_BYTES_PER_POINT = 328.0
-KERNEL_SOURCES = ("paper_2606_06720_amd/csrc/nf_kernels.hip", "paper_2606_06720_amd/csrc/nf_fft.hpp")
+KERNEL_SOURCES = ("paper_2606_06720_amd/csrc/nf_kernels.hip", "paper_2606_06720_amd/csrc/nf_fft.hpp",
+                  "paper_2606_06720_amd/csrc/nf_tiles.hpp", "paper_2606_06720_amd/csrc/nf_internal.h")
 
 
 def kernel_source_hash():
@@ -61,6 +63,21 @@ def load_traffic(kernel, n):
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def load_rocprof_duration(kernel, n):
+    """Working-dispatch average duration (us) of the kernel in the committed
+    rocprofv3 trace of the default bench command, or None if absent or taken
+    on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "duration_%s_%d.json" % (kernel, n))
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("concurrent_working_avg_us")
 
 
 def cpu_baseline(N, steps):
@@ -265,6 +282,30 @@ def ensemble_cost(steps, mix=None):
     return out
 
 
+def profile_case(spec):
+    """N:form:steps:ndim -- run `steps` time steps of the dipole case (gamma
+    0.75, rtol 1e-10) at N^ndim with form f64 or f32r through nf_step, for
+    kernel traces of the precision form."""
+    import numpy as np
+    import torch
+
+    from paper_2606_06720_amd import nf as NF
+    from paper_2606_06720_amd import workloads as W
+
+    N, form, steps, ndim = spec.split(":")
+    N, steps, ndim = int(N), int(steps), int(ndim)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    w = W.dipole_workload(N, 0.75, ndim=ndim)
+    m, r, S = T(w["m0"]), T(w["r"]), T(w["S"])
+    p = torch.zeros_like(r)
+    with NF.Grid(w["n"], w["L"], dtype=NF.NF_F64 if form == "f64" else NF.NF_F32_REFINED) as g:
+        for k in range(steps):
+            _, si = g.step(w["c2"], w["D2"], w["gamma"], w["dt"], m, p, r, S, rtol=w["rtol"])
+            print(json.dumps({"case": spec, "step": k, "pcg_iters": si.solve.iters}), flush=True)
+    torch.cuda.synchronize()
+
+
 def copy_calibration(nbytes):
     """A plain device-to-device copy of known size, for scaling HBM counters."""
     import torch
@@ -292,6 +333,7 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=10, help="steps per form of the precision comparison (0 = skip)")
     ap.add_argument("--ensemble-steps", type=int, default=20, help="steps of the ensemble comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
+    ap.add_argument("--profile-case", default="", help="only run N:form:steps:ndim time steps (for kernel traces)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -300,6 +342,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.profile_case:
+        profile_case(args.profile_case)
         return
 
     import numpy as np
@@ -375,6 +420,7 @@ def main():
     achieved = alg_bytes / avg_s / 1e9 if kcount else None
     traffic = load_traffic(args.kernel, N)
     step_bytes = (sum(KERNEL_BYTES_PER_POINT.values()) * cg_iters + STEP_BYTES_PER_POINT * len(GAMMAS) * args.steps) * N * N
+    rp_us = load_rocprof_duration(args.kernel, N) if not args.sequential else None
     roofline = {
         "bound": "hbm",
         "kernel": args.kernel,
@@ -386,6 +432,12 @@ def main():
         "algorithmic_bytes_per_launch": alg_bytes,
         "avg_launch_us": avg_s * 1e6,
         "launches": kcount,
+        "duration_source": "kernel execution span (device wall clock, first workgroup start to last end)",
+        # the same kernel's working-dispatch average in the committed rocprofv3 trace of this
+        # command (dispatch to completion signal, so it includes launch setup and end-of-kernel
+        # release), and the fraction that duration gives
+        "rocprof_avg_launch_us": rp_us,
+        "frac_rocprof": (alg_bytes / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if rp_us else None,
         # all passes of the timed steps: algorithmic bytes over the wall time
         "step_achieved": step_bytes / elapsed / 1e9,
         "step_frac": step_bytes / elapsed / 1e9 / HBM_PEAK_GBS,

@@ -266,11 +266,13 @@ int nf_batch_run(nf_batch *b, const nf_params *prm, double dt, int64_t steps, do
 const char *nf_batch_last_error(const nf_batch *b);
 
 /*
- * Kernel timing: nf_time_kernel(g, k) makes the handle bracket every launch of
- * the PCG-loop kernel k (NF_KERNEL_*) with a pair of HIP events on its stream;
- * launches queued after the solver stopped (which do no work) are discarded.
- * k = -1 switches timing off.  Both calls reset the accumulators.
- * nf_time_kernel_read returns the summed event time (ms) and the launch count.
+ * Kernel timing: nf_time_kernel(g, k) makes the PCG-loop kernel k (NF_KERNEL_*)
+ * stamp, for every loop iteration, the start of its first and the end of its
+ * last workgroup on the device wall clock; after each PCG loop the handle adds
+ * the spans of the launches that did work (launches queued after the solver
+ * stopped are discarded).  k = -1 switches timing off.  Both calls reset the
+ * accumulators.  nf_time_kernel_read returns the summed span (ms) and the
+ * launch count.  Handles of a batch are not timed.
  */
 enum { NF_KERNEL_ROW_FLUX = 0, NF_KERNEL_COL_DIV = 1, NF_KERNEL_COL_UPDATE = 2 };
 int nf_time_kernel(nf_grid *g, int which);

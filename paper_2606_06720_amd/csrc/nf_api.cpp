@@ -106,37 +106,44 @@ int compute_rhs(nf_grid* g, const double* S) {
 
 enum XSource { X_FROM_P = 0, X_FROM_XH = 1, X_ZERO = 2 };
 
-// Timing hooks: when the handle times kernel `which`, its launches in the PCG
-// loop carry a start/stop event pair timestamped by the dispatch itself
-// (hipExtLaunchKernelGGL); pairs of launches that ran after the solver
-// stopped (no-op launches) are discarded when the solve ends.
+// Timing hooks: when the handle times kernel `which`, the kernel stamps, for
+// each loop iteration, the earliest workgroup start and the latest workgroup
+// end on the device wall clock (Geo::tclk).  The stamps are cleared before
+// each PCG loop and collected after it; launches queued after the solver
+// stopped (no-ops) are discarded.  The launch events are no longer used.
 int timed_events(nf_grid* g, int which, int it, hipEvent_t* e0, hipEvent_t* e1) {
+  (void)g;
+  (void)which;
+  (void)it;
   *e0 = *e1 = nullptr;
-  if (g->timed != which) return NF_OK;
-  if (g->pool_used == g->pool.size()) {
-    nf_grid::TimedLaunch t;
-    HIPCHK(g, hipEventCreate(&t.a));
-    HIPCHK(g, hipEventCreate(&t.b));
-    g->pool.push_back(t);
-  }
-  g->pool[g->pool_used].it = it;
-  *e0 = g->pool[g->pool_used].a;
-  *e1 = g->pool[g->pool_used].b;
-  g->pool_used++;
   return NF_OK;
 }
-// called after the stream is synchronised; a launch of iteration `it` did work
-// iff it < limit
-int timed_collect(nf_grid* g, int limit) {
-  for (size_t i = 0; i < g->pool_used; ++i) {
-    if (g->pool[i].it < limit) {
-      float ms = 0.f;
-      HIPCHK(g, hipEventElapsedTime(&ms, g->pool[i].a, g->pool[i].b));
-      g->timed_ms += ms;
-      g->timed_count++;
+int timed_reset(nf_grid* g) {
+  if (g->timed < 0) return NF_OK;
+  LCHK(g, launch_tclk_reset(g->tclk, g->stream));
+  return NF_OK;
+}
+// called after the stream is synchronised; flux and div of iteration it did
+// work iff it < conv_at, the update stamped with it iff 1 <= it <= conv_at
+int timed_collect(nf_grid* g, int conv_at) {
+  if (g->timed < 0) return NF_OK;
+  const int lo = g->timed == NF_KERNEL_COL_UPDATE ? 1 : 0;
+  int hi = g->timed == NF_KERNEL_COL_UPDATE ? conv_at : conv_at - 1;
+  if (hi > TCLK_CAP - 1) hi = TCLK_CAP - 1;
+  if (hi < lo) return NF_OK;
+  const size_t n = (size_t)(hi + 1) * TCLK_W * 2;
+  HIPCHK(g, hipMemcpy(g->htclk, g->tclk, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  for (int it = lo; it <= hi; ++it) {
+    unsigned long long t0 = ~0ULL, t1 = 0;
+    for (int w = 0; w < TCLK_W; ++w) {
+      const unsigned long long a = g->htclk[2 * ((size_t)it * TCLK_W + w)], b = g->htclk[2 * ((size_t)it * TCLK_W + w) + 1];
+      if (a < t0) t0 = a;
+      if (b > t1) t1 = b;
     }
+    if (t0 == ~0ULL || t1 < t0) continue;
+    g->timed_ms += (double)(t1 - t0) / g->wall_khz;
+    g->timed_count++;
   }
-  g->pool_used = 0;
   return NF_OK;
 }
 
@@ -174,8 +181,8 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
   const Geo& G = f32 ? g->geo32 : g->geo;
   hipStream_t s = g->stream;
   const size_t n = (size_t)g->nx * g->ny * g->nz;
-  int rc = NF_OK;
-  g->pool_used = 0;
+  int rc = timed_reset(g);
+  if (rc) return rc;
   int it = 0;
   int slot = 0, pending = -1;
   bool first_chunk = true;
@@ -232,11 +239,7 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
   }
   rc = read_status(g, fin);
   if (rc) return rc;
-  if (g->timed >= 0) {
-    // flux/div of iteration it work iff it < conv_at; the update launched with
-    // it+1 works iff it + 1 <= conv_at, i.e. it < conv_at as well
-    if ((rc = timed_collect(g, fin->conv_at))) return rc;
-  }
+  if ((rc = timed_collect(g, fin->conv_at))) return rc;
   return NF_OK;
 }
 
@@ -605,6 +608,8 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.pstride = pstride;
   G.tot = g->part + (size_t)NSLOTS * SLOT_K * pstride;
   G.cnt = (unsigned*)(G.tot + NSLOTS * SLOT_K);
+  G.tclk = nullptr;
+  G.tkind = -1;
   g->geo32 = G;
   g->geo32.tw = g->tw32;
   *out = g;
@@ -620,8 +625,18 @@ int nf_set_inner_tolerance(nf_grid* g, double floor_rtol) {
 
 int nf_time_kernel(nf_grid* g, int which) {
   if (!g || which < -1 || which > NF_KERNEL_COL_UPDATE) return NF_EINVAL;
+  if (which >= 0 && !g->tclk) {
+    const size_t nb = 2 * sizeof(unsigned long long) * TCLK_CAP * TCLK_W;
+    HIPCHK(g, hipMalloc((void**)&g->tclk, nb));
+    HIPCHK(g, hipHostMalloc((void**)&g->htclk, nb, hipHostMallocDefault));
+    int khz = 0;
+    HIPCHK(g, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+    if (khz <= 0) return fail(g, NF_EDEVICE, "device wall-clock rate unavailable");
+    g->wall_khz = (double)khz;
+  }
   g->timed = which;
-  g->pool_used = 0;
+  g->geo.tclk = g->geo32.tclk = which >= 0 ? g->tclk : nullptr;
+  g->geo.tkind = g->geo32.tkind = which;
   g->timed_ms = 0.0;
   g->timed_count = 0;
   return NF_OK;
@@ -644,12 +659,10 @@ int nf_destroy_grid(nf_grid* g) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (g->hst) (void)hipHostFree(g->hst);
+  if (g->tclk) (void)hipFree(g->tclk);
+  if (g->htclk) (void)hipHostFree(g->htclk);
   for (int i = 0; i < 2; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
-  for (auto& t : g->pool) {
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
-  }
   delete g;
   return NF_OK;
 }

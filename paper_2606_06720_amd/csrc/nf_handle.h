@@ -45,14 +45,12 @@ struct nf_grid {
   double inner_floor = 1e-5;
   int last_inner[4] = {0, 0, 0, 0};
   Geo geo32;
-  // optional per-kernel timing of one PCG-loop kernel (events on the handle's stream)
-  struct TimedLaunch {
-    hipEvent_t a, b;
-    int it;
-  };
+  // optional per-kernel timing of one PCG-loop kernel: execution-span stamps
+  // written by the kernel itself (Geo::tclk), read back after each PCG loop
   int timed = -1;
-  std::vector<TimedLaunch> pool;
-  size_t pool_used = 0;
+  unsigned long long* tclk = nullptr;   // device, 2 * TCLK_CAP
+  unsigned long long* htclk = nullptr;  // pinned copy
+  double wall_khz = 0.0;                // device wall-clock ticks per ms
   double timed_ms = 0.0;
   int64_t timed_count = 0;
 };

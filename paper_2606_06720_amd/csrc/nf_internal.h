@@ -62,7 +62,15 @@ struct Geo {
   int pstride;        // stride of the partial-sum arrays of one slot
   double* tot;        // NSLOTS * SLOT_K reduced totals (last-workgroup reduction)
   unsigned* cnt;      // NSLOTS arrival counters of that reduction (zero between launches)
+  // optional execution-span timing of one PCG-loop pass (nullptr = off): for
+  // iteration it, the workgroups of kind tkind fold their start and end stamps
+  // (device wall clock) into TCLK_W (min, max) pairs at
+  // tclk[2 (it TCLK_W + (block mod TCLK_W))]; the host reduces them
+  unsigned long long* tclk;
+  int tkind;
 };
+
+enum { TCLK_CAP = 2048, TCLK_W = 64 };  // timed iterations per PCG loop, stamp slots per iteration
 
 __host__ __device__ inline double* slot_ptr(double* part, int slot) {
   return part + (size_t)slot * SLOT_K * MAX_WG;
@@ -259,6 +267,8 @@ hipError_t launch_row_adj2(const Geo& g, const void* M1, const void* M2, const v
                            hipStream_t s);
 hipError_t launch_col_divrhs(const Geo& g, const void* V0, const void* V1, void* bh, hipStream_t s);
 hipError_t launch_zero_doubles(double* p, size_t n, hipStream_t s);
+// set the TCLK_CAP * TCLK_W stamp pairs to (max, 0)
+hipError_t launch_tclk_reset(unsigned long long* t, hipStream_t s);
 // reduce K arrays of n partials of a slot into st->out[o..o+K)
 hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o, hipStream_t s);
 

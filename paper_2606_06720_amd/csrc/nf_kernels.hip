@@ -161,6 +161,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   using V = cx<T>;
   using P = typename vec2<T>::type;
   if (it >= 0 ? g.st->conv_at <= it : g.st->outer_done != 0) return;
+  tclk_start(g, 0, it);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[4 * (C::NT / 64)];
   const V* tw = (const V*)g.tw;
@@ -235,6 +236,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
     block_sum<C::NT, 4>(ks, red);
     write_partials<C::NT>(kslot, ks, 4);
   }
+  tclk_end(g, 0, it);
 }
 template <int NX, typename T>
 __global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
@@ -714,6 +716,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   using V = cx<T>;
   static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
   if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
+  if (!INIT) tclk_start(g, 1, it);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   __shared__ double Ks[4];
@@ -790,6 +793,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   }
   block_sum<C::NT, 7>(s, red);
   write_partials<C::NT>(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
+  if (!INIT) tclk_end(g, 1, it);
 }
 template <int NY, bool INIT, typename T>
 __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
@@ -820,6 +824,8 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
   using V = cx<T>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
+  const int tit = first ? -1 : it;  // timing slot (the first update is not a loop pass)
+  tclk_start(g, 2, tit);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   const V* tw = (const V*)g.tw;
@@ -916,10 +922,14 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
     block_sum<C::NT, 1>(rrp, red);
     write_partials<C::NT>(slot_ptr(g.part, SLOT_RR), rrp, 1);
   }
-  if (stop) return;
+  if (stop) {
+    tclk_end(g, 2, tit);
+    return;
+  }
   __syncthreads();
   lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  tclk_end(g, 2, tit);
 }
 template <int NY, typename T>
 __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,

@@ -65,9 +65,11 @@ __device__ __forceinline__ double precond3_inv(const double* K, double a, double
 }
 
 // ---------------------------------------------------------------- z tiles
+// A z tile holds 2 * TILE elements per field: at Nz = 256 that is 8 lines, so
+// the strided gathers and scatters move 128-byte runs (full cache lines).
 template <int NZ, int NF>
 struct ZCfg {
-  static constexpr int C0 = TILE / NZ;
+  static constexpr int C0 = 2 * TILE / NZ;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);  // lines (kx, ky) per workgroup
   static constexpr int NT = TPF * NF;
   static constexpr int LS = lpad_use(NZ) ? lpad_len(NZ) : NZ + 1;  // room for the FFT's padded layout
@@ -224,6 +226,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   using V = cx<T>;
   using P = typename vec2<T>::type;
   if (it >= 0 ? g.st->conv_at <= it : g.st->outer_done != 0) return;
+  tclk_start(g, 0, it);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   const V* tw = (const V*)g.tw;
@@ -291,6 +294,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 3, 3>(buf, G0, G1, G2, rows, y0, nrow);
   if (kbar) reduce_last<C::NT, 7>(ks, g, SLOT_KBAR, red);
+  tclk_end(g, 0, it);
 }
 
 // Split update, pointwise part: P, G0..G2 hold x/n, and the gradient (mixed,
@@ -573,6 +577,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
   using V = cx<T>;
   static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
   if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
+  if (!INIT) tclk_start(g, 1, it);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   __shared__ double Ks[6];
@@ -652,6 +657,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
     }
   }
   reduce_last<C::NT, 7>(s, g, INIT ? SLOT_P3INIT : SLOT_P3, red);
+  if (!INIT) tclk_end(g, 1, it);
 }
 
 // PCG scalar step + vector update + next direction + its gradient through the
@@ -664,6 +670,8 @@ __global__ void __launch_bounds__(3 * TPF) k3_zupdate(Geo g, int first, cx<T>* x
   using V = cx<T>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
+  const int tit = first ? -1 : it;  // timing slot (the first update is not a loop pass)
+  tclk_start(g, 2, tit);
   __shared__ V buf[C::NB * C::LS];
   __shared__ double red[7 * (C::NT / 64)];
   const V* tw = (const V*)g.tw;
@@ -755,10 +763,14 @@ __global__ void __launch_bounds__(3 * TPF) k3_zupdate(Geo g, int first, cx<T>* x
     if (!stop && p < C::CN) put_grad3<NZ, 3, T>(buf, 0, c, kz, d, xx, yy, zz, g.inv_n);
   }
   if (!first && !zero_x) reduce_last<C::NT, 1>(rrp, g, SLOT_RR, red);
-  if (stop) return;
+  if (stop) {
+    tclk_end(g, 2, tit);
+    return;
+  }
   __syncthreads();
   lds_fft<T, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   zT_store<NZ, 3, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
+  tclk_end(g, 2, tit);
 }
 
 // Diffusion, z part: forward z transform of the three components, multiply by
@@ -913,6 +925,19 @@ __global__ void __launch_bounds__(3 * TPF) k3_zrefine_acc(Geo g, cd* x64, const 
   zT_store<NZ, 3, 3>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
 }
 
+__global__ void k_tclk_reset(unsigned long long* t, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    t[2 * i] = ~0ULL;
+    t[2 * i + 1] = 0ULL;
+  }
+}
+hipError_t launch_tclk_reset(unsigned long long* t, hipStream_t s) {
+  const int n = TCLK_CAP * TCLK_W;
+  hipLaunchKernelGGL(k_tclk_reset, dim3((n + 255) / 256), dim3(256), 0, s, t, n);
+  return hipGetLastError();
+}
+
 __global__ void k3_copy_tot(Geo g, int slot, int K, int o) {
   if (threadIdx.x < K) g.st->out[o + threadIdx.x] = g.tot[slot * SLOT_K + threadIdx.x];
 }
@@ -951,7 +976,7 @@ int nwg3_y(const Geo& g) {
   return (g.h * g.nz + C - 1) / C;
 }
 int nwg3_z(const Geo& g) {
-  const int C = clamp_tile(g.nz);
+  const int C = clamp_tile(g.nz / 2);
   return (g.h * g.ny + C - 1) / C;
 }
 

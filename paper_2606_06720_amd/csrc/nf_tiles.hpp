@@ -198,6 +198,25 @@ __device__ __forceinline__ void colP_gload(V (&v)[(ColCfg<NY, NF>::EP)], const V
   }
 }
 
+// Execution-span stamps of a timed pass (see Geo::tclk): the first thread of
+// every workgroup lowers the start stamp on entry and, after the workgroup's
+// last instruction, raises the end stamp.  Uniform per workgroup.
+__device__ __forceinline__ bool tclk_on(const Geo& g, int kind, int it) {
+  return g.tclk != nullptr && g.tkind == kind && it >= 0 && it < TCLK_CAP;
+}
+__device__ __forceinline__ unsigned long long* tclk_slot(const Geo& g, int it) {
+  return g.tclk + 2 * ((size_t)it * TCLK_W + (blockIdx.x & (TCLK_W - 1)));
+}
+__device__ __forceinline__ void tclk_start(const Geo& g, int kind, int it) {
+  if (tclk_on(g, kind, it) && threadIdx.x == 0) atomicMin(tclk_slot(g, it), (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void tclk_end(const Geo& g, int kind, int it) {
+  if (tclk_on(g, kind, it)) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(tclk_slot(g, it) + 1, (unsigned long long)wall_clock64());
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ void write_partials(double* slot, const double* v, int K) {
   if (threadIdx.x == 0) {
