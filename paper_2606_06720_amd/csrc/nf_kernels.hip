@@ -170,10 +170,6 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   const size_t n = (size_t)g.nx * g.ny;
   V tv[C::ET];
   rowT_gload<NX, 2>(tv, G0, G1, nullptr, g.ny, y0, nrow);
-  P mx[C::EP], my[C::EP], rv[C::EP];
-  rowP_gload<NX, 2>(mx, m, y0, nrow);
-  rowP_gload<NX, 2>(my, m + n, y0, nrow);
-  rowP_gload<NX, 2>(rv, r, y0, nrow);
   if (it >= 1) {
     double rr[1];
     sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
@@ -189,6 +185,17 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
       return;
     }
   }
+  rowT_put<NX, 2>(buf, tv);
+  __syncthreads();
+  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  // m and r are loaded only now: held across the transform they would cost
+  // about 48 registers, and a workgroup with fewer registers shares a compute
+  // unit more easily with the passes of concurrent solves
+  P mx[C::EP], my[C::EP], rv[C::EP];
+  rowP_gload<NX, 2>(mx, m, y0, nrow);
+  rowP_gload<NX, 2>(my, m + n, y0, nrow);
+  rowP_gload<NX, 2>(rv, r, y0, nrow);
   if (lo) {
 #pragma unroll
     for (int i = 0; i < C::EP; ++i) {
@@ -202,10 +209,6 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
       }
     }
   }
-  rowT_put<NX, 2>(buf, tv);
-  __syncthreads();
-  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double ks[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -722,14 +725,8 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   __shared__ double Ks[4];
   const V* tw = (const V*)g.tw;
   const int kx0 = blockIdx.x * C::C;
-  V tv[C::ET], av[C::EP], bv[C::EP];
+  V tv[C::ET];
   colT_gload<NY, 2, 2>(tv, Fx, Fy, kx0, g.h);
-  if (INIT) {
-    colP_gload<NY, 2>(av, bh, kx0, g.h);
-  } else {
-    colP_gload<NY, 2>(av, dh, kx0, g.h);
-    colP_gload<NY, 2>(bv, rh, kx0, g.h);
-  }
   if (INIT) {
     double kb[4], sc[2];
     sum_partials<C::NT, 4>(slot_ptr(g.part, SLOT_KBAR), nwg_row, MAX_WG, kb, red);
@@ -750,6 +747,15 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   colT_put<NY, 2, 2>(buf, tv);
   __syncthreads();
   lds_fft<T, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  // the vectors of the dot products are loaded after the transform (fewer
+  // registers held across it)
+  V av[C::EP], bv[C::EP];
+  if (INIT) {
+    colP_gload<NY, 2>(av, bh, kx0, g.h);
+  } else {
+    colP_gload<NY, 2>(av, dh, kx0, g.h);
+    colP_gload<NY, 2>(bv, rh, kx0, g.h);
+  }
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
