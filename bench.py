@@ -251,7 +251,9 @@ def ensemble_cost(steps, mix=None):
         ms = [T(w["m0"]) for w in inst]
         ps = [torch.zeros_like(x) for x in rs]
         with NF.Batch([w["n"] for w in inst], dtype=dt_) as b:
+            # the first run tunes the partition count (not timed)
             b.run(prm, dt, 2, ms, ps, rs, Ss, rtol=rtol)
+            parts, tune_ms = b.partitions()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             infos = b.run(prm, dt, steps, ms, ps, rs, Ss, rtol=rtol)
@@ -276,6 +278,8 @@ def ensemble_cost(steps, mix=None):
             "batch_speedup": ts / tb,
             "bitwise_equal_to_one_by_one": all(torch.equal(a, c) for a, c in zip(ms, ms2)),
             "pcg_iters_per_solve": sum(i.total_cg_iters for i in infos) / (len(inst) * steps),
+            "partitions": parts,
+            "tuning_ms_two_steps_by_partition_count": [round(t, 2) for t in tune_ms],
         }
         del ms, ps, ms2, ps2
         torch.cuda.empty_cache()

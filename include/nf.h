@@ -254,7 +254,25 @@ int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double
  *   violates the solvability condition; nothing is advanced), NF_ENONFINITE
  *   (the run stops for all instances after the step that produced it),
  *   NF_EINVAL or NF_EDEVICE.  Unconverged solves are counted per instance as
- *   in nf_run.
+ *   in nf_run.  The call returns when all the work is complete.
+ *
+ * Partitions: the instances are split into 1 to 4 partitions of about equal
+ * grid-point counts, each with its own HIP stream (created by the batch,
+ * default priority) and host thread, forked from and complete before the
+ * return to the batch's stream.  Partitions overlap each other's transform
+ * and memory phases.  They meet after the first solve and after every step,
+ * so a stop (NF_EINCOMPAT, NF_ENONFINITE, a device error) ends all of them at
+ * the same point; the fields are those above for every partition count.
+ * nf_batch_set_partitions: parts 0 (the default) tunes the count at the next
+ *   nf_batch_run: every count from 1 to min(4, count) runs two steps on
+ *   scratch copies of m and p (device memory for 3 doubles per grid point,
+ *   freed before the run; the caller's fields are not written) and the fastest
+ *   is kept for the following runs.  parts in [1, min(4, count)] fixes it.
+ *   NF_EINVAL otherwise.
+ * nf_batch_partitions: the partition count in use (0 before the first run
+ *   when tuning); tune_ms (NULL or 4 entries) receives the tuning time of
+ *   each candidate count (ms for the two steps, -1 where none was taken).
+ *   Returns NF_EINVAL (< 0) for a NULL handle.
  */
 typedef struct nf_batch nf_batch;
 int nf_batch_create(nf_batch **out, int count, const int64_t *n, const double *L, int dtype, void *stream);
@@ -263,6 +281,8 @@ int nf_batch_destroy(nf_batch *b);
 int nf_batch_set_stream(nf_batch *b, void *stream);
 int nf_batch_run(nf_batch *b, const nf_params *prm, double dt, int64_t steps, double *const *m, double *const *p,
                  const double *const *r, const double *const *S, double rtol, int max_iter, nf_run_info *info);
+int nf_batch_set_partitions(nf_batch *b, int parts);
+int nf_batch_partitions(const nf_batch *b, double *tune_ms);
 const char *nf_batch_last_error(const nf_batch *b);
 
 /*

@@ -1,18 +1,30 @@
 // Host side of the ensemble entry points (nf_batch_*, include/nf.h).
 //
-// Each instance owns the workspace of one nf_grid; their status blocks are
-// moved into one contiguous array so that a single copy polls them all.
-// Instances of equal grid shape form a launch group: every pass of the time
-// step (Algorithm 1) and every PCG iteration is one launch per group, with the
-// instance as the second grid dimension and its pointers and parameters read
-// from a device table of per-instance argument structs.  The kernel bodies are
-// those of the single-instance entry points, so each instance computes exactly
-// what nf_run computes for it.
+// Each instance owns the workspace of one nf_grid.  The instances are split
+// into partitions; a partition has its own HIP stream and host thread, and
+// its instances' status blocks are moved into one contiguous array so that a
+// single copy polls them all.  Within a partition, instances of equal grid
+// shape form a launch group: every pass of the time step (Algorithm 1) and
+// every PCG iteration is one launch per group, with the instance as the second
+// grid dimension and its pointers and parameters read from a device table of
+// per-instance argument structs.  The kernel bodies are those of the
+// single-instance entry points, so each instance computes exactly what nf_run
+// computes for it, whatever the partition.
+//
+// The partition count is tuned: unless the caller fixes it, the first
+// nf_batch_run times two steps of every candidate count on scratch copies of
+// m and p and keeps the fastest.  Different partitions overlap one another's
+// transform and memory phases, which identical kernels of one launch cannot.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
+#include <condition_variable>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "nf.h"
@@ -39,13 +51,13 @@ struct Tables {
   SumArgs *sum_rr = nullptr, *sum_dm = nullptr;
 };
 
-}  // namespace
-
-struct nf_batch {
+// One partition: a subset of the instances, with its own stream and statuses.
+struct Part {
   int count = 0;
   int dtype = NF_F64;
-  hipStream_t stream = nullptr;
-  std::vector<nf_grid*> inst;
+  hipStream_t stream = nullptr;  // owned
+  std::vector<nf_grid*> inst;    // not owned
+  std::vector<int> gidx;         // ensemble index of each instance
   DevStatus* st = nullptr;   // count contiguous statuses
   DevStatus* hst = nullptr;  // pinned, 2 * count
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -64,9 +76,23 @@ struct nf_batch {
   std::string err;
 };
 
+}  // namespace
+
+struct nf_batch {
+  int count = 0;
+  int dtype = NF_F64;
+  hipStream_t stream = nullptr;   // the caller's stream
+  std::vector<nf_grid*> inst;     // owned
+  std::vector<Part*> parts;
+  int nparts = 0;                 // 0: tune at the next run
+  hipEvent_t fork = nullptr;
+  std::vector<double> tune_ms;    // step time of each candidate count (index = count - 1)
+  std::string err;
+};
+
 namespace {
 
-int bfail(nf_batch* b, int code, const std::string& msg) {
+int bfail(Part* b, int code, const std::string& msg) {
   b->err = msg;
   return code;
 }
@@ -104,7 +130,7 @@ T* at(char* base, size_t off) {
   return reinterpret_cast<T*>(base + off);
 }
 
-void bind_tables(nf_batch::Group& G, char* base, const Layout& L) {
+void bind_tables(Part::Group& G, char* base, const Layout& L) {
   Tables& t = G.t;
   t.flux_init = at<FluxArgs>(base, L.off[0]);
   t.flux_init_lo = at<FluxArgs>(base, L.off[1]);
@@ -127,12 +153,12 @@ void bind_tables(nf_batch::Group& G, char* base, const Layout& L) {
 }
 
 // Fill the host image of a group's tables for one run and copy it to the device.
-int upload_tables(nf_batch* b, nf_batch::Group& G, const nf_params* prm, double dt, double* const* m,
+int upload_tables(Part* b, Part::Group& G, const nf_params* prm, double dt, double* const* m,
                   double* const* p, const double* const* r) {
   const int k = (int)G.idx.size();
   const Layout L = layout(k);
   char* hb = G.host.data();
-  nf_batch::Group H;  // host-side view of the same layout
+  Part::Group H;  // host-side view of the same layout
   bind_tables(H, hb, L);
   for (int j = 0; j < k; ++j) {
     const int i = G.idx[j];
@@ -164,7 +190,7 @@ int upload_tables(nf_batch* b, nf_batch::Group& G, const nf_params* prm, double 
   return NF_OK;
 }
 
-int read_all(nf_batch* b) {
+int read_all(Part* b) {
   BCHK(b, hipMemcpyAsync(b->fin.data(), b->st, sizeof(DevStatus) * b->count, hipMemcpyDeviceToHost, b->stream));
   BCHK(b, hipStreamSynchronize(b->stream));
   return NF_OK;
@@ -172,7 +198,7 @@ int read_all(nf_batch* b) {
 
 // PCG iterations of all instances, chunked and polled as in the single-instance
 // loop; stops once every instance's status reports a stop.
-int batch_loop(nf_batch* b, bool f32, int max_iter, double tol2, int expect) {
+int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
   hipStream_t s = b->stream;
   const int c = b->count;
   int it = 0, slot = 0, pending = -1;
@@ -211,7 +237,7 @@ struct SolveRes {
 // Pressure solves of all instances (the pcg / pcg_refined sequence of the
 // single-instance path, batched).  first: warm start from p, else from the
 // spectral iterate kept from the previous solve.
-int batch_solve(nf_batch* b, bool first, double* const* p, double rtol, int max_iter, SolveRes* out) {
+int batch_solve(Part* b, bool first, double* const* p, double rtol, int max_iter, SolveRes* out) {
   hipStream_t s = b->stream;
   const int c = b->count;
   BCHK(b, launchb_status_reset(b->st, c, 0, s));
@@ -283,113 +309,56 @@ int batch_solve(nf_batch* b, bool first, double* const* p, double rtol, int max_
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-const char* nf_batch_last_error(const nf_batch* b) { return b ? b->err.c_str() : batch_create_err.c_str(); }
-
-int nf_batch_destroy(nf_batch* b) {
-  if (!b) return NF_OK;
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
-  else (void)hipDeviceSynchronize();
-  for (nf_grid* g : b->inst) {
-    if (!g) continue;
-    g->st = g->st_own;
-    g->geo.st = g->st_own;
-    g->geo32.st = g->st_own;
-    nf_destroy_grid(g);
+// Host-side meeting point of the partitions after the first solve and after
+// every step: a stop reported by any partition (incompatible S, non-finite
+// activation, a device error) stops all of them at the same point, as in a
+// single-partition run.  A partition that returns early leaves the barrier.
+struct StepSync {
+  std::mutex mu;
+  std::condition_variable cv;
+  int live;
+  int arrived = 0;
+  int64_t gen = 0;
+  bool flag = false, last = false, sticky = false;
+  explicit StepSync(int k) : live(k) {}
+  void complete() {
+    last = flag || sticky;
+    flag = false;
+    arrived = 0;
+    ++gen;
+    cv.notify_all();
   }
-  for (auto& G : b->groups)
-    if (G.dev) (void)hipFree(G.dev);
-  if (b->st) (void)hipFree(b->st);
-  if (b->hst) (void)hipHostFree(b->hst);
-  for (int i = 0; i < 2; ++i)
-    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
-  delete b;
-  return NF_OK;
-}
-
-int nf_batch_set_stream(nf_batch* b, void* stream) {
-  if (!b) return NF_EINVAL;
-  b->stream = (hipStream_t)stream;
-  return NF_OK;
-}
-
-int nf_batch_create(nf_batch** out, int count, const int64_t* n, const double* L, int dtype, void* stream) {
-  if (!out) return NF_EINVAL;
-  *out = nullptr;
-  batch_create_err.clear();
-  if (count < 1 || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) {
-    batch_create_err = "count >= 1, non-NULL n and L and a valid dtype are required";
-    return NF_EINVAL;
-  }
-  nf_batch* b = new nf_batch();
-  b->count = count;
-  b->dtype = dtype;
-  b->stream = (hipStream_t)stream;
-  b->inst.assign(count, nullptr);
-  hipError_t herr = hipSuccess;
-  auto bail = [&](int code, const std::string& what) {
-    batch_create_err = what + (herr != hipSuccess ? std::string(": ") + hipGetErrorString(herr) : "");
-    nf_batch_destroy(b);
-    return code;
-  };
-  for (int i = 0; i < count; ++i) {
-    const int64_t nn[3] = {n[2 * i], n[2 * i + 1], 1};
-    const double LL[3] = {L[2 * i], L[2 * i + 1], 1.0};
-    const int rc = nf_create_grid(&b->inst[i], 2, nn, LL, dtype, stream);
-    if (rc != NF_OK) return bail(rc, "instance " + std::to_string(i) + ": " + nf_last_error(nullptr));
-  }
-  if ((herr = hipMalloc((void**)&b->st, sizeof(DevStatus) * count)) != hipSuccess) return bail(NF_ENOMEM, "hipMalloc(st)");
-  if ((herr = hipMemset(b->st, 0, sizeof(DevStatus) * count)) != hipSuccess) return bail(NF_EDEVICE, "hipMemset(st)");
-  if ((herr = hipHostMalloc((void**)&b->hst, 2 * sizeof(DevStatus) * count, hipHostMallocDefault)) != hipSuccess)
-    return bail(NF_ENOMEM, "hipHostMalloc(status)");
-  for (int i = 0; i < 2; ++i)
-    if ((herr = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming)) != hipSuccess)
-      return bail(NF_EDEVICE, "hipEventCreate");
-  b->fin.resize(count);
-  for (int i = 0; i < count; ++i) {
-    nf_grid* g = b->inst[i];
-    g->st = b->st + i;
-    g->geo.st = g->st;
-    g->geo32.st = g->st;
-    // group by shape and box
-    nf_batch::Group* grp = nullptr;
-    for (auto& G : b->groups) {
-      const nf_grid* h = b->inst[G.idx[0]];
-      if (h->nx == g->nx && h->ny == g->ny && h->lx == g->lx && h->ly == g->ly) grp = &G;
+  // report this partition's stop condition; true if any partition stops
+  bool arrive(bool stop) {
+    std::unique_lock<std::mutex> lk(mu);
+    flag = flag || stop;
+    const int64_t g = gen;
+    if (++arrived >= live) {
+      complete();
+      return last;
     }
-    if (!grp) {
-      b->groups.emplace_back();
-      grp = &b->groups.back();
-      grp->shape = g->geo;
-    }
-    grp->idx.push_back(i);
+    cv.wait(lk, [&] { return gen != g; });
+    return last;
   }
-  for (auto& G : b->groups) {
-    const Layout Lo = layout((int)G.idx.size());
-    G.bytes = Lo.total;
-    G.host.assign(Lo.total, 0);
-    if ((herr = hipMalloc((void**)&G.dev, Lo.total)) != hipSuccess) return bail(NF_ENOMEM, "hipMalloc(tables)");
-    bind_tables(G, G.dev, Lo);
+  void leave(bool error) {
+    std::lock_guard<std::mutex> lk(mu);
+    sticky = sticky || error;
+    --live;
+    if (arrived > 0 && arrived >= live) complete();
   }
-  *out = b;
-  return NF_OK;
-}
+};
 
-int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, double* const* m, double* const* p,
-                 const double* const* r, const double* const* S, double rtol, int max_iter, nf_run_info* info) {
-  if (!b) return NF_EINVAL;
+// returned by a partition that stopped because another one did
+constexpr int NF_STOPPED_BY_OTHER = 1;
+
+// nf_batch_run for the instances of one partition (arrays indexed locally).
+int part_run(Part* b, StepSync* sync, const nf_params* prm, double dt, int64_t steps, double* const* m,
+             double* const* p, const double* const* r, const double* const* S, double rtol, int max_iter,
+             nf_run_info* info) {
   b->err.clear();
   const int c = b->count;
-  if (!prm || !m || !p || !r || !S) return bfail(b, NF_EINVAL, "NULL argument array");
-  if (!(dt > 0.0)) return bfail(b, NF_EINVAL, "dt must be > 0");
-  if (!(rtol >= 0.0) || max_iter < 0 || steps < 1)
-    return bfail(b, NF_EINVAL, "rtol >= 0, max_iter >= 0 and steps >= 1 required");
-  for (int i = 0; i < c; ++i) {
-    if (!m[i] || !p[i] || !r[i] || !S[i]) return bfail(b, NF_EINVAL, "NULL field pointer of instance " + std::to_string(i));
-    if (!(prm[i].gamma > 0.0) || !(prm[i].c2 >= 0.0) || !(prm[i].D2 >= 0.0))
-      return bfail(b, NF_EINVAL, "invalid params of instance " + std::to_string(i));
-  }
   hipStream_t s = b->stream;
   std::vector<nf_run_info> ri(c);
   for (auto& x : ri) {
@@ -423,11 +392,12 @@ int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, do
     ri[i].total_cg_iters += sr.iters[i];
     if (b->fin[i].flags & FLAG_INCOMPAT) {
       ri[i].stop_reason = NF_STOP_ERROR;
-      rc = bfail(b, NF_EINCOMPAT, "instance " + std::to_string(i) + ": S violates the solvability condition");
+      rc = bfail(b, NF_EINCOMPAT, "instance " + std::to_string(b->gidx[i]) + ": S violates the solvability condition");
     } else if (!sr.converged[i]) {
       ri[i].unconverged_solves++;
     }
   }
+  if (sync->arrive(rc != NF_OK) && rc == NF_OK) return finish(NF_STOPPED_BY_OTHER);
   if (rc) return finish(rc);
   for (int64_t step = 0; step < steps; ++step) {
     for (auto& G : b->groups) {
@@ -451,6 +421,7 @@ int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, do
         ri[i].unconverged_solves++;
       }
     }
+    if (sync->arrive(bad) && !bad) return finish(NF_STOPPED_BY_OTHER);
     if (bad) return finish(bfail(b, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step"));
   }
   // Delta m of the last step and p = p[m_final]
@@ -472,6 +443,325 @@ int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, do
     }
   }
   return finish(rc);
+}
+
+void part_destroy(Part* q) {
+  if (!q) return;
+  if (q->stream) (void)hipStreamSynchronize(q->stream);
+  for (auto& G : q->groups)
+    if (G.dev) (void)hipFree(G.dev);
+  if (q->st) (void)hipFree(q->st);
+  if (q->hst) (void)hipHostFree(q->hst);
+  for (int i = 0; i < 2; ++i)
+    if (q->ev[i]) (void)hipEventDestroy(q->ev[i]);
+  if (q->stream) (void)hipStreamDestroy(q->stream);
+  delete q;
+}
+
+// A partition over the instances idx of the ensemble: its stream (default
+// priority), contiguous statuses (the instances' handles point into them) and
+// the launch groups of its grid shapes.
+int part_create(nf_batch* top, const std::vector<int>& idx, Part** out, std::string& what) {
+  *out = nullptr;
+  Part* q = new Part();
+  q->count = (int)idx.size();
+  q->dtype = top->dtype;
+  q->gidx = idx;
+  hipError_t e = hipSuccess;
+  auto fail = [&](int code, const char* call) {
+    what = std::string(call) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "");
+    part_destroy(q);
+    return code;
+  };
+  if ((e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking)) != hipSuccess)
+    return fail(NF_EDEVICE, "hipStreamCreateWithFlags");
+  if ((e = hipMalloc((void**)&q->st, sizeof(DevStatus) * q->count)) != hipSuccess) return fail(NF_ENOMEM, "hipMalloc(st)");
+  if ((e = hipMemset(q->st, 0, sizeof(DevStatus) * q->count)) != hipSuccess) return fail(NF_EDEVICE, "hipMemset(st)");
+  if ((e = hipHostMalloc((void**)&q->hst, 2 * sizeof(DevStatus) * q->count, hipHostMallocDefault)) != hipSuccess)
+    return fail(NF_ENOMEM, "hipHostMalloc(status)");
+  for (int i = 0; i < 2; ++i)
+    if ((e = hipEventCreateWithFlags(&q->ev[i], hipEventDisableTiming)) != hipSuccess)
+      return fail(NF_EDEVICE, "hipEventCreate");
+  q->fin.resize(q->count);
+  for (int i = 0; i < q->count; ++i) {
+    nf_grid* g = top->inst[idx[i]];
+    q->inst.push_back(g);
+    g->st = q->st + i;
+    g->geo.st = g->st;
+    g->geo32.st = g->st;
+    Part::Group* grp = nullptr;
+    for (auto& G : q->groups) {
+      const nf_grid* h = q->inst[G.idx[0]];
+      if (h->nx == g->nx && h->ny == g->ny && h->lx == g->lx && h->ly == g->ly) grp = &G;
+    }
+    if (!grp) {
+      q->groups.emplace_back();
+      grp = &q->groups.back();
+      grp->shape = g->geo;
+    }
+    grp->idx.push_back(i);
+  }
+  for (auto& G : q->groups) {
+    const Layout Lo = layout((int)G.idx.size());
+    G.bytes = Lo.total;
+    G.host.assign(Lo.total, 0);
+    if ((e = hipMalloc((void**)&G.dev, Lo.total)) != hipSuccess) return fail(NF_ENOMEM, "hipMalloc(tables)");
+    bind_tables(G, G.dev, Lo);
+  }
+  *out = q;
+  return NF_OK;
+}
+
+void parts_clear(nf_batch* b) {
+  for (Part* q : b->parts) part_destroy(q);
+  b->parts.clear();
+  for (nf_grid* g : b->inst) {
+    if (!g) continue;  // creation failed before this instance
+    g->st = g->st_own;
+    g->geo.st = g->st_own;
+    g->geo32.st = g->st_own;
+  }
+}
+
+// Split the instances into k partitions of about equal grid-point counts
+// (largest instances first, each to the lightest partition; ties to the lower
+// partition index, so the split is deterministic).
+int parts_build(nf_batch* b, int k) {
+  parts_clear(b);
+  std::vector<int> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  auto pts = [&](int i) { return (int64_t)b->inst[i]->nx * b->inst[i]->ny; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return pts(a) > pts(c); });
+  std::vector<std::vector<int>> idx(k);
+  std::vector<int64_t> load(k, 0);
+  for (int i : order) {
+    int best = 0;
+    for (int j = 1; j < k; ++j)
+      if (load[j] < load[best]) best = j;
+    idx[best].push_back(i);
+    load[best] += pts(i);
+  }
+  for (auto& v : idx) std::sort(v.begin(), v.end());
+  for (int j = 0; j < k; ++j) {
+    Part* q = nullptr;
+    std::string what;
+    const int rc = part_create(b, idx[j], &q, what);
+    if (rc != NF_OK) {
+      parts_clear(b);
+      b->nparts = 0;
+      b->err = "partition setup: " + what;
+      return rc;
+    }
+    b->parts.push_back(q);
+  }
+  b->nparts = k;
+  return NF_OK;
+}
+
+// Run every partition on its own host thread (the first on the calling one),
+// after the caller's stream has reached this point.
+int parts_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, double* const* m, double* const* p,
+              const double* const* r, const double* const* S, double rtol, int max_iter, nf_run_info* info) {
+  const int k = (int)b->parts.size();
+  hipError_t e = hipEventRecord(b->fork, b->stream);
+  for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->parts[j]->stream, b->fork, 0);
+  if (e != hipSuccess) {
+    b->err = std::string("fork of the partition streams: ") + hipGetErrorString(e);
+    return NF_EDEVICE;
+  }
+  struct Args {
+    std::vector<nf_params> prm;
+    std::vector<double*> m, p;
+    std::vector<const double*> r, S;
+    std::vector<nf_run_info> info;
+    int rc = NF_OK;
+  };
+  std::vector<Args> a(k);
+  for (int j = 0; j < k; ++j) {
+    for (int i : b->parts[j]->gidx) {
+      a[j].prm.push_back(prm[i]);
+      a[j].m.push_back(m[i]);
+      a[j].p.push_back(p[i]);
+      a[j].r.push_back(r[i]);
+      a[j].S.push_back(S[i]);
+    }
+    a[j].info.resize(b->parts[j]->count);
+  }
+  StepSync sync(k);
+  const int dev = b->inst[0]->device;
+  auto go = [&](int j) {
+    // the calling thread (j = 0) already has the device current
+    const hipError_t de = j > 0 ? hipSetDevice(dev) : hipSuccess;
+    a[j].rc = de != hipSuccess ? NF_EDEVICE
+                               : part_run(b->parts[j], &sync, a[j].prm.data(), dt, steps, a[j].m.data(),
+                                          a[j].p.data(), a[j].r.data(), a[j].S.data(), rtol, max_iter,
+                                          a[j].info.data());
+    if (de != hipSuccess) b->parts[j]->err = std::string("hipSetDevice: ") + hipGetErrorString(de);
+    sync.leave(a[j].rc != NF_OK && a[j].rc != NF_STOPPED_BY_OTHER);
+  };
+  std::vector<std::thread> th;
+  for (int j = 1; j < k; ++j) th.emplace_back(go, j);
+  go(0);
+  for (auto& t : th) t.join();
+  // all partition work is complete when the call returns (also after an error)
+  for (int j = 0; j < k; ++j) (void)hipStreamSynchronize(b->parts[j]->stream);
+  int rc = NF_OK;
+  for (int j = 0; j < k; ++j) {
+    if (info)
+      for (int i = 0; i < b->parts[j]->count; ++i) info[b->parts[j]->gidx[i]] = a[j].info[i];
+    if (a[j].rc != NF_OK && a[j].rc != NF_STOPPED_BY_OTHER && rc == NF_OK) {
+      rc = a[j].rc;
+      b->err = b->parts[j]->err;
+    }
+  }
+  return rc;
+}
+
+constexpr int MAX_PARTS = 4;
+
+// Time two steps of every candidate partition count on scratch copies of m
+// and p (the caller's fields are not touched) and keep the fastest.
+int parts_tune(nf_batch* b, const nf_params* prm, double dt, double* const* m, double* const* p,
+               const double* const* r, const double* const* S, double rtol, int max_iter) {
+  const int c = b->count;
+  std::vector<size_t> off(c + 1, 0);
+  for (int i = 0; i < c; ++i) off[i + 1] = off[i] + 3 * (size_t)b->inst[i]->nx * b->inst[i]->ny;
+  double* scratch = nullptr;
+  hipError_t e = hipMalloc((void**)&scratch, sizeof(double) * off[c]);
+  if (e != hipSuccess) {
+    b->err = std::string("hipMalloc(tuning scratch): ") + hipGetErrorString(e);
+    return NF_ENOMEM;
+  }
+  std::vector<double*> ms(c), ps(c);
+  for (int i = 0; i < c; ++i) {
+    const size_t n = (size_t)b->inst[i]->nx * b->inst[i]->ny;
+    ms[i] = scratch + off[i];
+    ps[i] = scratch + off[i] + 2 * n;
+  }
+  const int kmax = c < MAX_PARTS ? c : MAX_PARTS;
+  b->tune_ms.assign(kmax, -1.0);
+  int best = 1;
+  double best_ms = 0.0;
+  for (int k = 1; k <= kmax; ++k) {
+    int rc = parts_build(b, k);
+    if (rc != NF_OK) break;
+    for (int i = 0; i < c && e == hipSuccess; ++i) {
+      const size_t n = (size_t)b->inst[i]->nx * b->inst[i]->ny;
+      e = hipMemcpyAsync(ms[i], m[i], sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, b->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(ps[i], p[i], sizeof(double) * n, hipMemcpyDeviceToDevice, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = parts_run(b, prm, dt, 2, ms.data(), ps.data(), r, S, rtol, max_iter, nullptr);
+    const double ms_k = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rc != NF_OK) break;  // the real run reports the error
+    b->tune_ms[k - 1] = ms_k;
+    if (k == 1 || ms_k < best_ms) {
+      best = k;
+      best_ms = ms_k;
+    }
+  }
+  (void)hipFree(scratch);
+  b->err.clear();
+  return parts_build(b, best);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nf_batch_last_error(const nf_batch* b) { return b ? b->err.c_str() : batch_create_err.c_str(); }
+
+int nf_batch_destroy(nf_batch* b) {
+  if (!b) return NF_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  parts_clear(b);
+  for (nf_grid* g : b->inst)
+    if (g) nf_destroy_grid(g);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+  return NF_OK;
+}
+
+int nf_batch_set_stream(nf_batch* b, void* stream) {
+  if (!b) return NF_EINVAL;
+  b->stream = (hipStream_t)stream;
+  return NF_OK;
+}
+
+int nf_batch_set_partitions(nf_batch* b, int parts) {
+  if (!b) return NF_EINVAL;
+  if (parts < 0 || parts > MAX_PARTS || parts > b->count) {
+    b->err = "partitions must be 0 (tune) or in [1, min(4, count)]";
+    return NF_EINVAL;
+  }
+  if (parts == 0) {
+    parts_clear(b);
+    b->nparts = 0;
+    return NF_OK;
+  }
+  return parts_build(b, parts);
+}
+
+int nf_batch_partitions(const nf_batch* b, double* tune_ms) {
+  if (!b) return NF_EINVAL;
+  if (tune_ms)
+    for (int k = 0; k < MAX_PARTS; ++k) tune_ms[k] = k < (int)b->tune_ms.size() ? b->tune_ms[k] : -1.0;
+  return b->nparts;
+}
+
+int nf_batch_create(nf_batch** out, int count, const int64_t* n, const double* L, int dtype, void* stream) {
+  if (!out) return NF_EINVAL;
+  *out = nullptr;
+  batch_create_err.clear();
+  if (count < 1 || !n || !L || (dtype != NF_F64 && dtype != NF_F32_REFINED)) {
+    batch_create_err = "count >= 1, non-NULL n and L and a valid dtype are required";
+    return NF_EINVAL;
+  }
+  nf_batch* b = new nf_batch();
+  b->count = count;
+  b->dtype = dtype;
+  b->stream = (hipStream_t)stream;
+  b->inst.assign(count, nullptr);
+  hipError_t herr = hipSuccess;
+  auto bail = [&](int code, const std::string& what) {
+    batch_create_err = what + (herr != hipSuccess ? std::string(": ") + hipGetErrorString(herr) : "");
+    nf_batch_destroy(b);
+    return code;
+  };
+  for (int i = 0; i < count; ++i) {
+    const int64_t nn[3] = {n[2 * i], n[2 * i + 1], 1};
+    const double LL[3] = {L[2 * i], L[2 * i + 1], 1.0};
+    const int rc = nf_create_grid(&b->inst[i], 2, nn, LL, dtype, stream);
+    if (rc != NF_OK) return bail(rc, "instance " + std::to_string(i) + ": " + nf_last_error(nullptr));
+  }
+  if ((herr = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
+    return bail(NF_EDEVICE, "hipEventCreate");
+  *out = b;
+  return NF_OK;
+}
+
+int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, double* const* m, double* const* p,
+                 const double* const* r, const double* const* S, double rtol, int max_iter, nf_run_info* info) {
+  if (!b) return NF_EINVAL;
+  b->err.clear();
+  const int c = b->count;
+  if (!prm || !m || !p || !r || !S) return (b->err = "NULL argument array", NF_EINVAL);
+  if (!(dt > 0.0)) return (b->err = "dt must be > 0", NF_EINVAL);
+  if (!(rtol >= 0.0) || max_iter < 0 || steps < 1)
+    return (b->err = "rtol >= 0, max_iter >= 0 and steps >= 1 required", NF_EINVAL);
+  for (int i = 0; i < c; ++i) {
+    if (!m[i] || !p[i] || !r[i] || !S[i]) return (b->err = "NULL field pointer of instance " + std::to_string(i), NF_EINVAL);
+    if (!(prm[i].gamma > 0.0) || !(prm[i].c2 >= 0.0) || !(prm[i].D2 >= 0.0))
+      return (b->err = "invalid params of instance " + std::to_string(i), NF_EINVAL);
+  }
+  if (b->nparts == 0) {
+    const int rc = parts_tune(b, prm, dt, m, p, r, S, rtol, max_iter);
+    if (rc != NF_OK) return rc;
+  }
+  return parts_run(b, prm, dt, steps, m, p, r, S, rtol, max_iter, info);
 }
 
 }  // extern "C"

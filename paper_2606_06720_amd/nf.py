@@ -105,6 +105,8 @@ def _load():
     lib.nf_batch_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, ctypes.POINTER(vp),
                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ctypes.c_int,
                                  ctypes.POINTER(nf_run_info)]
+    lib.nf_batch_set_partitions.argtypes = [vp, ctypes.c_int]
+    lib.nf_batch_partitions.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nf_batch_last_error.argtypes = [vp]
     lib.nf_batch_last_error.restype = ctypes.c_char_p
     lib.nf_last_error.argtypes = [vp]
@@ -113,7 +115,7 @@ def _load():
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
               "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_batch_create", "nf_batch_destroy",
-              "nf_batch_set_stream", "nf_batch_run"):
+              "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -365,6 +367,20 @@ class Batch:
     def __exit__(self, *a):
         self.close()
 
+    def set_partitions(self, parts):
+        """nf_batch_set_partitions: 0 tunes the count at the next run."""
+        rc = _lib.nf_batch_set_partitions(self._h, int(parts))
+        if rc != NF_OK:
+            raise NfError(rc, _lib.nf_batch_last_error(self._h).decode())
+
+    def partitions(self):
+        """nf_batch_partitions: (count in use, tuning ms per candidate count)."""
+        t = (ctypes.c_double * 4)()
+        k = _lib.nf_batch_partitions(self._h, t)
+        if k < 0:
+            raise NfError(k, "nf_batch_partitions failed")
+        return k, [v for v in t]
+
     def run(self, params, dt, steps, m, p, r, S, rtol=1e-10, max_iter=1000):
         """nf_batch_run: params is a list of (c2, D2, gamma); m, p, r, S lists of
         device tensors (one per instance, shapes as for Grid.run).  Returns the
@@ -434,3 +450,11 @@ def nf_batch_destroy(b):
 
 def nf_batch_run(b, params, dt, steps, m, p, r, S, rtol=1e-10, max_iter=1000):
     return b.run(params, dt, steps, m, p, r, S, rtol, max_iter)
+
+
+def nf_batch_set_partitions(b, parts):
+    return b.set_partitions(parts)
+
+
+def nf_batch_partitions(b):
+    return b.partitions()

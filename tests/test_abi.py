@@ -67,3 +67,19 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.nf_destroy_grid(None) == 0
     lib.nf_set_inner_tolerance.argtypes = [ctypes.c_void_p, ctypes.c_double]
     assert lib.nf_set_inner_tolerance(None, 1e-5) == -1
+    lib.nf_batch_set_partitions.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert lib.nf_batch_set_partitions(None, 1) == -1
+    lib.nf_batch_partitions.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.nf_batch_partitions(None, None) == -1
+
+
+def test_batch_create_rejects_bad_sizes_on_host(lib):
+    # the failure path frees a partly built ensemble (instances not created yet)
+    lib.nf_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    for sizes in ((32, 33), (7, 64, 32, 32)):
+        h = ctypes.c_void_p()
+        nn = (ctypes.c_int64 * len(sizes))(*sizes)
+        LL = (ctypes.c_double * len(sizes))(*([1.0] * len(sizes)))
+        assert lib.nf_batch_create(ctypes.byref(h), len(sizes) // 2, nn, LL, 0, None) == -1
+        assert not h.value

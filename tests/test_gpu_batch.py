@@ -1,7 +1,9 @@
 """GPU tests of the ensemble entry points (nf_batch_create / nf_batch_run):
 every instance of a batch must produce bitwise the fields and counters of
-nf_run on its own handle (same kernel bodies, deterministic reductions), and
-the oracle's time loop within the FP64 bar."""
+nf_run on its own handle (same kernel bodies, deterministic reductions),
+whatever the partition count (fixed or tuned), and the oracle's time loop
+within the FP64 bar.  A stop in one partition ends all of them at the same
+point."""
 
 import numpy as np
 import pytest
@@ -40,14 +42,20 @@ def _key(info):
     return (info.steps, info.stop_reason, info.last_dm, info.total_cg_iters, info.unconverged_solves)
 
 
-def _run_batch(env, inst, dtype, steps, dt, rtol):
+def _run_batch(env, inst, dtype, steps, dt, rtol, parts=None, out=None):
     NF, T, torch = env
     ms = [T(w["m0"]) for w in inst]
     ps = [torch.zeros_like(T(w["r"])) for w in inst]
     rs = [T(w["r"]) for w in inst]
     Ss = [T(w["S"]) for w in inst]
+    if out is not None:
+        out.update(m=ms, p=ps)
     with NF.Batch([w["n"] for w in inst], dtype=dtype) as b:
+        if parts is not None:
+            b.set_partitions(parts)
         infos = b.run([w["prm"] for w in inst], dt, steps, ms, ps, rs, Ss, rtol=rtol)
+        if out is not None:
+            out["parts"] = b.partitions()
     return ms, ps, infos
 
 
@@ -112,3 +120,58 @@ def test_batch_failure_paths(env):
     with pytest.raises(NF.NfError) as e:
         NF.Batch([(32, 33)])
     assert e.value.code == NF.NF_EINVAL
+
+
+@pytest.mark.parametrize("dtype_name", ["NF_F64", "NF_F32_REFINED"])
+def test_batch_partition_count_does_not_change_results(env, dtype_name):
+    NF, T, torch = env
+    dtype = getattr(NF, dtype_name)
+    inst = _instances(((64, 3), (128, 2), (32, 2)), 5000)
+    ref = _run_batch(env, inst, dtype, 4, 5e-4, 1e-10, parts=1)
+    for parts in (2, 3, 4, 0):
+        got = {}
+        ms, ps, infos = _run_batch(env, inst, dtype, 4, 5e-4, 1e-10, parts=parts, out=got)
+        k, tune_ms = got["parts"]
+        print("parts", parts, "in use", k, "tuning ms", tune_ms)
+        assert k == (parts if parts else k) and 1 <= k <= 4
+        if parts == 0:
+            # the tuner timed every count up to min(4, count) and kept the fastest
+            assert all(t > 0 for t in tune_ms) and tune_ms[k - 1] == min(tune_ms)
+        for i in range(len(inst)):
+            assert torch.equal(ms[i], ref[0][i]) and torch.equal(ps[i], ref[1][i]), (parts, i)
+            assert _key(infos[i]) == _key(ref[2][i]), (parts, i)
+
+
+def test_batch_partitions_stop_together(env):
+    NF, T, torch = env
+    # incompatible S in one partition: nothing is advanced in any partition
+    inst = _instances(((32, 4),), 6000)
+    inst[3]["S"] = inst[3]["S"] + 1e-3
+    got = {}
+    with pytest.raises(NF.NfError) as e:
+        _run_batch(env, inst, NF.NF_F64, 2, 5e-4, 1e-10, parts=2, out=got)
+    assert e.value.code == NF.NF_EINCOMPAT
+    for i, w in enumerate(inst):
+        assert np.array_equal(got["m"][i].cpu().numpy(), w["m0"]), i
+    # activation overflow in one partition at the first step: every partition
+    # stops after that step, as with a single partition
+    inst = _instances(((32, 4),), 6001)
+    for w in inst:
+        w["prm"] = (1.0, 1e-3, 0.75)
+    inst[2]["prm"] = (1e6, 1e-3, 0.75)
+    inst[2]["S"] = 1e3 * inst[2]["S"]
+    runs = []
+    for parts in (1, 2):
+        got = {}
+        with pytest.raises(NF.NfError) as e:
+            _run_batch(env, inst, NF.NF_F64, 3, 1.0, 1e-10, parts=parts, out=got)
+        assert e.value.code == NF.NF_ENONFINITE
+        runs.append(got)
+    for i in (0, 1, 3):
+        assert torch.equal(runs[0]["m"][i], runs[1]["m"][i]), i
+        assert not np.array_equal(runs[1]["m"][i].cpu().numpy(), inst[i]["m0"]), i
+    with NF.Batch([(32, 32)] * 2) as b:
+        for bad in (-1, 3, 5):
+            with pytest.raises(NF.NfError) as e:
+                b.set_partitions(bad)
+            assert e.value.code == NF.NF_EINVAL
