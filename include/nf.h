@@ -269,6 +269,11 @@ int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double
  *   freed before the run; the caller's fields are not written) and the fastest
  *   is kept for the following runs.  parts in [1, min(4, count)] fixes it.
  *   NF_EINVAL otherwise.
+ * nf_batch_set_graphs: on records each chunk of PCG iterations a partition
+ *   launches (the three passes of every iteration for every grid shape) as a
+ *   HIP graph on first use and replays it afterwards; 0 (the default)
+ *   launches the kernels one by one.  The results are the same either way.
+ *   NF_EINVAL for a NULL handle.
  * nf_batch_partitions: the partition count in use (0 before the first run
  *   when tuning); tune_ms (NULL or 4 entries) receives the tuning time of
  *   each candidate count (ms for the two steps, -1 where none was taken).
@@ -282,6 +287,7 @@ int nf_batch_set_stream(nf_batch *b, void *stream);
 int nf_batch_run(nf_batch *b, const nf_params *prm, double dt, int64_t steps, double *const *m, double *const *p,
                  const double *const *r, const double *const *S, double rtol, int max_iter, nf_run_info *info);
 int nf_batch_set_partitions(nf_batch *b, int parts);
+int nf_batch_set_graphs(nf_batch *b, int on);
 int nf_batch_partitions(const nf_batch *b, double *tune_ms);
 const char *nf_batch_last_error(const nf_batch *b);
 

@@ -15,6 +15,8 @@
 // nf_batch_run times two steps of every candidate count on scratch copies of
 // m and p and keeps the fastest.  Different partitions overlap one another's
 // transform and memory phases, which identical kernels of one launch cannot.
+// Optionally (nf_batch_set_graphs) a partition records each chunk of PCG
+// iterations as a HIP graph and replays it in later solves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,9 +24,12 @@
 #include <climits>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "nf.h"
@@ -74,6 +79,10 @@ struct Part {
   int last_iters = 0;
   int last_inner[4] = {0, 0, 0, 0};
   std::string err;
+  // PCG iteration chunks recorded as HIP graphs, keyed by (first iteration,
+  // iterations, FP32 inner solve, max_iter, tol2 bits)
+  bool use_graphs = false;
+  std::map<std::tuple<int, int, int, int, uint64_t>, hipGraphExec_t> graphs;
 };
 
 }  // namespace
@@ -87,6 +96,7 @@ struct nf_batch {
   int nparts = 0;                 // 0: tune at the next run
   hipEvent_t fork = nullptr;
   std::vector<double> tune_ms;    // step time of each candidate count (index = count - 1)
+  bool use_graphs = false;
   std::string err;
 };
 
@@ -196,6 +206,60 @@ int read_all(Part* b) {
   return NF_OK;
 }
 
+// Iterations it0 .. it0 + nk - 1 of the PCG loop of every launch group (kernel
+// launches only, so that the sequence can be recorded as a graph).
+int launch_chunk(Part* b, bool f32, int it0, int nk, int max_iter, double tol2) {
+  hipStream_t s = b->stream;
+  for (int it = it0; it < it0 + nk; ++it) {
+    for (auto& G : b->groups) {
+      const int k = (int)G.idx.size();
+      BCHK(b, launchb_row_flux(G.shape, f32, f32 ? G.t.flux32 : G.t.flux_loop, k, it, tol2, s));
+      BCHK(b, launchb_col_div(G.shape, f32, false, f32 ? G.t.div32 : G.t.div64, k, it, s));
+      BCHK(b, launchb_col_update(G.shape, f32, f32 ? G.t.upd32 : G.t.upd64, k, 0, it + 1, max_iter, tol2, s));
+    }
+  }
+  return NF_OK;
+}
+
+void graphs_clear(Part* b) {
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+// A chunk of iterations, replayed from its recorded graph (recorded on first
+// use).  The launches read their per-instance arguments from the group tables,
+// whose device addresses are fixed for the partition and whose contents each
+// run uploads before the first chunk, so a recording stays valid across runs.
+int run_chunk(Part* b, bool f32, int it0, int nk, int max_iter, double tol2) {
+  if (!b->use_graphs) return launch_chunk(b, f32, it0, nk, max_iter, tol2);
+  hipStream_t s = b->stream;
+  uint64_t tb;
+  std::memcpy(&tb, &tol2, sizeof tb);
+  const auto key = std::make_tuple(it0, nk, f32 ? 1 : 0, max_iter, tb);
+  auto found = b->graphs.find(key);
+  hipGraphExec_t ex = nullptr;
+  if (found != b->graphs.end()) {
+    ex = found->second;
+  } else {
+    if (b->graphs.size() >= 256) graphs_clear(b);
+    BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_chunk(b, f32, it0, nk, max_iter, tol2);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &gr);
+    if (rc != NF_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    BCHK(b, ee);
+    const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    BCHK(b, ie);
+    b->graphs[key] = ex;
+  }
+  BCHK(b, hipGraphLaunch(ex, s));
+  return NF_OK;
+}
+
 // PCG iterations of all instances, chunked and polled as in the single-instance
 // loop; stops once every instance's status reports a stop.
 int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
@@ -207,15 +271,9 @@ int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
     int nk = first_chunk ? (expect > 6 ? expect - 4 : 2) : 3;
     first_chunk = false;
     if (nk > max_iter - it) nk = max_iter - it;
-    for (int q = 0; q < nk; ++q) {
-      for (auto& G : b->groups) {
-        const int k = (int)G.idx.size();
-        BCHK(b, launchb_row_flux(G.shape, f32, f32 ? G.t.flux32 : G.t.flux_loop, k, it, tol2, s));
-        BCHK(b, launchb_col_div(G.shape, f32, false, f32 ? G.t.div32 : G.t.div64, k, it, s));
-        BCHK(b, launchb_col_update(G.shape, f32, f32 ? G.t.upd32 : G.t.upd64, k, 0, it + 1, max_iter, tol2, s));
-      }
-      ++it;
-    }
+    const int rc = run_chunk(b, f32, it, nk, max_iter, tol2);
+    if (rc != NF_OK) return rc;
+    it += nk;
     BCHK(b, hipMemcpyAsync(b->hst + (size_t)slot * c, b->st, sizeof(DevStatus) * c, hipMemcpyDeviceToHost, s));
     BCHK(b, hipEventRecord(b->ev[slot], s));
     if (pending >= 0) {
@@ -448,6 +506,7 @@ int part_run(Part* b, StepSync* sync, const nf_params* prm, double dt, int64_t s
 void part_destroy(Part* q) {
   if (!q) return;
   if (q->stream) (void)hipStreamSynchronize(q->stream);
+  graphs_clear(q);
   for (auto& G : q->groups)
     if (G.dev) (void)hipFree(G.dev);
   if (q->st) (void)hipFree(q->st);
@@ -466,6 +525,7 @@ int part_create(nf_batch* top, const std::vector<int>& idx, Part** out, std::str
   Part* q = new Part();
   q->count = (int)idx.size();
   q->dtype = top->dtype;
+  q->use_graphs = top->use_graphs;
   q->gidx = idx;
   hipError_t e = hipSuccess;
   auto fail = [&](int code, const char* call) {
@@ -703,6 +763,16 @@ int nf_batch_set_partitions(nf_batch* b, int parts) {
     return NF_OK;
   }
   return parts_build(b, parts);
+}
+
+int nf_batch_set_graphs(nf_batch* b, int on) {
+  if (!b) return NF_EINVAL;
+  b->use_graphs = on != 0;
+  for (Part* q : b->parts) {
+    q->use_graphs = b->use_graphs;
+    if (!q->use_graphs) graphs_clear(q);
+  }
+  return NF_OK;
 }
 
 int nf_batch_partitions(const nf_batch* b, double* tune_ms) {

@@ -107,6 +107,7 @@ def _load():
                                  ctypes.POINTER(nf_run_info)]
     lib.nf_batch_set_partitions.argtypes = [vp, ctypes.c_int]
     lib.nf_batch_partitions.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nf_batch_set_graphs.argtypes = [vp, ctypes.c_int]
     lib.nf_batch_last_error.argtypes = [vp]
     lib.nf_batch_last_error.restype = ctypes.c_char_p
     lib.nf_last_error.argtypes = [vp]
@@ -115,7 +116,8 @@ def _load():
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
               "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_batch_create", "nf_batch_destroy",
-              "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions"):
+              "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions",
+              "nf_batch_set_graphs"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -373,6 +375,12 @@ class Batch:
         if rc != NF_OK:
             raise NfError(rc, _lib.nf_batch_last_error(self._h).decode())
 
+    def set_graphs(self, on):
+        """nf_batch_set_graphs: replay recorded PCG chunks (True) or launch one by one."""
+        rc = _lib.nf_batch_set_graphs(self._h, 1 if on else 0)
+        if rc != NF_OK:
+            raise NfError(rc, "nf_batch_set_graphs failed")
+
     def partitions(self):
         """nf_batch_partitions: (count in use, tuning ms per candidate count)."""
         t = (ctypes.c_double * 4)()
@@ -458,3 +466,7 @@ def nf_batch_set_partitions(b, parts):
 
 def nf_batch_partitions(b):
     return b.partitions()
+
+
+def nf_batch_set_graphs(b, on):
+    return b.set_graphs(on)

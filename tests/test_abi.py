@@ -71,6 +71,8 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.nf_batch_set_partitions(None, 1) == -1
     lib.nf_batch_partitions.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert lib.nf_batch_partitions(None, None) == -1
+    lib.nf_batch_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert lib.nf_batch_set_graphs(None, 1) == -1
 
 
 def test_batch_create_rejects_bad_sizes_on_host(lib):

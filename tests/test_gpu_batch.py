@@ -175,3 +175,33 @@ def test_batch_partitions_stop_together(env):
             with pytest.raises(NF.NfError) as e:
                 b.set_partitions(bad)
             assert e.value.code == NF.NF_EINVAL
+
+
+@pytest.mark.parametrize("dtype_name", ["NF_F64", "NF_F32_REFINED"])
+def test_batch_graph_replays_match_eager_launches(env, dtype_name):
+    # the same handle runs several times (recorded chunks replayed, with the
+    # eager passes of the time step and host synchronisation in between); every
+    # run must be bitwise the run of a handle that launches kernel by kernel
+    NF, T, torch = env
+    dtype = getattr(NF, dtype_name)
+    inst = _instances(((32, 3), (64, 2)), 7000)
+    states = []
+    for graphs in (True, False):
+        ms = [T(w["m0"]) for w in inst]
+        ps = [torch.zeros_like(T(w["r"])) for w in inst]
+        rs = [T(w["r"]) for w in inst]
+        Ss = [T(w["S"]) for w in inst]
+        seq = []
+        with NF.Batch([w["n"] for w in inst], dtype=dtype) as b:
+            b.set_partitions(2)
+            b.set_graphs(graphs)
+            for rep in range(4):
+                infos = b.run([w["prm"] for w in inst], 5e-4, 3, ms, ps, rs, Ss, rtol=1e-10)
+                torch.cuda.synchronize()
+                seq.append(([x.clone() for x in ms], [x.clone() for x in ps], [_key(i) for i in infos]))
+        states.append(seq)
+    for rep in range(4):
+        g, e = states[0][rep], states[1][rep]
+        for i in range(len(inst)):
+            assert torch.equal(g[0][i], e[0][i]) and torch.equal(g[1][i], e[1][i]), (rep, i)
+        assert g[2] == e[2], rep
