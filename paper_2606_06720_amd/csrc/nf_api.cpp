@@ -202,9 +202,12 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
         if ((rc = timed_events(g, NF_KERNEL_COL_DIV, it, &e0, &e1))) return rc;
         LCHK(g, launch3_zdiv(G, f32, 0, F[0], F[1], F[2], f32 ? g->q32 : g->qh, f32 ? g->d32 : g->dh,
                              f32 ? g->r32 : g->rh, g->bh, it, s, e0, e1));
+        LCHK(g, launch3_sum_tot(G, SLOT_P3, 7, nwg3_z(G), s));
         if ((rc = timed_events(g, NF_KERNEL_COL_UPDATE, it, &e0, &e1))) return rc;
         LCHK(g, launch3_zupdate(G, f32, 0, f32 ? g->x32 : g->xh, f32 ? g->r32 : g->rh, f32 ? g->d32 : g->dh,
                                 f32 ? g->q32 : g->qh, F[0], F[1], F[2], it + 1, max_iter, tol2, s, e0, e1));
+        // the loop passes store partials; their totals are formed here, between passes
+        LCHK(g, launch3_sum_tot(G, SLOT_RR, 1, nwg3_z(G), s));
         ++it;
         continue;
       }

@@ -59,6 +59,20 @@ __device__ __forceinline__ void reduce_last(double (&v)[K], const Geo& g, int sl
   }
 }
 
+// Block sums of this workgroup stored as partials only; the PCG loop sums them
+// in a separate one-workgroup pass (k3_sum_tot).  A last-workgroup reduction
+// would need an agent-scope release fence in every workgroup, which writes
+// back the dirty lines of that XCD's L2 and cost a fifth to a third of the
+// duration of the z passes.
+template <int NT, int K>
+__device__ __forceinline__ void store_partials(double (&v)[K], const Geo& g, int slot, double* red) {
+  block_sum<NT, K>(v, red);
+  if (threadIdx.x == 0) {
+    double* part = g.part + (size_t)slot * SLOT_K * g.pstride;
+    for (int k = 0; k < K; ++k) part[(size_t)k * g.pstride + blockIdx.x] = v[k];
+  }
+}
+
 __device__ __forceinline__ double precond3_inv(const double* K, double a, double b, double c) {
   const double s = K[0] * a * a + K[3] * b * b + K[5] * c * c + 2.0 * (K[1] * a * b + K[2] * a * c + K[4] * b * c);
   return s > 0.0 ? 1.0 / s : 0.0;
@@ -656,7 +670,10 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
       }
     }
   }
-  reduce_last<C::NT, 7>(s, g, INIT ? SLOT_P3INIT : SLOT_P3, red);
+  if (INIT)
+    reduce_last<C::NT, 7>(s, g, SLOT_P3INIT, red);
+  else
+    store_partials<C::NT, 7>(s, g, SLOT_P3, red);
   if (!INIT) tclk_end(g, 1, it);
 }
 
@@ -762,7 +779,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zupdate(Geo g, int first, cx<T>* x
     }
     if (!stop && p < C::CN) put_grad3<NZ, 3, T>(buf, 0, c, kz, d, xx, yy, zz, g.inv_n);
   }
-  if (!first && !zero_x) reduce_last<C::NT, 1>(rrp, g, SLOT_RR, red);
+  if (!first && !zero_x) store_partials<C::NT, 1>(rrp, g, SLOT_RR, red);
   if (stop) {
     tclk_end(g, 2, tit);
     return;
@@ -940,6 +957,21 @@ hipError_t launch_tclk_reset(unsigned long long* t, hipStream_t s) {
 
 __global__ void k3_copy_tot(Geo g, int slot, int K, int o) {
   if (threadIdx.x < K) g.st->out[o + threadIdx.x] = g.tot[slot * SLOT_K + threadIdx.x];
+}
+
+// totals of the n partials of each of the K arrays of a slot, in a fixed order
+__global__ void __launch_bounds__(256) k3_sum_tot(Geo g, int slot, int K, int n) {
+  __shared__ double red[8 * 4];
+  const double* part = g.part + (size_t)slot * SLOT_K * g.pstride;
+  double s[SLOT_K];
+#pragma unroll
+  for (int k = 0; k < SLOT_K; ++k) {
+    s[k] = 0.0;
+    if (k < K)
+      for (int i = threadIdx.x; i < n; i += 256) s[k] += part[(size_t)k * g.pstride + i];
+  }
+  block_sum<256, SLOT_K>(s, red);
+  if (threadIdx.x < K) g.tot[slot * SLOT_K + threadIdx.x] = s[threadIdx.x];
 }
 
 // ================================================================ launchers
@@ -1163,6 +1195,11 @@ hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G
 }
 hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s) {
   hipLaunchKernelGGL(k3_copy_tot, dim3(1), dim3(64), 0, s, g, slot, K, o);
+  return hipGetLastError();
+}
+hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s) {
+  if (K < 1 || K > SLOT_K || n < 1 || n > g.pstride) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k3_sum_tot, dim3(1), dim3(256), 0, s, g, slot, K, n);
   return hipGetLastError();
 }
 
