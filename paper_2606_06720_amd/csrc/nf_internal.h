@@ -217,7 +217,8 @@ hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G
                                hipStream_t s);
 // reduced totals of a slot into st->out[o..o+K)
 hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s);
-// g.tot of a slot from the n partials the passes of the PCG loop store (one workgroup)
+// g.tot of a slot from the n partials the passes of the PCG loop store (one
+// workgroup; K = 1 or 7 arrays)
 hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s);
 hipError_t launch_zero_spec(const Geo& g, void* xh, hipStream_t s);
 // row passes (physical <-> mixed)

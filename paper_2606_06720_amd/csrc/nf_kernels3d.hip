@@ -960,17 +960,21 @@ __global__ void k3_copy_tot(Geo g, int slot, int K, int o) {
 }
 
 // totals of the n partials of each of the K arrays of a slot, in a fixed order
-__global__ void __launch_bounds__(256) k3_sum_tot(Geo g, int slot, int K, int n) {
-  __shared__ double red[8 * 4];
+template <int K>
+__global__ void __launch_bounds__(256) k3_sum_tot(Geo g, int slot, int n) {
+  __shared__ double red[K * 4];
   const double* part = g.part + (size_t)slot * SLOT_K * g.pstride;
-  double s[SLOT_K];
+  double s[K];
 #pragma unroll
-  for (int k = 0; k < SLOT_K; ++k) {
-    s[k] = 0.0;
-    if (k < K)
-      for (int i = threadIdx.x; i < n; i += 256) s[k] += part[(size_t)k * g.pstride + i];
+  for (int k = 0; k < K; ++k) s[k] = 0.0;
+  // the loads of all arrays and of several indices are independent: keep many
+  // in flight (the sum is latency-bound)
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n; i += 256) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] += part[(size_t)k * g.pstride + i];
   }
-  block_sum<256, SLOT_K>(s, red);
+  block_sum<256, K>(s, red);
   if (threadIdx.x < K) g.tot[slot * SLOT_K + threadIdx.x] = s[threadIdx.x];
 }
 
@@ -1198,8 +1202,13 @@ hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s)
   return hipGetLastError();
 }
 hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s) {
-  if (K < 1 || K > SLOT_K || n < 1 || n > g.pstride) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k3_sum_tot, dim3(1), dim3(256), 0, s, g, slot, K, n);
+  if (n < 1 || n > g.pstride) return hipErrorInvalidValue;
+  if (K == 1)
+    hipLaunchKernelGGL(k3_sum_tot<1>, dim3(1), dim3(256), 0, s, g, slot, n);
+  else if (K == 7)
+    hipLaunchKernelGGL(k3_sum_tot<7>, dim3(1), dim3(256), 0, s, g, slot, n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
