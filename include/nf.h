@@ -267,7 +267,8 @@ int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double
  *   nf_batch_run: every count from 1 to min(4, count) runs two steps on
  *   scratch copies of m and p (device memory for 3 doubles per grid point,
  *   freed before the run; the caller's fields are not written) and the fastest
- *   is kept for the following runs.  parts in [1, min(4, count)] fixes it.
+ *   is kept for the following runs (one partition if that memory is not
+ *   available).  parts in [1, min(4, count)] fixes it.
  *   NF_EINVAL otherwise.
  * nf_batch_set_graphs: on records each chunk of PCG iterations a partition
  *   launches (the three passes of every iteration for every grid shape) as a

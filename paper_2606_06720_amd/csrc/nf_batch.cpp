@@ -689,8 +689,10 @@ int parts_tune(nf_batch* b, const nf_params* prm, double dt, double* const* m, d
   double* scratch = nullptr;
   hipError_t e = hipMalloc((void**)&scratch, sizeof(double) * off[c]);
   if (e != hipSuccess) {
-    b->err = std::string("hipMalloc(tuning scratch): ") + hipGetErrorString(e);
-    return NF_ENOMEM;
+    // no room to tune: one partition, the untuned default
+    (void)hipGetLastError();
+    b->tune_ms.assign(c < MAX_PARTS ? c : MAX_PARTS, -1.0);
+    return parts_build(b, 1);
   }
   std::vector<double*> ms(c), ps(c);
   for (int i = 0; i < c; ++i) {
@@ -818,14 +820,17 @@ int nf_batch_run(nf_batch* b, const nf_params* prm, double dt, int64_t steps, do
   if (!b) return NF_EINVAL;
   b->err.clear();
   const int c = b->count;
-  if (!prm || !m || !p || !r || !S) return (b->err = "NULL argument array", NF_EINVAL);
-  if (!(dt > 0.0)) return (b->err = "dt must be > 0", NF_EINVAL);
-  if (!(rtol >= 0.0) || max_iter < 0 || steps < 1)
-    return (b->err = "rtol >= 0, max_iter >= 0 and steps >= 1 required", NF_EINVAL);
+  auto invalid = [&](const std::string& msg) {
+    b->err = msg;
+    return NF_EINVAL;
+  };
+  if (!prm || !m || !p || !r || !S) return invalid("NULL argument array");
+  if (!(dt > 0.0)) return invalid("dt must be > 0");
+  if (!(rtol >= 0.0) || max_iter < 0 || steps < 1) return invalid("rtol >= 0, max_iter >= 0 and steps >= 1 required");
   for (int i = 0; i < c; ++i) {
-    if (!m[i] || !p[i] || !r[i] || !S[i]) return (b->err = "NULL field pointer of instance " + std::to_string(i), NF_EINVAL);
+    if (!m[i] || !p[i] || !r[i] || !S[i]) return invalid("NULL field pointer of instance " + std::to_string(i));
     if (!(prm[i].gamma > 0.0) || !(prm[i].c2 >= 0.0) || !(prm[i].D2 >= 0.0))
-      return (b->err = "invalid params of instance " + std::to_string(i), NF_EINVAL);
+      return invalid("invalid params of instance " + std::to_string(i));
   }
   if (b->nparts == 0) {
     const int rc = parts_tune(b, prm, dt, m, p, r, S, rtol, max_iter);

@@ -133,7 +133,7 @@ def test_batch_partition_count_does_not_change_results(env, dtype_name):
         ms, ps, infos = _run_batch(env, inst, dtype, 4, 5e-4, 1e-10, parts=parts, out=got)
         k, tune_ms = got["parts"]
         print("parts", parts, "in use", k, "tuning ms", tune_ms)
-        assert k == (parts if parts else k) and 1 <= k <= 4
+        assert k == parts if parts else 1 <= k <= 4
         if parts == 0:
             # the tuner timed every count up to min(4, count) and kept the fastest
             assert all(t > 0 for t in tune_ms) and tune_ms[k - 1] == min(tune_ms)
