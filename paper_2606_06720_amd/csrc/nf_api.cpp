@@ -187,7 +187,10 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
   int slot = 0, pending = -1;
   bool first_chunk = true;
   while (it < max_iter) {
-    int nk = first_chunk ? (expect > 6 ? expect - 4 : 2) : 3;
+    // up to one iteration short of the last solve's count, then one iteration per
+    // chunk: the host polls one chunk behind, so at most about one chunk of
+    // launches is queued past the stop (they return at once)
+    int nk = first_chunk ? (expect > 3 ? expect - 1 : 2) : 1;
     first_chunk = false;
     if (nk > max_iter - it) nk = max_iter - it;
     for (int k = 0; k < nk; ++k) {

@@ -268,7 +268,10 @@ int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
   int it = 0, slot = 0, pending = -1;
   bool first_chunk = true;
   while (it < max_iter) {
-    int nk = first_chunk ? (expect > 6 ? expect - 4 : 2) : 3;
+    // up to one iteration short of the last solve's count, then one iteration per
+    // chunk: the host polls one chunk behind, so at most about one chunk of
+    // launches is queued past the stop (they return at once)
+    int nk = first_chunk ? (expect > 3 ? expect - 1 : 2) : 1;
     first_chunk = false;
     if (nk > max_iter - it) nk = max_iter - it;
     const int rc = run_chunk(b, f32, it, nk, max_iter, tol2);
