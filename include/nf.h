@@ -11,14 +11,21 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Grid: n[0] = Nx, n[1] = Ny (2D), powers of two in [8, 4096]; nodes
- *   x_i = i Lx / Nx, i < Nx (Sec. 2.2, node Nx identified with node 0).
+ * - Grid: n[0] = Nx, n[1] = Ny (2D), n[2] = Nz (3D), with the sizes listed
+ *   under nf_create_grid; nodes x_i = i Lx / Nx, i < Nx (Sec. 2.2, node Nx
+ *   identified with node 0).
  * - Fields are caller-owned DEVICE buffers of double, C-contiguous, x fastest:
  *   scalars (p, r, S) are [Ny][Nx]; the conductivity m is [2][Ny][Nx] with
  *   component 0 = m_x.  The library never frees, reallocates or retains them.
- * - The handle owns all workspace (allocated once by nf_create_grid); no entry
- *   point allocates device memory.
- * - All work is enqueued on the handle's HIP stream.  Entry points that run a
+ * - The handle owns all workspace (allocated once by nf_create_grid); the
+ *   solver entry points allocate no device memory.  Exceptions, outside the
+ *   solver: nf_time_kernel allocates its stamp buffer, and an ensemble
+ *   allocates the state of its partitions when they are set or tuned
+ *   (nf_batch_set_partitions, the first nf_batch_run), the tuning also a
+ *   scratch copy of m and p that it frees before the run.
+ * - All work is enqueued on the handle's HIP stream (an ensemble's partitions
+ *   run on streams of their own, forked from and joined to the batch's
+ *   stream).  Entry points that run a
  *   PCG solve synchronise with that stream to test convergence; they return
  *   after the last kernel of the call has been queued and every host-visible
  *   result has been read back.
@@ -239,7 +246,7 @@ int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double
  * solve has stopped does no work in the later iterations of that solve.
  *
  * nf_batch_create: count >= 1 instances; n [count][2] grid sizes (Nx, Ny),
- *   powers of two in [8, 4096]; L [count][2] box lengths (> 0); dtype
+ *   2D sizes as for nf_create_grid; L [count][2] box lengths (> 0); dtype
  *   NF_F64 or NF_F32_REFINED for every instance; stream as for
  *   nf_create_grid.  Each instance owns the workspace of one nf_grid.
  *   Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure (*out is then NULL;
