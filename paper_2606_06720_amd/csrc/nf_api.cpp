@@ -18,7 +18,7 @@ using namespace nf;
 
 namespace {
 
-const char* kVersion = "nf-mi355x 0.2 (gfx950, 2D, fp64 and fp32-refined pressure solve)";
+const char* kVersion = "nf-mi355x 0.3 (gfx950; 2D and 3D; FP64 and FP32-refined solves; adjoint step; ensembles)";
 
 // message of the last nf_create_grid failure on this thread (nf_last_error(NULL))
 thread_local std::string create_err;
