@@ -341,8 +341,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); a multi-GPU layout is "
-              "described in the design notes but not implemented" % args.gpus, file=sys.stderr)
+        print("bench.py: one GPU only (--gpus %d requested); sharding a grid or an ensemble across GPUs "
+              "is not implemented" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

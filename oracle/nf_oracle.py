@@ -22,8 +22,7 @@ Conventions
 * forward DFT ``e^{-i ...}`` unnormalised, inverse with ``1/n`` (numpy's
   convention).  Every operator below is independent of that choice.
 
-Readings of points the paper leaves open (each is listed with its reason in the
-design notes of the repository):
+Readings of points the paper leaves open:
 * first-derivative multipliers use the discrete Fourier variable with the
   Nyquist entry set to zero (``xi_tilde``); the heat kernel keeps it;
 * the discrete pressure is the minimum-norm solution: the 2^d Fourier modes whose
