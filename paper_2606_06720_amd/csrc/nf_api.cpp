@@ -205,12 +205,9 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
         if ((rc = timed_events(g, NF_KERNEL_COL_DIV, it, &e0, &e1))) return rc;
         LCHK(g, launch3_zdiv(G, f32, 0, F[0], F[1], F[2], f32 ? g->q32 : g->qh, f32 ? g->d32 : g->dh,
                              f32 ? g->r32 : g->rh, g->bh, it, s, e0, e1));
-        LCHK(g, launch3_sum_tot(G, SLOT_P3, 7, nwg3_z(G), s));
         if ((rc = timed_events(g, NF_KERNEL_COL_UPDATE, it, &e0, &e1))) return rc;
         LCHK(g, launch3_zupdate(G, f32, 0, f32 ? g->x32 : g->xh, f32 ? g->r32 : g->rh, f32 ? g->d32 : g->dh,
                                 f32 ? g->q32 : g->qh, F[0], F[1], F[2], it + 1, max_iter, tol2, s, e0, e1));
-        // the loop passes store partials; their totals are formed here, between passes
-        LCHK(g, launch3_sum_tot(G, SLOT_RR, 1, nwg3_z(G), s));
         ++it;
         continue;
       }
@@ -555,8 +552,8 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   for (void** b : bufs) CREATE_CHK(hipMalloc(b, spec_bytes), NF_ENOMEM);
   for (int i = 0; i < nmix; ++i) CREATE_CHK(hipMalloc(&g->mix[i], spec_bytes), NF_ENOMEM);
   CREATE_CHK(hipMalloc(&g->tw, (size_t)twn * 2 * sizeof(double)), NF_ENOMEM);
-  // partial sums: 2D keeps MAX_WG per array; 3D sizes them to the largest pass
-  // and appends the reduced totals and the arrival counters
+  // partial sums: 2D keeps MAX_WG per array; 3D sizes them to the largest pass.
+  // The reduced totals follow them.
   int pstride = MAX_WG;
   if (ndim == 3) {
     Geo tmp{};
@@ -568,7 +565,7 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
     if (nwg3_y(tmp) > pstride) pstride = nwg3_y(tmp);
     if (nwg3_z(tmp) > pstride) pstride = nwg3_z(tmp);
   }
-  const size_t part_doubles = (size_t)NSLOTS * SLOT_K * pstride + NSLOTS * SLOT_K + NSLOTS;
+  const size_t part_doubles = (size_t)NSLOTS * SLOT_K * pstride + NSLOTS * SLOT_K;
   CREATE_CHK(hipMalloc((void**)&g->part, part_doubles * sizeof(double)), NF_ENOMEM);
   CREATE_CHK(hipMalloc((void**)&g->st, sizeof(DevStatus)), NF_ENOMEM);
   g->st_own = g->st;
@@ -613,7 +610,6 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.lz = g->lz;
   G.pstride = pstride;
   G.tot = g->part + (size_t)NSLOTS * SLOT_K * pstride;
-  G.cnt = (unsigned*)(G.tot + NSLOTS * SLOT_K);
   G.tclk = nullptr;
   G.tkind = -1;
   g->geo32 = G;

@@ -60,8 +60,7 @@ struct Geo {
   int nz;
   double lz;
   int pstride;        // stride of the partial-sum arrays of one slot
-  double* tot;        // NSLOTS * SLOT_K reduced totals (last-workgroup reduction)
-  unsigned* cnt;      // NSLOTS arrival counters of that reduction (zero between launches)
+  double* tot;        // NSLOTS * SLOT_K totals of the 3D partials (formed by a one-workgroup pass)
   // optional execution-span timing of one PCG-loop pass (nullptr = off): for
   // iteration it, the workgroups of kind tkind fold their start and end stamps
   // (device wall clock) into TCLK_W (min, max) pairs at

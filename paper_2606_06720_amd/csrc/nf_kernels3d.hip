@@ -29,41 +29,12 @@
 namespace nf {
 
 // ---------------------------------------------------------------- reductions
-// v holds this thread's K partial values; on return the totals of the whole
-// grid are in g.tot[slot * SLOT_K + k] once the kernel has finished.
-template <int NT, int K>
-__device__ __forceinline__ void reduce_last(double (&v)[K], const Geo& g, int slot, double* red) {
-  __shared__ int last;
-  block_sum<NT, K>(v, red);
-  double* part = g.part + (size_t)slot * SLOT_K * g.pstride;
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < K; ++k) part[(size_t)k * g.pstride + blockIdx.x] = v[k];
-    __threadfence();
-    const unsigned t = atomicAdd(&g.cnt[slot], 1u);
-    last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    double s[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      s[k] = 0.0;
-      for (int i = threadIdx.x; i < (int)gridDim.x; i += NT) s[k] += part[(size_t)k * g.pstride + i];
-    }
-    block_sum<NT, K>(s, red);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < K; ++k) g.tot[slot * SLOT_K + k] = s[k];
-      g.cnt[slot] = 0;
-    }
-  }
-}
-
-// Block sums of this workgroup stored as partials only; the PCG loop sums them
-// in a separate one-workgroup pass (k3_sum_tot).  A last-workgroup reduction
-// would need an agent-scope release fence in every workgroup, which writes
-// back the dirty lines of that XCD's L2 and cost a fifth to a third of the
-// duration of the z passes.
+// Block sums of this workgroup stored as partials only; a one-workgroup pass
+// (k3_sum_tot) launched right after the producing pass adds them in a fixed
+// order into g.tot.  (A pass can have more workgroups than a consumer could
+// re-read in every workgroup.)  A last-workgroup reduction would need an
+// agent-scope release fence in every workgroup, which writes back the dirty
+// lines of that XCD's L2 and cost a fifth to a third of the z passes.
 template <int NT, int K>
 __device__ __forceinline__ void store_partials(double (&v)[K], const Geo& g, int slot, double* red) {
   block_sum<NT, K>(v, red);
@@ -204,7 +175,7 @@ __global__ void __launch_bounds__(TPF) k3_row_r2c(Geo g, const double* __restric
   lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, rows, y0, nrow);
-  if (schk) reduce_last<C::NT, 2>(s, g, SLOT_SCHK, red);
+  if (schk) store_partials<C::NT, 2>(s, g, SLOT_SCHK, red);
 }
 
 template <int NX>
@@ -307,7 +278,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<NX, 3, 3>(buf, G0, G1, G2, rows, y0, nrow);
-  if (kbar) reduce_last<C::NT, 7>(ks, g, SLOT_KBAR, red);
+  if (kbar) store_partials<C::NT, 7>(ks, g, SLOT_KBAR, red);
   tclk_end(g, 0, it);
 }
 
@@ -454,7 +425,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_final(Geo g, const cd* __restr
       *(double2*)(m + 2 * n + idx) = make_double2(a2.x, a2.y);
     }
   }
-  reduce_last<C::NT, 2>(s, g, SLOT_DM, red);
+  store_partials<C::NT, 2>(s, g, SLOT_DM, red);
 }
 
 // ================================================================ y passes
@@ -670,10 +641,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
       }
     }
   }
-  if (INIT)
-    reduce_last<C::NT, 7>(s, g, SLOT_P3INIT, red);
-  else
-    store_partials<C::NT, 7>(s, g, SLOT_P3, red);
+  store_partials<C::NT, 7>(s, g, INIT ? SLOT_P3INIT : SLOT_P3, red);
   if (!INIT) tclk_end(g, 1, it);
 }
 
@@ -1021,6 +989,10 @@ hipError_t launch3_row_r2c(const Geo& g, const double* f, void* out, int schk, h
 #define L_(N) hipLaunchKernelGGL(k3_row_r2c<N>, grid, blk, 0, s, g, f, (cd*)out, schk)
   NF3_DISPATCH(g.nx, L_)
 #undef L_
+  if (schk) {
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch3_sum_tot(g, SLOT_SCHK, 2, nwg3_row(g), s);
+  }
   return hipGetLastError();
 }
 hipError_t launch3_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s) {
@@ -1047,6 +1019,10 @@ hipError_t launch3_row_flux(const Geo& g, bool f32, void* G0, void* G1, void* G2
     NF3_DISPATCH(g.nx, L_)
 #undef L_
   }
+  if (kbar) {
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch3_sum_tot(g, SLOT_KBAR, 7, nwg3_row(g), s);
+  }
   return hipGetLastError();
 }
 hipError_t launch3_row_split(const Geo& g, void* P, void* G0, void* G1, void* G2, const double* m, double* p_out,
@@ -1064,7 +1040,8 @@ hipError_t launch3_row_final(const Geo& g, const void* M0, const void* M1, const
 #define L_(N) hipLaunchKernelGGL(k3_row_final<N>, grid, blk, 0, s, g, (const cd*)M0, (const cd*)M1, (const cd*)M2, m)
   NF3_DISPATCH(g.nx, L_)
 #undef L_
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch3_sum_tot(g, SLOT_DM, 2, nwg3_row(g), s);
 }
 
 template <int NF, int DIR, typename T>
@@ -1147,7 +1124,8 @@ hipError_t launch3_zdiv(const Geo& g, bool f32, int init, const void* F0, const 
     NF3_DISPATCH(g.nz, L_)
 #undef L_
   }
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch3_sum_tot(g, init ? SLOT_P3INIT : SLOT_P3, 7, nwg3_z(g), s);
 }
 hipError_t launch3_zupdate(const Geo& g, bool f32, int first, void* xh, void* rh, void* dh, const void* qh, void* G0,
                            void* G1, void* G2, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0,
@@ -1167,7 +1145,9 @@ hipError_t launch3_zupdate(const Geo& g, bool f32, int first, void* xh, void* rh
     NF3_DISPATCH(g.nz, L_)
 #undef L_
   }
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  // the first update writes no residual norm
+  return e != hipSuccess || first ? e : launch3_sum_tot(g, SLOT_RR, 1, nwg3_z(g), s);
 }
 hipError_t launch3_zheat(const Geo& g, void* M0, void* M1, void* M2, double D2dt, hipStream_t s) {
   const dim3 grid(nwg3_z(g)), blk(3 * TPF);
@@ -1203,12 +1183,12 @@ hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s)
 }
 hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s) {
   if (n < 1 || n > g.pstride) return hipErrorInvalidValue;
-  if (K == 1)
-    hipLaunchKernelGGL(k3_sum_tot<1>, dim3(1), dim3(256), 0, s, g, slot, n);
-  else if (K == 7)
-    hipLaunchKernelGGL(k3_sum_tot<7>, dim3(1), dim3(256), 0, s, g, slot, n);
-  else
-    return hipErrorInvalidValue;
+  switch (K) {
+    case 1: hipLaunchKernelGGL(k3_sum_tot<1>, dim3(1), dim3(256), 0, s, g, slot, n); break;
+    case 2: hipLaunchKernelGGL(k3_sum_tot<2>, dim3(1), dim3(256), 0, s, g, slot, n); break;
+    case 7: hipLaunchKernelGGL(k3_sum_tot<7>, dim3(1), dim3(256), 0, s, g, slot, n); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
