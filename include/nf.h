@@ -130,9 +130,10 @@ int nf_set_stream(nf_grid *g, void *stream);
 
 /*
  * NF_F32_REFINED handles: smallest relative residual reduction asked of one
- * FP32 correction (default 1e-5; each correction asks for the reduction that
- * reaches rtol with a margin of 2, but not below this floor).  Must lie in
- * (0, 0.5); NF_EINVAL otherwise.  No effect on NF_F64 handles.
+ * FP32 correction (default 3e-6 in 2D, 1e-5 in 3D; each correction asks for
+ * the reduction that reaches rtol with a margin of 2, but not below this
+ * floor).  Must lie in (0, 0.5); NF_EINVAL otherwise.  No effect on NF_F64
+ * handles.
  */
 int nf_set_inner_tolerance(nf_grid *g, double floor_rtol);
 

@@ -517,6 +517,9 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
     if (!(L[c] > 0.0)) return NF_EINVAL;
   nf_grid* g = new nf_grid();
   g->dim = ndim;
+  // default floor of the FP32 corrections, measured per dimension: 3e-6 saves
+  // a correction per solve on 2D grids; on 256^3 1e-5 was 3% faster
+  g->inner_floor = ndim == 3 ? 1e-5 : 3e-6;
   g->nx = (int)n[0];
   g->ny = (int)n[1];
   g->nz = ndim == 3 ? (int)n[2] : 1;
