@@ -82,14 +82,14 @@ __global__ void __launch_bounds__(256) kb_sum_slot(const SumArgs* __restrict__ A
 template <int NX>
 __device__ __forceinline__ void row_r2c_body(Geo g, const double* __restrict__ f, cd* __restrict__ out,
                                                  double* schk) {
-  using C = RowCfg<NX, 1>;
+  using C = Row2D<NX, 1>;
   __shared__ cd buf[C::NB * C::LS];
   __shared__ double red[2 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   double2 v[C::EP];
-  rowP_gload<NX, 1>(v, f, y0, nrow);
+  rowP_gload<C>(v, f, y0, nrow);
   double s[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -103,34 +103,34 @@ __device__ __forceinline__ void row_r2c_body(Geo g, const double* __restrict__ f
   __syncthreads();
   lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, g.ny, y0, nrow);
+  rowT_store<C, 1>(buf, out, nullptr, nullptr, g.ny, y0, nrow);
   if (schk) {
     block_sum<C::NT, 2>(s, red);
     write_partials<C::NT>(schk, s, 2);
   }
 }
 template <int NX>
-__global__ void __launch_bounds__(TPF) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
+__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_r2c(Geo g, const double* __restrict__ f, cd* __restrict__ out,
                                                  double* schk) {
   row_r2c_body<NX>(g, f, out, schk);
 }
 template <int NX>
-__global__ void __launch_bounds__(TPF) kb_row_r2c(const RowR2cArgs* __restrict__ A) {
+__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) kb_row_r2c(const RowR2cArgs* __restrict__ A) {
   const RowR2cArgs& a = A[blockIdx.y];
   row_r2c_body<NX>(a.g, (const double*)a.f, (cd*)a.out, (double*)a.schk);
 }
 
 // mixed -> physical (unnormalised inverse: the caller folds 1/n into the spectral side)
 template <int NX>
-__global__ void __launch_bounds__(TPF) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
-  using C = RowCfg<NX, 1>;
+__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
+  using C = Row2D<NX, 1>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   cd tv[C::ET];
-  rowT_gload<NX, 1>(tv, in, nullptr, nullptr, g.ny, y0, nrow);
-  rowT_put<NX, 1>(buf, tv);
+  rowT_gload<C>(tv, in, nullptr, nullptr, g.ny, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -157,7 +157,7 @@ template <int NX, typename T>
 __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
                                                   const T* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2, float* lo) {
-  using C = RowCfg<NX, 2>;
+  using C = Row2D<NX, 2>;
   using V = cx<T>;
   using P = typename vec2<T>::type;
   if (it >= 0 ? g.st->conv_at <= it : g.st->outer_done != 0) return;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
   V tv[C::ET];
-  rowT_gload<NX, 2>(tv, G0, G1, nullptr, g.ny, y0, nrow);
+  rowT_gload<C>(tv, G0, G1, nullptr, g.ny, y0, nrow);
   if (it >= 1) {
     double rr[1];
     sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
@@ -185,7 +185,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
       return;
     }
   }
-  rowT_put<NX, 2>(buf, tv);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -193,9 +193,9 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   // about 48 registers, and a workgroup with fewer registers shares a compute
   // unit more easily with the passes of concurrent solves
   P mx[C::EP], my[C::EP], rv[C::EP];
-  rowP_gload<NX, 2>(mx, m, y0, nrow);
-  rowP_gload<NX, 2>(my, m + n, y0, nrow);
-  rowP_gload<NX, 2>(rv, r, y0, nrow);
+  rowP_gload<C>(mx, m, y0, nrow);
+  rowP_gload<C>(my, m + n, y0, nrow);
+  rowP_gload<C>(rv, r, y0, nrow);
   if (lo) {
 #pragma unroll
     for (int i = 0; i < C::EP; ++i) {
@@ -234,7 +234,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   __syncthreads();
   lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 2, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
+  rowT_store<C, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
     write_partials<C::NT>(kslot, ks, 4);
@@ -242,13 +242,13 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   tclk_end(g, 0, it);
 }
 template <int NX, typename T>
-__global__ void __launch_bounds__(2 * TPF) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
+__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
                                                   const T* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2, float* lo) {
   row_flux_body<NX, T>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo);
 }
 template <int NX, typename T>
-__global__ void __launch_bounds__(2 * TPF) kb_row_flux(const FluxArgs* __restrict__ A, int it, int nwg_col, double tol2) {
+__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) kb_row_flux(const FluxArgs* __restrict__ A, int it, int nwg_col, double tol2) {
   const FluxArgs& a = A[blockIdx.y];
   row_flux_body<NX, T>(a.g, (cx<T>*)a.G0, (cx<T>*)a.G1, (const T*)a.m, (const T*)a.r, it, (double*)a.kslot, nwg_col, tol2, (float*)a.lo);
 }
@@ -260,18 +260,18 @@ template <int NX>
 __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
-  using C = RowCfg<NX, 3>;
+  using C = Row2D<NX, 3>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
   cd tv[C::ET];
-  rowT_gload<NX, 3>(tv, P, Gx, Gy, g.ny, y0, nrow);
+  rowT_gload<C>(tv, P, Gx, Gy, g.ny, y0, nrow);
   double2 mxv[C::EP], myv[C::EP];
-  rowP_gload<NX, 3>(mxv, m, y0, nrow);
-  rowP_gload<NX, 3>(myv, m + n, y0, nrow);
-  rowT_put<NX, 3>(buf, tv);
+  rowP_gload<C>(mxv, m, y0, nrow);
+  rowP_gload<C>(myv, m + n, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -326,16 +326,16 @@ __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* _
   __syncthreads();
   lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 3, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
+  rowT_store<C, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
 }
 template <int NX>
-__global__ void __launch_bounds__(3 * TPF) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
+__global__ void __launch_bounds__((Row2D<NX, 3>::NT)) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
   row_split_body<NX>(g, P, Gx, Gy, m, p_out, c2dt, gamma, dt, relax1);
 }
 template <int NX>
-__global__ void __launch_bounds__(3 * TPF) kb_row_split(const SplitArgs* __restrict__ A) {
+__global__ void __launch_bounds__((Row2D<NX, 3>::NT)) kb_row_split(const SplitArgs* __restrict__ A) {
   const SplitArgs& a = A[blockIdx.y];
   row_split_body<NX>(a.g, (cd*)a.P, (cd*)a.Gx, (const cd*)a.Gy, (const double*)a.m, (double*)a.p_out, a.c2dt, a.gamma, a.dt, a.relax1);
 }
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(3 * TPF) kb_row_split(const SplitArgs* __restr
 template <int NX>
 __device__ __forceinline__ void row_final_body(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                    double* m, double* dslot) {
-  using C = RowCfg<NX, 2>;
+  using C = Row2D<NX, 2>;
   __shared__ cd buf[C::NB * C::LS];
   __shared__ double red[2 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
@@ -353,11 +353,11 @@ __device__ __forceinline__ void row_final_body(Geo g, const cd* __restrict__ Mx,
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
   cd tv[C::ET];
-  rowT_gload<NX, 2>(tv, Mx, My, nullptr, g.ny, y0, nrow);
+  rowT_gload<C>(tv, Mx, My, nullptr, g.ny, y0, nrow);
   double2 o0[C::EP], o1[C::EP];
-  rowP_gload<NX, 2>(o0, m, y0, nrow);
-  rowP_gload<NX, 2>(o1, m + n, y0, nrow);
-  rowT_put<NX, 2>(buf, tv);
+  rowP_gload<C>(o0, m, y0, nrow);
+  rowP_gload<C>(o1, m + n, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -383,22 +383,22 @@ __device__ __forceinline__ void row_final_body(Geo g, const cd* __restrict__ Mx,
   }
 }
 template <int NX>
-__global__ void __launch_bounds__(2 * TPF) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) k_row_final(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                    double* m, double* dslot) {
   row_final_body<NX>(g, Mx, My, m, dslot);
 }
 template <int NX>
-__global__ void __launch_bounds__(2 * TPF) kb_row_final(const FinalArgs* __restrict__ A) {
+__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) kb_row_final(const FinalArgs* __restrict__ A) {
   const FinalArgs& a = A[blockIdx.y];
   row_final_body<NX>(a.g, (const cd*)a.Mx, (const cd*)a.My, (double*)a.m, (double*)a.dslot);
 }
 
 // Pointwise energy terms: sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
 template <int NX>
-__global__ void __launch_bounds__(2 * TPF) k_row_energy(Geo g, const cd* __restrict__ Gx, const cd* __restrict__ Gy,
+__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) k_row_energy(Geo g, const cd* __restrict__ Gx, const cd* __restrict__ Gy,
                                                     const double* __restrict__ m, const double* __restrict__ r,
                                                     double gamma, double* eslot) {
-  using C = RowCfg<NX, 2>;
+  using C = Row2D<NX, 2>;
   __shared__ cd buf[C::NB * C::LS];
   __shared__ double red[3 * (C::NT / 64)];
   const cd* tw = (const cd*)g.tw;
@@ -406,12 +406,12 @@ __global__ void __launch_bounds__(2 * TPF) k_row_energy(Geo g, const cd* __restr
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
   cd tv[C::ET];
-  rowT_gload<NX, 2>(tv, Gx, Gy, nullptr, g.ny, y0, nrow);
+  rowT_gload<C>(tv, Gx, Gy, nullptr, g.ny, y0, nrow);
   double2 mx[C::EP], my[C::EP], rv[C::EP];
-  rowP_gload<NX, 2>(mx, m, y0, nrow);
-  rowP_gload<NX, 2>(my, m + n, y0, nrow);
-  rowP_gload<NX, 2>(rv, r, y0, nrow);
-  rowT_put<NX, 2>(buf, tv);
+  rowP_gload<C>(mx, m, y0, nrow);
+  rowP_gload<C>(my, m + n, y0, nrow);
+  rowP_gload<C>(rv, r, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -498,11 +498,11 @@ __device__ __forceinline__ void adjoint_point(double mx, double my, double gx, d
 // pointwise reverse of relaxation and activation; lam_m written to lam_out,
 // lam_g transformed forward back into A0 / A1 (in place).
 template <int NX>
-__global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, const cd* __restrict__ G0,
+__global__ void __launch_bounds__((Row2D<NX, 4>::NT)) k_row_adj1(Geo g, cd* A0, cd* A1, const cd* __restrict__ G0,
                                                       const cd* __restrict__ G1, const double* __restrict__ m,
                                                       double* __restrict__ lam_out, double c2dt, double gamma,
                                                       double dt, double relax1) {
-  using C = RowCfg<NX, 4>;
+  using C = Row2D<NX, 4>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
@@ -518,9 +518,9 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, con
     tv[i] = (e < 4 * C::RH && rr < nrow) ? src[(size_t)kx * g.ny + y0 + rr] : mk<double>(0.0, 0.0);
   }
   double2 mx[C::EP], my[C::EP];
-  rowP_gload<NX, 4>(mx, m, y0, nrow);
-  rowP_gload<NX, 4>(my, m + n, y0, nrow);
-  rowT_put<NX, 4>(buf, tv);
+  rowP_gload<C>(mx, m, y0, nrow);
+  rowP_gload<C>(my, m + n, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -548,18 +548,18 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj1(Geo g, cd* A0, cd* A1, con
   __syncthreads();
   lds_fft<double, -1, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 4, 2>(buf, A0, A1, nullptr, g.ny, y0, nrow);
+  rowT_store<C, 2>(buf, A0, A1, nullptr, g.ny, y0, nrow);
 }
 
 // Adjoint, second pass: c2r of (grad mu, grad p); with mu (physical) and m:
 // dL/dS += mu, dL/dr -= grad mu . grad p, and
 // lam -= (m.grad p) grad mu + (m.grad mu) grad p.
 template <int NX>
-__global__ void __launch_bounds__(4 * TPF) k_row_adj2(Geo g, const cd* __restrict__ M1, const cd* __restrict__ M2,
+__global__ void __launch_bounds__((Row2D<NX, 4>::NT)) k_row_adj2(Geo g, const cd* __restrict__ M1, const cd* __restrict__ M2,
                                                       const cd* __restrict__ P1, const cd* __restrict__ P2,
                                                       const double* __restrict__ m, const double* __restrict__ mu,
                                                       double* lam, double* grad_r, double* grad_S) {
-  using C = RowCfg<NX, 4>;
+  using C = Row2D<NX, 4>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
@@ -575,10 +575,10 @@ __global__ void __launch_bounds__(4 * TPF) k_row_adj2(Geo g, const cd* __restric
     tv[i] = (e < 4 * C::RH && rr < nrow) ? src[(size_t)kx * g.ny + y0 + rr] : mk<double>(0.0, 0.0);
   }
   double2 mx[C::EP], my[C::EP], muv[C::EP];
-  rowP_gload<NX, 4>(mx, m, y0, nrow);
-  rowP_gload<NX, 4>(my, m + n, y0, nrow);
-  rowP_gload<NX, 4>(muv, mu, y0, nrow);
-  rowT_put<NX, 4>(buf, tv);
+  rowP_gload<C>(mx, m, y0, nrow);
+  rowP_gload<C>(my, m + n, y0, nrow);
+  rowP_gload<C>(muv, mu, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -1279,19 +1279,17 @@ __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __res
     else hipLaunchKernelGGL(K, GRID, BLK, 0, S, __VA_ARGS__);                      \
   } while (0)
 
-static int row_rows(int nx) {
-  const int h = nx / 2;
-  int r = TILE / h;
-  return r < 1 ? 1 : (r > 64 ? 64 : r);
+static int row_threads(int nx, int nf) { return row_tile(nx, nf) / 8 * nf; }
+static int row_nwg(const Geo& g, int nf) {
+  const int R = tile_rows(g.nx / 2, row_tile(g.nx, nf));
+  return (g.ny + R - 1) / R;
 }
 static int col_cols(int ny) {
   int c = TILE / ny;
   return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
-int row_nwg(const Geo& g) {
-  const int R = row_rows(g.nx);
-  return (g.ny + R - 1) / R;
-}
+// workgroups of the 2D row passes over one or two fields (the writers of row partials)
+int row_nwg(const Geo& g) { return row_nwg(g, 2); }
 int col_nwg(const Geo& g) {
   const int C = col_cols(g.ny);
   return (g.h + C - 1) / C;
@@ -1312,14 +1310,14 @@ hipError_t launch_sum_slot(const Geo& g, const double* slot, int K, int n, int o
 }
 
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out, double* schk, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(TPF);
+  const dim3 grid(row_nwg(g, 1)), blk(row_threads(g.nx, 1));
 #define L_(N) hipLaunchKernelGGL(k_row_r2c<N>, grid, blk, 0, s, g, f, (cd*)out, schk)
   NF_DISPATCH(g.nx, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(TPF);
+  const dim3 grid(row_nwg(g, 1)), blk(row_threads(g.nx, 1));
 #define L_(N) hipLaunchKernelGGL(k_row_c2r<N>, grid, blk, 0, s, g, (const cd*)in, f)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -1327,7 +1325,7 @@ hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s
 }
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
                            double* kslot, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* lo) {
-  const dim3 grid(row_nwg(g)), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
   const int nwg_col = col_nwg(g);
 #define L_(N)                                                                                                    \
   NF_LAUNCH((k_row_flux<N, double>), grid, blk, s, e0, e1, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2, \
@@ -1338,7 +1336,7 @@ hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, co
 }
 hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32, const float* r32, int it,
                              double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const dim3 grid(row_nwg(g)), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
   const int nwg_col = col_nwg(g);
 #define L_(N)                                                                                                     \
   NF_LAUNCH((k_row_flux<N, float>), grid, blk, s, e0, e1, g, (cx<float>*)G0, (cx<float>*)G1, m32, r32, it,        \
@@ -1349,7 +1347,7 @@ hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32,
 }
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(3 * TPF);
+  const dim3 grid(row_nwg(g, 3)), blk(row_threads(g.nx, 3));
 #define L_(N)                                                                                            \
   hipLaunchKernelGGL(k_row_split<N>, grid, blk, 0, s, g, (cd*)P, (cd*)Gx, (const cd*)Gy, m, p_out, c2dt, \
                      gamma, dt, relax1)
@@ -1359,7 +1357,7 @@ hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const dou
 }
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dslot,
                             hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
 #define L_(N) hipLaunchKernelGGL(k_row_final<N>, grid, blk, 0, s, g, (const cd*)Mx, (const cd*)My, m, dslot)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -1367,7 +1365,7 @@ hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double
 }
 hipError_t launch_row_energy(const Geo& g, const void* Gx, const void* Gy, const double* m, const double* r,
                              double gamma, double* slot, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
 #define L_(N) \
   hipLaunchKernelGGL(k_row_energy<N>, grid, blk, 0, s, g, (const cd*)Gx, (const cd*)Gy, m, r, gamma, slot)
   NF_DISPATCH(g.nx, L_)
@@ -1495,7 +1493,7 @@ hipError_t launchb_sum_slot(const SumArgs* A, int count, int K, int n, int o, hi
   return hipGetLastError();
 }
 hipError_t launchb_row_r2c(const Geo& g, const RowR2cArgs* A, int count, hipStream_t s) {
-  const dim3 grid(row_nwg(g), count), blk(TPF);
+  const dim3 grid(row_nwg(g, 1), count), blk(row_threads(g.nx, 1));
 #define L_(N) hipLaunchKernelGGL(kb_row_r2c<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -1523,7 +1521,7 @@ hipError_t launchb_col_grad(const Geo& g, const ColGradArgs* A, int count, bool 
 }
 hipError_t launchb_row_flux(const Geo& g, bool f32, const FluxArgs* A, int count, int it, double tol2,
                             hipStream_t s) {
-  const dim3 grid(row_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2), count), blk(row_threads(g.nx, 2));
   const int nwg_col = col_nwg(g);
   if (f32) {
 #define L_(N) hipLaunchKernelGGL((kb_row_flux<N, float>), grid, blk, 0, s, A, it, nwg_col, tol2)
@@ -1570,7 +1568,7 @@ hipError_t launchb_col_update(const Geo& g, bool f32, const UpdArgs* A, int coun
   return hipGetLastError();
 }
 hipError_t launchb_row_split(const Geo& g, const SplitArgs* A, int count, hipStream_t s) {
-  const dim3 grid(row_nwg(g), count), blk(3 * TPF);
+  const dim3 grid(row_nwg(g, 3), count), blk(row_threads(g.nx, 3));
 #define L_(N) hipLaunchKernelGGL(kb_row_split<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -1584,7 +1582,7 @@ hipError_t launchb_col_heat(const Geo& g, const HeatArgs* A, int count, hipStrea
   return hipGetLastError();
 }
 hipError_t launchb_row_final(const Geo& g, const FinalArgs* A, int count, hipStream_t s) {
-  const dim3 grid(row_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(row_nwg(g, 2), count), blk(row_threads(g.nx, 2));
 #define L_(N) hipLaunchKernelGGL(kb_row_final<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.nx, L_)
 #undef L_
@@ -1612,7 +1610,7 @@ hipError_t launchb_col_refine_acc(const Geo& g, const RefAccArgs* A, int count, 
 namespace nf {
 hipError_t launch_row_adj1(const Geo& g, void* A0, void* A1, const void* G0, const void* G1, const double* m,
                            double* lam_out, double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(4 * TPF);
+  const dim3 grid(row_nwg(g, 4)), blk(row_threads(g.nx, 4));
 #define L_(N)                                                                                                    \
   hipLaunchKernelGGL(k_row_adj1<N>, grid, blk, 0, s, g, (cd*)A0, (cd*)A1, (const cd*)G0, (const cd*)G1, m, lam_out, \
                      c2dt, gamma, dt, relax1)
@@ -1623,7 +1621,7 @@ hipError_t launch_row_adj1(const Geo& g, void* A0, void* A1, const void* G0, con
 hipError_t launch_row_adj2(const Geo& g, const void* M1, const void* M2, const void* P1, const void* P2,
                            const double* m, const double* mu, double* lam, double* grad_r, double* grad_S,
                            hipStream_t s) {
-  const dim3 grid(row_nwg(g)), blk(4 * TPF);
+  const dim3 grid(row_nwg(g, 4)), blk(row_threads(g.nx, 4));
 #define L_(N)                                                                                                 \
   hipLaunchKernelGGL(k_row_adj2<N>, grid, blk, 0, s, g, (const cd*)M1, (const cd*)M2, (const cd*)P1,           \
                      (const cd*)P2, m, mu, lam, grad_r, grad_S)

@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(TPF) k3_row_r2c(Geo g, const double* __restric
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, rows - y0);
   double2 v[C::EP];
-  rowP_gload<NX, 1>(v, f, y0, nrow);
+  rowP_gload<C>(v, f, y0, nrow);
   double s[2] = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(TPF) k3_row_r2c(Geo g, const double* __restric
   __syncthreads();
   lds_fft<double, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 1, 1>(buf, out, nullptr, nullptr, rows, y0, nrow);
+  rowT_store<C, 1>(buf, out, nullptr, nullptr, rows, y0, nrow);
   if (schk) store_partials<C::NT, 2>(s, g, SLOT_SCHK, red);
 }
 
@@ -187,8 +187,8 @@ __global__ void __launch_bounds__(TPF) k3_row_c2r(Geo g, const cd* __restrict__ 
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, rows - y0);
   cd tv[C::ET];
-  rowT_gload<NX, 1>(tv, in, nullptr, nullptr, rows, y0, nrow);
-  rowT_put<NX, 1>(buf, tv);
+  rowT_gload<C>(tv, in, nullptr, nullptr, rows, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -220,12 +220,12 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   const int nrow = min(C::R, rows - y0);
   const size_t n = (size_t)g.nx * rows;
   V tv[C::ET];
-  rowT_gload<NX, 3>(tv, G0, G1, G2, rows, y0, nrow);
+  rowT_gload<C>(tv, G0, G1, G2, rows, y0, nrow);
   P mx[C::EP], my[C::EP], mz[C::EP], rv[C::EP];
-  rowP_gload<NX, 3>(mx, m, y0, nrow);
-  rowP_gload<NX, 3>(my, m + n, y0, nrow);
-  rowP_gload<NX, 3>(mz, m + 2 * n, y0, nrow);
-  rowP_gload<NX, 3>(rv, r, y0, nrow);
+  rowP_gload<C>(mx, m, y0, nrow);
+  rowP_gload<C>(my, m + n, y0, nrow);
+  rowP_gload<C>(mz, m + 2 * n, y0, nrow);
+  rowP_gload<C>(rv, r, y0, nrow);
   if (lo) {
 #pragma unroll
     for (int i = 0; i < C::EP; ++i) {
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
       }
     }
   }
-  rowT_put<NX, 3>(buf, tv);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_flux(Geo g, cx<T>* G0, cx<T>* 
   __syncthreads();
   lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<NX, 3, 3>(buf, G0, G1, G2, rows, y0, nrow);
+  rowT_store<C, 3>(buf, G0, G1, G2, rows, y0, nrow);
   if (kbar) store_partials<C::NT, 7>(ks, g, SLOT_KBAR, red);
   tclk_end(g, 0, it);
 }
@@ -308,10 +308,10 @@ __global__ void __launch_bounds__(4 * TPF) k3_row_split(Geo g, cd* P, cd* G0, cd
     tv[i] = (e < 4 * C::RH && rr < nrow) ? src[(size_t)kx * rows + y0 + rr] : mk<double>(0.0, 0.0);
   }
   double2 m0v[C::EP], m1v[C::EP], m2v[C::EP];
-  rowP_gload<NX, 4>(m0v, m, y0, nrow);
-  rowP_gload<NX, 4>(m1v, m + n, y0, nrow);
-  rowP_gload<NX, 4>(m2v, m + 2 * n, y0, nrow);
-  rowT_put<NX, 4>(buf, tv);
+  rowP_gload<C>(m0v, m, y0, nrow);
+  rowP_gload<C>(m1v, m + n, y0, nrow);
+  rowP_gload<C>(m2v, m + 2 * n, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(4 * TPF) k3_row_split(Geo g, cd* P, cd* G0, cd
     }
   }
   __syncthreads();
-  rowT_store<NX, 4, 3>(buf, P, G0, G1, rows, y0, nrow);
+  rowT_store<C, 3>(buf, P, G0, G1, rows, y0, nrow);
 }
 
 // Last pass of the step: inverse x transform of the three components (already
@@ -398,12 +398,12 @@ __global__ void __launch_bounds__(3 * TPF) k3_row_final(Geo g, const cd* __restr
   const int nrow = min(C::R, rows - y0);
   const size_t n = (size_t)g.nx * rows;
   cd tv[C::ET];
-  rowT_gload<NX, 3>(tv, M0, M1, M2, rows, y0, nrow);
+  rowT_gload<C>(tv, M0, M1, M2, rows, y0, nrow);
   double2 o0[C::EP], o1[C::EP], o2[C::EP];
-  rowP_gload<NX, 3>(o0, m, y0, nrow);
-  rowP_gload<NX, 3>(o1, m + n, y0, nrow);
-  rowP_gload<NX, 3>(o2, m + 2 * n, y0, nrow);
-  rowT_put<NX, 3>(buf, tv);
+  rowP_gload<C>(o0, m, y0, nrow);
+  rowP_gload<C>(o1, m + n, y0, nrow);
+  rowP_gload<C>(o2, m + 2 * n, y0, nrow);
+  rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<double, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<double, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);

@@ -26,18 +26,30 @@ static constexpr double TWO_PI = 6.283185307179586476925286766559;
 static constexpr int TILE = 1024;
 static constexpr int TPF = TILE / 8;  // threads per field: one radix-8 butterfly per stage
 
-template <int NX, int NF>
+// Rows of a row tile of t complex elements per field over lines of h pairs.
+__host__ __device__ constexpr int tile_rows(int h, int t) { return t / h < 1 ? 1 : (t / h > 64 ? 64 : t / h); }
+// Tile of the 2D row passes.  From Nx = 4096 on, the passes over one or two
+// fields hold two rows per workgroup instead of one: the transposed stores then
+// move runs twice as long and leave half as many partial cache lines open in
+// L2 (one 16-wave workgroup per compute unit instead of two 8-wave ones).  The
+// passes over three and four fields keep TILE.
+__host__ __device__ constexpr int row_tile(int nx, int nf) { return (nf <= 2 && nx >= 4096) ? nx : TILE; }
+
+template <int NX, int NF, int RT = TILE>
 struct RowCfg {
   static constexpr int H = NX / 2;
-  static constexpr int R0 = TILE / H;
-  static constexpr int R = R0 < 1 ? 1 : (R0 > 64 ? 64 : R0);  // rows per workgroup
-  static constexpr int NT = TPF * NF;
+  static constexpr int R = tile_rows(H, RT);                    // rows per workgroup
+  static constexpr int NFv = NF;
+  static constexpr int NT = (RT / 8) * NF;
   static constexpr int LS = lpad_use(H) ? lpad_len(H) + 1 : H + 2;  // LDS line stride (room for the FFT's padded layout)
   static constexpr int RH = R * H;                              // pairs per field in the block
   static constexpr int NB = NF * R;                             // LDS lines
   static constexpr int ET = (NF * RH + NT - 1) / NT;            // transposed-image elements per thread
   static constexpr int EP = (RH + NT - 1) / NT;                 // pointwise elements per thread
 };
+// configuration of the 2D row passes
+template <int NX, int NF>
+using Row2D = RowCfg<NX, NF, row_tile(NX, NF)>;
 
 template <int NY, int NF>
 struct ColCfg {
@@ -110,10 +122,10 @@ __device__ __forceinline__ V vzero() {
 // "T" image: element e -> field e / RH, row (e % RH) % R, column (e % RH) / R;
 // coalesced over the column-major mixed layout M[kx][y].  LDS line of (field,
 // row) is field * R + row.
-template <int NX, int NF, typename V>
-__device__ __forceinline__ void rowT_gload(V (&v)[(RowCfg<NX, NF>::ET)], const V* s0, const same<V>* s1, const same<V>* s2,
+template <class C, typename V>
+__device__ __forceinline__ void rowT_gload(V (&v)[(C::ET)], const V* s0, const same<V>* s1, const same<V>* s2,
                                            int ny, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
+  constexpr int NF = C::NFv;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -122,9 +134,9 @@ __device__ __forceinline__ void rowT_gload(V (&v)[(RowCfg<NX, NF>::ET)], const V
     v[i] = (e < NF * C::RH && rr < nrow) ? pick<V>(f, s0, s1, s2)[(size_t)kx * ny + y0 + rr] : vzero<V>();
   }
 }
-template <int NX, int NF, typename V>
-__device__ __forceinline__ void rowT_put(V* buf, const V (&v)[(RowCfg<NX, NF>::ET)]) {
-  using C = RowCfg<NX, NF>;
+template <class C, typename V>
+__device__ __forceinline__ void rowT_put(V* buf, const V (&v)[(C::ET)]) {
+  constexpr int NF = C::NFv;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -133,9 +145,8 @@ __device__ __forceinline__ void rowT_put(V* buf, const V (&v)[(RowCfg<NX, NF>::E
   }
 }
 // store the first NFS fields of the block back to the mixed layout
-template <int NX, int NF, int NFS, typename V>
+template <class C, int NFS, typename V>
 __device__ __forceinline__ void rowT_store(const V* buf, same<V>* d0, same<V>* d1, same<V>* d2, int ny, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
   for (int e = threadIdx.x; e < NFS * C::RH; e += C::NT) {
     const int f = e / C::RH, ee = e % C::RH;
     const int rr = ee % C::R, kx = ee / C::R;
@@ -144,9 +155,9 @@ __device__ __forceinline__ void rowT_store(const V* buf, same<V>* d0, same<V>* d
 }
 // "P" image of a physical field: element p -> row p / H, pair p % H (the
 // grid points 2j, 2j+1 of the row), coalesced over the row-major layout
-template <int NX, int NF, typename P, typename S>
-__device__ __forceinline__ void rowP_gload(P (&v)[(RowCfg<NX, NF>::EP)], const S* __restrict__ f, int y0, int nrow) {
-  using C = RowCfg<NX, NF>;
+template <class C, typename P, typename S>
+__device__ __forceinline__ void rowP_gload(P (&v)[(C::EP)], const S* __restrict__ f, int y0, int nrow) {
+  constexpr int NX = 2 * C::H;
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
