@@ -35,6 +35,34 @@ Readings of points the paper leaves open:
   ``I - g g^T / |g|^2`` (identical in 2D);
 * the energy of Sec. 2.5 uses the same spectral gradient, the variable ``r``
   inside the ``||grad p||^2`` term, and ``p = p[m]`` for the same ``m``.
+
+Pins (tests/test_oracle_pins.py; each is something other than this code)
+------------------------------------------------------------------------
+* wavenumbers, first_derivative_wavenumbers: hand-worked example (golden file),
+  Nyquist checkerboards annihilated;
+* grad, neg_div, apply_K, apply_A: exact derivatives of trigonometric modes,
+  symbolic (sympy) divergence of manufactured 2D/3D solutions, adjointness,
+  eigenpairs of K;
+* null_mode_mask, project, assemble_A, pressure_dense: symmetry, positive
+  semi-definiteness and exact nullity 2^d with the checkerboard basis;
+* kbar, apply_Minv, pressure_pcg: closed-form Fourier solution for constant
+  coefficients (one iteration), SVD minimum-norm solves, the energy identity,
+  invariance to the preconditioner's scale, warm start and failure paths;
+* activation: scipy.linalg.expm, RK4 of the ODE, special directions, semigroup;
+* relaxation: closed forms at gamma = 1 and 1/2, RK4, semigroup, extinction;
+* diffusion: heat-kernel decay per Fourier mode (Nyquist included), mean,
+  semigroup;
+* split_update: order of the sub-steps (activation before relaxation by the
+  closed forms at gamma = 1/2; diffusion last by mean preservation), axis-swap
+  and reflection equivariance;
+* energy: single-mode closed form of the diffusion term, two-valued fields for
+  the relaxation term at three gamma, constant-coefficient closed forms of both
+  pressure terms, the pressure energy identity, and the gradient-flow identity
+  (its directional derivative is minus the flow's right-hand side);
+* dm_rel: hand-worked example (golden file) and the closed form |a - 1| / dt
+  for m^k = a m^{k-1};
+* run: stopping criteria, energy decrease for small dt;
+* step_adjoint, run_gradient: central differences of the forward map.
 """
 
 from __future__ import annotations

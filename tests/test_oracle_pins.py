@@ -540,3 +540,207 @@ def test_run_gradient_matches_central_differences():
     fd_S = _fd(lambda x: loss(w["r"], x), w["S"], vS, h)
     assert abs(fd_r - np.sum(gr * vr)) < 1e-5 * abs(fd_r)
     assert abs(fd_S - np.sum(gS * vS)) < 1e-5 * abs(fd_S)
+
+
+# ---------------------------------------------------------------- Sec. 2.5 pins ------
+
+def _read_dm_cases():
+    path = __file__.replace("test_oracle_pins.py", "golden/dm_rel_worked_example.txt")
+    cases, cur = [], None
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if not line:
+                continue
+            if line[0] == "case":
+                cur = {}
+                cases.append(cur)
+            else:
+                vals = [float(v) for v in line[1:]]
+                cur[line[0]] = vals[0] if len(vals) == 1 else np.array(vals).reshape(2, 2)
+    return cases
+
+
+def test_dm_rel_worked_example():
+    # Sec. 2.5: hand-computed values (golden file), including the case that tells
+    # the old state's norm in the denominator from the new one's
+    cases = _read_dm_cases()
+    assert len(cases) == 2
+    for c in cases:
+        old = np.stack([c["old_x"], c["old_y"]])
+        new = np.stack([c["new_x"], c["new_y"]])
+        assert abs(O.dm_rel(new, old, c["dt"]) - c["want"]) < 1e-14 * c["want"]
+
+
+@pytest.mark.parametrize("a", [0.5, 1.5, 2.0, -1.0])
+def test_dm_rel_closed_form_for_scaled_state(a):
+    # m^k = a m^{k-1}: ||(a - 1) m^{k-1}|| / (dt ||m^{k-1}||) = |a - 1| / dt, whatever
+    # m^{k-1} and the grid (the discrete L2 weights cancel)
+    rng = np.random.default_rng(61)
+    dt = 2.5e-3
+    for shape in ((2, 8, 16), (3, 4, 4, 8)):
+        old = rng.standard_normal(shape)
+        assert abs(O.dm_rel(a * old, old, dt) - abs(a - 1.0) / dt) < 1e-12 * abs(a - 1.0) / dt
+    assert O.dm_rel(old, old, dt) == 0.0
+
+
+def test_energy_diffusion_term_single_mode():
+    # D^2/2 ||grad m||^2 for m_c = A_c cos(2 pi k_c . x / L + phi_c): |grad m_c|^2 has
+    # grid mean A_c^2 |xi_c|^2 / 2 (k_c below the Nyquist index), so the term is
+    # D^2/2 * |Omega| * sum_c A_c^2 |xi_c|^2 / 2
+    n, L = (32, 16), (1.0, 2.0)
+    X, Y = W.grid_coords(n, L)
+    area = L[0] * L[1]
+    D2 = 3e-3
+    modes = [((3, -2), 0.7, 0.4), ((1, 5), -1.3, 2.0)]
+    m = np.empty((2,) + X.shape)
+    want = 0.0
+    for c, (k, A, ph) in enumerate(modes):
+        m[c] = A * np.cos(2 * np.pi * (k[0] * X / L[0] + k[1] * Y / L[1]) + ph)
+        xi2 = (2 * np.pi * k[0] / L[0]) ** 2 + (2 * np.pi * k[1] / L[1]) ** 2
+        want += A * A * xi2 / 2.0
+    want *= 0.5 * D2 * area
+    r = np.full(X.shape, 0.1)
+    p = np.zeros(X.shape)
+    e = O.energy(m, p, r, 5.0, D2, 0.75, L)
+    assert abs(e[1] - want) < 1e-12 * want
+    # the pressure terms vanish for p = 0, the total is the sum of its terms
+    assert e[3] == 0.0 and e[4] == 0.0
+    assert abs(e[0] - (e[1] + e[2])) < 1e-14 * e[0]
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.75, 1.2])
+def test_energy_relaxation_term_two_valued_field(gamma):
+    # ||  |m|^gamma ||^2 / (2 gamma) with half of the nodes at |m| = 2 and half at
+    # |m| = 1/2: |Omega| / 2 * (2^{2 gamma} + 2^{-2 gamma}) / (2 gamma); and at |m| = 1
+    # everywhere: |Omega| / (2 gamma)
+    n, L = (8, 16), (2.0, 0.5)
+    area = L[0] * L[1]
+    m = np.zeros((2, 16, 8))
+    m[0, :, ::2] = 2.0
+    m[0, :, 1::2] = 0.3
+    m[1, :, 1::2] = 0.4
+    r = np.full((16, 8), 0.1)
+    p = np.zeros((16, 8))
+    want = {0.5: 2.5, 0.75: 2.0 ** 1.5 + 2.0 ** -1.5, 1.2: 2.0 ** 2.4 + 2.0 ** -2.4}[gamma]
+    want = area / 2.0 * want / (2.0 * gamma)
+    e = O.energy(m, p, r, 1.0, 0.0, gamma, L)
+    assert abs(e[2] - want) < 1e-13 * want
+    unit = np.stack([np.full((16, 8), 0.6), np.full((16, 8), -0.8)])
+    assert abs(O.energy(unit, p, r, 1.0, 0.0, gamma, L)[2] - area / (2.0 * gamma)) < 1e-13
+
+
+def test_energy_pressure_terms_constant_coefficients():
+    # constant m, r and S = A cos(2 pi k.x/L): p = S / (xi^T K xi) (closed-form
+    # Fourier solution), so with the grid mean of sin^2 = 1/2
+    #   c^2/2 ||m . grad p||^2 = c^2/2 (m.xi)^2 A^2 / (xi^T K xi)^2 |Omega| / 2,
+    #   c^2/2 sum r |grad p|^2 = c^2/2 r |xi|^2 A^2 / (xi^T K xi)^2 |Omega| / 2
+    n, L = (16, 32), (1.5, 1.0)
+    X, Y = W.grid_coords(n, L)
+    area = L[0] * L[1]
+    mc = np.array([0.6, -0.3])
+    rc, c2, A = 0.2, 11.0, 0.8
+    k = (2, 3)
+    xi = np.array([2 * np.pi * k[0] / L[0], 2 * np.pi * k[1] / L[1]])
+    S = A * np.cos(xi[0] * X + xi[1] * Y + 0.3)
+    m = np.broadcast_to(mc[:, None, None], (2,) + X.shape).copy()
+    r = np.full(X.shape, rc)
+    p, info = O.pressure_pcg(m, r, S, None, 1e-13, 50, L)
+    lam = xi @ (np.outer(mc, mc) + rc * np.eye(2)) @ xi
+    e = O.energy(m, p, r, c2, 1e-3, 0.75, L)
+    want_act = 0.5 * c2 * (mc @ xi) ** 2 * A * A / lam ** 2 * area / 2
+    want_flow = 0.5 * c2 * rc * (xi @ xi) * A * A / lam ** 2 * area / 2
+    assert abs(e[3] - want_act) < 1e-11 * want_act
+    assert abs(e[4] - want_flow) < 1e-11 * want_flow
+
+
+def _band_limited_state(n, L, seed):
+    """Conductivity built from a few low Fourier modes (no Nyquist content),
+    bounded away from zero; r likewise positive."""
+    rng = np.random.default_rng(seed)
+    X, Y = W.grid_coords(n, L)
+    m = np.empty((2,) + X.shape)
+    for c in range(2):
+        f = np.full(X.shape, 0.8 if c == 0 else 0.5)
+        for _ in range(3):
+            k = rng.integers(-3, 4, size=2)
+            f += 0.15 * rng.standard_normal() * np.cos(2 * np.pi * (k[0] * X / L[0] + k[1] * Y / L[1]) + rng.uniform(0, 6))
+        m[c] = f
+    r = 0.1 + 0.03 * np.cos(2 * np.pi * X / L[0])
+    S = np.cos(2 * np.pi * (X / L[0] + 2 * Y / L[1])) + 0.5 * np.sin(2 * np.pi * 3 * Y / L[1])
+    S -= S.mean()
+    return m, r, S, rng
+
+
+@pytest.mark.parametrize("c2,D2,gamma", [(0.0, 0.0, 0.6), (0.0, 0.05, 1.3), (40.0, 0.0, 0.75), (25.0, 0.02, 1.0)])
+def test_energy_is_lyapunov_functional_of_the_split_flow(c2, D2, gamma):
+    # Sec. 1.1 / Sec. 2.5: the conductivity equation is the gradient flow of the
+    # energy.  On the grid: the directional derivative of E_h along any v equals
+    # -h^d sum F(m) . v, where F is the right-hand side of the semi-discrete flow,
+    # here taken as d/dt of one split update at dt = 0 (activation, relaxation and
+    # diffusion each contribute their own term to first order).  A wrong factor,
+    # power or coefficient in any energy term breaks the identity.
+    n, L = (16, 16), (1.0, 1.0)
+    m, r, S, rng = _band_limited_state(n, L, 71)
+    hvol = L[0] * L[1] / (n[0] * n[1])
+
+    def p_of(mm):
+        return O.pressure_pcg(mm, r, S, None, 1e-14, 4000, L)[0]
+
+    def E(mm):
+        return O.energy(mm, p_of(mm), r, c2, D2, gamma, L)[0]
+
+    p = p_of(m)
+    d = 1e-4
+    F = (O.split_update(m, p, c2, D2, gamma, d, L) - O.split_update(m, p, c2, D2, gamma, -d, L)) / (2 * d)
+    v = rng.standard_normal(m.shape)
+    eps = 1e-5
+    dE = (E(m + eps * v) - E(m - eps * v)) / (2 * eps)
+    want = -hvol * float(np.sum(F * v))
+    assert abs(dE - want) < 1e-6 * (abs(want) + 1e-3 * hvol * np.linalg.norm(F) * np.linalg.norm(v))
+    # and along v = F itself the energy decreases at the rate h^d ||F||^2
+    dEF = (E(m + eps * F) - E(m - eps * F)) / (2 * eps)
+    assert dEF < 0 and abs(dEF + hvol * float(np.sum(F * F))) < 1e-6 * hvol * float(np.sum(F * F))
+
+
+def test_split_order_activation_before_relaxation():
+    # Algorithm 1 applies activation, then relaxation, then diffusion.  With D = 0,
+    # gamma = 1/2 and grad p parallel to m the two pointwise maps have closed forms
+    # (|m| -> |m| e^{c^2 |g|^2 dt}, then |m| -> max(|m| - dt, 0)); activation first
+    # gives max(|m| e^{c^2|g|^2 dt} - dt, 0), relaxation first (|m| - dt) e^{...}.
+    n = (16, 8)
+    X, Y = W.grid_coords(n, 1.0)
+    alpha = 0.9
+    p = alpha * np.cos(2 * np.pi * X) / (2 * np.pi)         # g = (-alpha sin(2 pi x), 0)
+    g2 = (alpha * np.sin(2 * np.pi * X)) ** 2
+    mx = 0.05 + 0.3 * (1 + np.cos(2 * np.pi * Y))           # > 0, along x like g
+    m = np.stack([mx, np.zeros_like(mx)])
+    c2, dt = 6.0, 0.04
+    out = O.split_update(m, p, c2, 0.0, 0.5, dt)
+    E = np.exp(c2 * g2 * dt)
+    want = np.maximum(mx * E - dt, 0.0)
+    assert np.max(np.abs(out[0] - want)) < 1e-14
+    assert np.max(np.abs(out[1])) < 1e-15
+    other = np.maximum(mx - dt, 0.0) * E
+    assert np.max(np.abs(out[0] - other)) > 1e-3
+
+
+def test_split_order_diffusion_last():
+    # The heat multiplier keeps the grid mean of each component.  With p = 0
+    # (activation is the identity) the mean of the split update therefore equals
+    # the mean of the relaxed field when diffusion comes last; with a soft
+    # threshold (gamma = 1/2) acting on a sign-changing field, relaxing the
+    # diffused field instead gives a different mean.
+    n = (32, 16)
+    X, Y = W.grid_coords(n, 1.0)
+    mx = 0.3 + np.cos(2 * np.pi * X) + 0.2 * np.sin(2 * np.pi * Y)
+    my = -0.2 + 0.7 * np.cos(2 * np.pi * (X + Y))
+    m = np.stack([mx, my])
+    D2, dt = 1e-2, 0.1
+    out = O.split_update(m, np.zeros_like(mx), 3.0, D2, 0.5, dt)
+    s = np.sqrt(mx * mx + my * my)
+    fac = np.maximum(s - dt, 0.0) / s                        # closed form of relaxation at gamma = 1/2
+    for c in range(2):
+        assert abs(out[c].mean() - (m[c] * fac).mean()) < 1e-14
+    swapped = O.relaxation(O.diffusion(m, D2, dt), 0.5, dt)
+    assert max(abs(swapped[c].mean() - out[c].mean()) for c in range(2)) > 1e-4
