@@ -154,6 +154,27 @@ int nf_pressure_solve(nf_grid *g, const double *m, const double *r, const double
                       int max_iter, nf_solve_info *info);
 
 /*
+ * Allocation-free pressure solve, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Computes what nf_pressure_solve computes on an FP64
+ * handle for the same grid (same kernels, same results), without a handle:
+ *   n    (Nx, Ny), powers of two in [8, 4096] with Nx * Ny <= 65536;
+ *   L    (Lx, Ly) > 0;  stream as for nf_create_grid;
+ *   m, r, S, p, rtol, max_iter, info as for nf_pressure_solve.
+ * Workspace: a fixed device array of 8 MiB per GPU (the library's own,
+ * held by every GPU it runs on until the process ends); no hipMalloc,
+ * hipFree, pinned host memory or events are used.  All calls on one GPU share
+ * that array and each call overwrites it, so calls that overlap on one GPU
+ * (several streams or host threads) race and must be serialised by the
+ * caller.  The call synchronises its stream (convergence is polled).
+ * Returns NF_EINVAL for sizes outside the limits above (message in
+ * nf_last_error(NULL)), before any device work; otherwise the codes of
+ * nf_pressure_solve.
+ */
+int nf_pressure_solve_noalloc(const int64_t n[2], const double L[2], void *stream, const double *m, const double *r,
+                              const double *S, double *p, double rtol, int max_iter, nf_solve_info *info);
+
+/*
  * One pass of the time loop of Algorithm 1:
  *   Step 1: p <- p[m^k] (as nf_pressure_solve, warm start from p on entry);
  *   Step 2: with g = grad p, exact activation (eq. m_activation_discrete), exact

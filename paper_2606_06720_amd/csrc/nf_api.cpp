@@ -191,6 +191,7 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
     // chunk: the host polls one chunk behind, so at most about one chunk of
     // launches is queued past the stop (they return at once)
     int nk = first_chunk ? (expect > 3 ? expect - 1 : 2) : 1;
+    if (!g->hst) nk = 8;  // synchronous polling: a few iterations per wait
     first_chunk = false;
     if (nk > max_iter - it) nk = max_iter - it;
     for (int k = 0; k < nk; ++k) {
@@ -230,6 +231,14 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
         LCHK(g, launch_col_update(G, 0, g->xh, g->rh, g->dh, g->qh, g->mix[0], g->mix[1], it + 1, max_iter, tol2,
                                   s, e0, e1));
       ++it;
+    }
+    if (!g->hst) {
+      // allocation-free solve (no pinned buffer, no events): wait for the chunk
+      DevStatus cur;
+      HIPCHK(g, hipMemcpyAsync(&cur, g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+      HIPCHK(g, hipStreamSynchronize(s));
+      if (cur.conv_at != INT_MAX) break;
+      continue;
     }
     HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipEventRecord(g->ev[slot], s));
@@ -763,6 +772,91 @@ int nf_pressure_solve(nf_grid* g, const double* m, const double* r, const double
   }
   HIPCHK(g, hipStreamSynchronize(g->stream));
   return solve_status_code(g, so);
+}
+
+int nf_pressure_solve_noalloc(const int64_t n[2], const double L[2], void* stream, const double* m, const double* r,
+                              const double* S, double* p, double rtol, int max_iter, nf_solve_info* info) {
+  create_err.clear();
+  auto reject = [](const char* msg) {
+    create_err = msg;
+    return NF_EINVAL;
+  };
+  // every argument is checked before the device is touched
+  if (!n || !L) return reject("NULL grid size or box length");
+  const int64_t nx = n[0], ny = n[1];
+  if (!is_pow2_in_range(nx) || !is_pow2_in_range(ny))
+    return reject("allocation-free solve: Nx and Ny must be powers of two in [8, 4096]");
+  if (nx * ny > NOALLOC_MAX_POINTS)
+    return reject("allocation-free solve: Nx * Ny exceeds the fixed workspace (at most 65536 grid points)");
+  if (!(L[0] > 0.0) || !(L[1] > 0.0)) return reject("box lengths must be > 0");
+  if (!m || !r || !S || !p) return reject("NULL field pointer");
+  if (!(rtol >= 0.0) || max_iter < 0) return reject("rtol must be >= 0 and max_iter >= 0");
+  void* base = nullptr;
+  hipError_t herr = noalloc_scratch(&base);
+  if (herr != hipSuccess) {
+    create_err = std::string("device address of the fixed workspace: ") + hipGetErrorString(herr);
+    return NF_EDEVICE;
+  }
+  // A handle on the stack whose workspace is carved from the fixed array: no
+  // pinned status buffer and no events (the PCG loop then polls synchronously).
+  nf_grid G;
+  nf_grid* g = &G;
+  g->dim = 2;
+  g->nx = (int)nx;
+  g->ny = (int)ny;
+  g->nz = 1;
+  g->h = g->nx / 2;
+  g->lx = L[0];
+  g->ly = L[1];
+  g->stream = (hipStream_t)stream;
+  g->dtype = NF_F64;
+  g->twn = (int)(nx > ny ? nx : ny);  // lcm of two powers of two
+  (void)hipGetDevice(&g->device);
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    void* q = (char*)base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  const size_t spec_bytes = (size_t)g->h * g->ny * 2 * sizeof(double);
+  void** spec[] = {&g->xh, &g->rh, &g->dh, &g->qh, &g->bh, &g->mix[0], &g->mix[1], &g->mix[2]};
+  for (void** b : spec) *b = carve(spec_bytes);
+  const size_t part_doubles = (size_t)NSLOTS * SLOT_K * MAX_WG + NSLOTS * SLOT_K;
+  g->part = (double*)carve(part_doubles * sizeof(double));
+  g->st = (DevStatus*)carve(sizeof(DevStatus));
+  g->tw = carve((size_t)g->twn * 2 * sizeof(double));
+  if (off > NOALLOC_SCRATCH_BYTES) return reject("allocation-free solve: workspace layout exceeds the fixed array");
+  // twiddles from the same long-double table as nf_create_grid (host copy per thread)
+  static thread_local double twh[2 * NOALLOC_MAX_TWIDDLES];
+  make_twiddles(g->twn, twh);
+  herr = hipMemcpyAsync(g->tw, twh, (size_t)g->twn * 2 * sizeof(double), hipMemcpyHostToDevice, g->stream);
+  if (herr != hipSuccess) {
+    create_err = std::string("twiddle upload: ") + hipGetErrorString(herr);
+    return NF_EDEVICE;
+  }
+  Geo& Gg = g->geo;
+  Gg.nx = g->nx;
+  Gg.ny = g->ny;
+  Gg.h = g->h;
+  Gg.twn = g->twn;
+  Gg.lx = g->lx;
+  Gg.ly = g->ly;
+  Gg.inv_n = 1.0 / ((double)g->nx * (double)g->ny);
+  Gg.tw = g->tw;
+  Gg.st = g->st;
+  Gg.part = g->part;
+  Gg.nz = 1;
+  Gg.lz = 1.0;
+  Gg.pstride = MAX_WG;
+  Gg.tot = g->part + (size_t)NSLOTS * SLOT_K * MAX_WG;
+  Gg.tclk = nullptr;
+  Gg.tkind = -1;
+  // the array keeps the previous call's contents: clear the partial sums (a
+  // fill kernel, no memset node) before the solve resets the status
+  int rc = check_launch(g, launch_zero_doubles(g->part, part_doubles, g->stream), "clear workspace");
+  if (rc == NF_OK) rc = nf_pressure_solve(g, m, r, S, p, rtol, max_iter, info);
+  if (rc != NF_OK) create_err = g->err;
+  return rc;
 }
 
 int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, const double* r, const double* S,

@@ -173,6 +173,17 @@ struct SumArgs {
   DevStatus* st;
 };
 
+// ---- fixed workspace of the allocation-free solve (nf_noalloc.hip) ------------------
+// Size of the per-GPU device array and the largest grid it serves: 2D FP64,
+// Nx * Ny <= NOALLOC_MAX_POINTS (8 complex half-spectrum fields of 8 bytes per
+// grid point, the partial-sum slots, the status block and a twiddle table of
+// at most 4096 entries).
+enum : size_t { NOALLOC_SCRATCH_BYTES = 8u << 20 };
+enum { NOALLOC_MAX_POINTS = 65536, NOALLOC_MAX_TWIDDLES = 4096, NOALLOC_MAX_DEVICES = 64 };
+// Device address of the current GPU's copy of the array (looked up on the
+// first call for that GPU and kept).
+hipError_t noalloc_scratch(void** out);
+
 // ---- host-callable launchers (defined in nf_kernels.hip) --------------------------
 // All take the stream last and return hipError_t of the launch.
 struct Bufs;

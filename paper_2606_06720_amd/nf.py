@@ -85,6 +85,8 @@ def _load():
     lib.nf_destroy_grid.argtypes = [vp]
     lib.nf_set_stream.argtypes = [vp, vp]
     lib.nf_pressure_solve.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, ctypes.POINTER(nf_solve_info)]
+    lib.nf_pressure_solve_noalloc.argtypes = [i64p, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp, dp,
+                                              ctypes.c_int, ctypes.POINTER(nf_solve_info)]
     lib.nf_step.argtypes = [vp, ctypes.POINTER(nf_params), dp, vp, vp, vp, vp, dp, ctypes.c_int,
                             ctypes.POINTER(nf_step_info)]
     lib.nf_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp, vp,
@@ -113,7 +115,8 @@ def _load():
     lib.nf_last_error.argtypes = [vp]
     lib.nf_last_error.restype = ctypes.c_char_p
     lib.nf_version.restype = ctypes.c_char_p
-    for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_step", "nf_run",
+    for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_pressure_solve_noalloc",
+              "nf_step", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
               "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_batch_create", "nf_batch_destroy",
               "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions",
@@ -424,6 +427,26 @@ def nf_destroy_grid(g):
 
 def nf_pressure_solve(g, m, r, S, p, rtol=1e-10, max_iter=1000):
     return g.pressure_solve(m, r, S, p, rtol, max_iter)
+
+
+def nf_pressure_solve_noalloc(n, L, m, r, S, p, rtol=1e-10, max_iter=1000, allow_notconv=False):
+    """nf_pressure_solve_noalloc on the current torch stream: the handle-free
+    solve whose workspace is the library's fixed device array (2D FP64,
+    power-of-two sides, Nx * Ny <= 65536).  Returns (rc, SolveInfo)."""
+    n = tuple(int(v) for v in n)
+    L = tuple(float(v) for v in (L if L is not None else (1.0, 1.0)))
+    if len(n) != 2 or len(L) != 2:
+        raise ValueError("2D grids only")
+    ss, vs = (n[1], n[0]), (2, n[1], n[0])
+    nn = (ctypes.c_int64 * 2)(*n)
+    LL = (ctypes.c_double * 2)(*L)
+    info = nf_solve_info()
+    rc = _lib.nf_pressure_solve_noalloc(nn, LL, _current_stream(), _ptr(m, vs, "m"), _ptr(r, ss, "r"),
+                                        _ptr(S, ss, "S"), _ptr(p, ss, "p"), float(rtol), int(max_iter),
+                                        ctypes.byref(info))
+    if rc != NF_OK and not (allow_notconv and rc == NF_ENOTCONV):
+        raise NfError(rc, _lib.nf_last_error(None).decode())
+    return rc, _si(info)
 
 
 def nf_step(g, c2, D2, gamma, dt, m, p, r, S, rtol=1e-10, max_iter=1000):

@@ -85,3 +85,19 @@ def test_batch_create_rejects_bad_sizes_on_host(lib):
         LL = (ctypes.c_double * len(sizes))(*([1.0] * len(sizes)))
         assert lib.nf_batch_create(ctypes.byref(h), len(sizes) // 2, nn, LL, 0, None) == -1
         assert not h.value
+
+
+@pytest.mark.parametrize("n", [(512, 256), (256, 512), (4096, 32), (50, 50), (12, 16), (8192, 8)])
+def test_noalloc_solve_rejects_sizes_beyond_its_workspace_on_host(lib, n):
+    # the size check comes before any device work, so it runs without a GPU
+    nn = (ctypes.c_int64 * 2)(*n)
+    L = (ctypes.c_double * 2)(1.0, 1.0)
+    dummy = ctypes.c_void_p(16)
+    lib.nf_pressure_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                              ctypes.c_int, ctypes.c_void_p]
+    lib.nf_last_error.restype = ctypes.c_char_p
+    lib.nf_last_error.argtypes = [ctypes.c_void_p]
+    rc = lib.nf_pressure_solve_noalloc(nn, L, None, dummy, dummy, dummy, dummy, 1e-10, 100, None)
+    assert rc == -1
+    assert b"allocation-free" in lib.nf_last_error(None)
