@@ -80,31 +80,90 @@ def load_rocprof_duration(kernel, n):
     return d.get("concurrent_working_avg_us")
 
 
-def cpu_baseline(N, steps):
-    import numpy as np
-
+def _oracle_steps(N, gamma, steps, barrier=None):
+    """Worker of the CPU baseline: `steps` oracle time steps of the dipole case
+    from m0 (the start of the GPU line's window); returns (seconds, PCG iterations)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import oracle as O
     from paper_2606_06720_amd import workloads as W
 
-    w = W.dipole_workload(N, 0.75)
+    w = W.dipole_workload(N, gamma)
     m, p = w["m0"], None
+    if barrier is not None:
+        barrier.wait()
     iters = 0
     t0 = time.perf_counter()
     for _ in range(steps):
         m, p, info = O.step(m, p, w["r"], w["S"], w["c2"], w["D2"], w["gamma"], w["dt"], w["rtol"])
         iters += info.iters
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, iters
+
+
+def _pool_worker(args):
+    return _oracle_steps(*args, barrier=_POOL_BARRIER)
+
+
+_POOL_BARRIER = None
+
+
+def _pool_init(b):
+    global _POOL_BARRIER
+    _POOL_BARRIER = b
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, steps, max_workers=16):
+    """The oracle (numpy FP64, single-threaded FFTs) on the host cores, on a bounded
+    sample of the GPU line's window: its first `steps` time steps from m0.
+    One thread: the gamma = 0.75 instance in this process.  All cores: one
+    worker process per available core (at most `max_workers`, the CPU share of
+    one GPU), each running one instance (the three gamma values in turn) for
+    the same steps, started together; the aggregate rate is the sum of the
+    workers' rates.  Runs before anything touches the GPU."""
+    import multiprocessing as mp
+
+    t1, it1 = _oracle_steps(N, 0.75, steps)
+    cores = max(1, min(len(os.sched_getaffinity(0)), max_workers))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    jobs = [(N, GAMMAS[k % len(GAMMAS)], steps) for k in range(cores)]
+    with ctx.Pool(cores, initializer=_pool_init, initargs=(barrier,)) as pool:
+        res = pool.map(_pool_worker, jobs, chunksize=1)
+    rate_all = sum(N * N * steps / t for t, _ in res)
+    iters_all = sum(i for _, i in res)
+    t_all = max(t for t, _ in res)
     return {
-        "value": N * N * steps / dt,
+        "value": rate_all,
         "unit": "grid-point-steps/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": "first %d time steps of the gamma=0.75 instance from m0 at %d^2 (%d PCG iterations, "
-                  "%.1f s; numpy FFT, single thread)" % (steps, N, iters, dt),
+        "sample": "first %d time step(s) from m0 of the %d^2 dipole instances (the start of the GPU line's window); "
+                  "one thread: gamma 0.75, %d PCG iterations, %.1f s; all cores: %d worker processes (one instance "
+                  "each, gammas in turn, started together), %d PCG iterations, slowest %.1f s; numpy FFT"
+                  % (steps, N, it1, t1, cores, iters_all, t_all),
+        "value_1": N * N * steps / t1,
+        "value_all": rate_all,
+        "cores_all": cores,
+        "cpu_model": cpu_model(),
+        "pcg_iters_per_step": it1 / steps,
+        # like-for-like across windows with different iteration counts: grid points
+        # times PCG iterations per second
+        "grid_point_iters_per_s_1": N * N * it1 / t1,
+        "grid_point_iters_per_s_all": sum(N * N * i / t for t, i in res),
     }
 
 
-def adjoint_cost(N, steps):
+def adjoint_cost(N, steps, fd_dirs=32):
     """Cost of reverse mode at N^2 (gamma = 0.75, the 1024^2 dipole case): one
     nf_step_adjoint against one nf_step (both from the same state), and the
     sqrt(T)-checkpointed gradient of the misfit of the final |m| after `steps`
@@ -161,9 +220,42 @@ def adjoint_cost(N, steps):
                 g.step(*prm, w["dt"], mm, pp, r, S, rtol=rtol, max_iter=1000)
         torch.cuda.synchronize()
         t_rec = time.perf_counter() - t0
+        fd = None
+        if fd_dirs > 0:
+            # central differences of the misfit along random directions, half
+            # in r and half in S (S directions made mean-free), against the
+            # checkpointed gradient; both at a tight PCG tolerance, since the
+            # noise of a difference quotient is about rtol / h relative to the loss
+            rtol_fd, h = 1e-12, 1e-6
+            l0, gr, gS = A.run_gradient(g, prm, w["dt"], steps, m0, r, S, m_tgt, rtol=rtol_fd, max_iter=2000)
+
+            def L(r_, S_):
+                m_T, _ = A.forward_states(g, prm, w["dt"], steps, m0, r_, S_, rtol_fd, 2000, steps)
+                return A.misfit_loss(m_T, m_tgt)[0]
+
+            rng = np.random.default_rng(7)
+            err_r, err_S = [], []
+            for k in range(fd_dirs):
+                if k % 8 == 0:
+                    progress("adjoint finite differences: direction %d of %d" % (k, fd_dirs))
+                v = rng.standard_normal((N, N))
+                if k % 2 == 0:
+                    vt = T(v)
+                    fdv = (L(r + h * vt, S) - L(r - h * vt, S)) / (2 * h)
+                    err_r.append(abs(fdv - float((gr * vt).sum())) / abs(float((gr * vt).sum())))
+                else:
+                    vt = T(v - v.mean())
+                    fdv = (L(r, S + h * vt) - L(r, S - h * vt)) / (2 * h)
+                    err_S.append(abs(fdv - float((gS * vt).sum())) / abs(float((gS * vt).sum())))
+            fd = {"directions": fd_dirs, "h": h, "rtol": rtol_fd, "loss": l0,
+                  "directions_r": len(err_r), "directions_S": len(err_S),
+                  "max_rel_err_r": max(err_r) if err_r else None, "max_rel_err_S": max(err_S) if err_S else None,
+                  "median_rel_err_r": float(np.median(err_r)) if err_r else None,
+                  "median_rel_err_S": float(np.median(err_S)) if err_S else None}
     t_adj = t_sweep - t_rec
     t_fwd = t_run / steps
     return {
+        "fd_check": fd,
         "workload": "%d^2 dipole case, gamma 0.75, PCG rtol 1e-10, misfit of the final |m|" % N,
         "gradient_steps": steps,
         "checkpoint_stride": stride,
@@ -178,11 +270,37 @@ def adjoint_cost(N, steps):
     }
 
 
+def oracle_sample(case):
+    """The oracle's stored one-step reference for the precision-form sizes
+    (tests/golden/make_precision_golden.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "precision_%s.json" % case)
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return None
+
+
+def sampled_errors(gold, m, p):
+    """Relative L2 error over the stored sample nodes, per field (m components, p)."""
+    import numpy as np
+
+    idx = np.asarray(gold["index"])
+    out = {}
+    for k, v in gold["fields"].items():
+        f = p if k == "p" else m[int(k[1:])]
+        got = f.reshape(-1)[idx]
+        want = np.asarray(v["sample"])
+        out[k] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    return out
+
+
 def precision_form(sizes, steps, warmup=3):
     """FP64 and FP32-refined pressure solves on the same GPU: ms per time step
-    of the dipole case (gamma 0.75) at each (N, ndim), and the relative L2
-    difference of m and p after the same steps from the same state (the FP64
-    form is held to the oracle at 1e-10)."""
+    of the dipole case (gamma 0.75) at each (N, ndim), the relative L2
+    difference of m and p between the forms after the same steps from the same
+    state, and, where the oracle's reference is stored, the error of one step
+    from m0 of each form against the FP64 oracle per field."""
     import numpy as np
     import torch
 
@@ -194,11 +312,18 @@ def precision_form(sizes, steps, warmup=3):
     out = {}
     for N, ndim in sizes:
         w = W.dipole_workload(N, 0.75, ndim=ndim)
+        gold = oracle_sample("%dx%d" % (N, ndim))
         res = {}
         for dt_, name in ((NF.NF_F64, "f64"), (NF.NF_F32_REFINED, "f32_refined")):
-            m, r, S = T(w["m0"]), T(w["r"]), T(w["S"])
-            p = torch.zeros_like(r)
+            r, S = T(w["r"]), T(w["S"])
             with NF.Grid(w["n"], w["L"], dtype=dt_) as g:
+                err = None
+                if gold is not None:
+                    m, p = T(w["m0"]), torch.zeros_like(r)
+                    g.step(w["c2"], w["D2"], w["gamma"], w["dt"], m, p, r, S, rtol=w["rtol"])
+                    err = sampled_errors(gold, m.cpu().numpy(), p.cpu().numpy())
+                    del m, p
+                m, p = T(w["m0"]), torch.zeros_like(r)
                 g.run(w["c2"], w["D2"], w["gamma"], w["dt"], warmup, m, p, r, S, rtol=w["rtol"])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -206,7 +331,8 @@ def precision_form(sizes, steps, warmup=3):
                 torch.cuda.synchronize()
                 t = time.perf_counter() - t0
             res[name] = dict(ms_per_step=1e3 * t / steps, pcg_iters_per_step=info.total_cg_iters / steps,
-                             m=m.cpu().numpy(), p=p.cpu().numpy())
+                             m=m.cpu().numpy(), p=p.cpu().numpy(), err=err)
+            progress("precision %d^%d %s: %.3f ms per step, vs oracle %s" % (N, ndim, name, 1e3 * t / steps, err))
             del m, r, S, p
             torch.cuda.empty_cache()
         a, b = res["f32_refined"], res["f64"]
@@ -221,15 +347,20 @@ def precision_form(sizes, steps, warmup=3):
             "f32_inner_iters_per_step": a["pcg_iters_per_step"],
             "rel_diff_m": float(np.linalg.norm(a["m"] - b["m"]) / np.linalg.norm(b["m"])),
             "rel_diff_p": float(np.linalg.norm(a["p"] - b["p"]) / np.linalg.norm(b["p"])),
+            # one step from m0 against the FP64 oracle (relative L2 over 4096 sampled nodes per field)
+            "f64_vs_oracle": b["err"],
+            "f32_refined_vs_oracle": a["err"],
         }
-    return {"workload": "dipole case, gamma 0.75, PCG rtol 1e-10, %d steps after %d" % (steps, warmup),
+    return {"workload": "dipole case, gamma 0.75, PCG rtol 1e-10, %d steps after %d; vs_oracle: one step from m0 "
+                        "against the oracle's stored values at sampled nodes" % (steps, warmup),
             "sizes": out}
 
 
-def ensemble_cost(steps, mix=None):
+def ensemble_cost(steps, check_steps=20, mix=None):
     """The ensemble of independent instances (grid mix as given) advanced by one
-    batch (nf_batch_run) against the same instances run one after another
-    (nf_run), FP64 and FP32-refined, from the same states."""
+    batch (nf_batch_run), FP64 and FP32-refined: `steps` timed steps from m0,
+    and, over the first `check_steps` steps from m0, the batch against the same
+    instances run one after another (nf_run): rates and bitwise equality."""
     import numpy as np
     import torch
 
@@ -243,45 +374,60 @@ def ensemble_cost(steps, mix=None):
     prm = [(w["c2"], w["D2"], w["gamma"]) for w in inst]
     dt = W.ENSEMBLE_RUN["dt"]
     rtol = W.ENSEMBLE_RUN["rtol"]
-    out = {"workload": "%d instances %s, per-instance (c2, D2, gamma) draws, dt %g, rtol %g, %d steps after 2"
-                       % (len(inst), [list(x) for x in (mix or W.ENSEMBLE_MIX)], dt, rtol, steps)}
+    out = {"workload": "%d instances %s, per-instance (c2, D2, gamma) draws, dt %g, rtol %g; batch: %d steps from "
+                       "m0 after tuning; comparison with one-by-one runs: the first %d steps from m0"
+                       % (len(inst), [list(x) for x in (mix or W.ENSEMBLE_MIX)], dt, rtol, steps, check_steps)}
     rs = [T(w["r"]) for w in inst]
     Ss = [T(w["S"]) for w in inst]
     for dt_, name in ((NF.NF_F64, "f64"), (NF.NF_F32_REFINED, "f32_refined")):
-        ms = [T(w["m0"]) for w in inst]
-        ps = [torch.zeros_like(x) for x in rs]
         with NF.Batch([w["n"] for w in inst], dtype=dt_) as b:
+            ms = [T(w["m0"]) for w in inst]
+            ps = [torch.zeros_like(x) for x in rs]
             # the first run tunes the partition count (not timed)
             b.run(prm, dt, 2, ms, ps, rs, Ss, rtol=rtol)
             parts, tune_ms = b.partitions()
+            for i, w in enumerate(inst):
+                ms[i].copy_(T(w["m0"]))
+                ps[i].zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             infos = b.run(prm, dt, steps, ms, ps, rs, Ss, rtol=rtol)
             torch.cuda.synchronize()
             tb = time.perf_counter() - t0
+            finite = all(bool(torch.isfinite(x).all()) for x in ms)
+            del ms, ps
+            mc = [T(w["m0"]) for w in inst]
+            pc = [torch.zeros_like(x) for x in rs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(prm, dt, check_steps, mc, pc, rs, Ss, rtol=rtol)
+            torch.cuda.synchronize()
+            tbc = time.perf_counter() - t0
         ms2 = [T(w["m0"]) for w in inst]
         ps2 = [torch.zeros_like(x) for x in rs]
         gs = [NF.Grid(w["n"], dtype=dt_) for w in inst]
-        for i, g in enumerate(gs):
-            g.run(*prm[i], dt, 2, ms2[i], ps2[i], rs[i], Ss[i], rtol=rtol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, g in enumerate(gs):
-            g.run(*prm[i], dt, steps, ms2[i], ps2[i], rs[i], Ss[i], rtol=rtol)
+            g.run(*prm[i], dt, check_steps, ms2[i], ps2[i], rs[i], Ss[i], rtol=rtol)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         for g in gs:
             g.close()
+        progress("ensemble %s: batch %.3g grid-point-steps/s" % (name, npts * steps / tb))
         out[name] = {
             "batch_grid_point_steps_per_s": npts * steps / tb,
-            "one_by_one_grid_point_steps_per_s": npts * steps / ts,
-            "batch_speedup": ts / tb,
-            "bitwise_equal_to_one_by_one": all(torch.equal(a, c) for a, c in zip(ms, ms2)),
+            "batch_steps": steps,
+            "finite": finite,
             "pcg_iters_per_solve": sum(i.total_cg_iters for i in infos) / (len(inst) * steps),
+            "first_steps_batch_grid_point_steps_per_s": npts * check_steps / tbc,
+            "first_steps_one_by_one_grid_point_steps_per_s": npts * check_steps / ts,
+            "first_steps_batch_speedup": ts / tbc,
+            "first_steps_bitwise_equal_to_one_by_one": all(torch.equal(a, c) for a, c in zip(mc, ms2)),
             "partitions": parts,
             "tuning_ms_two_steps_by_partition_count": [round(t, 2) for t in tune_ms],
         }
-        del ms, ps, ms2, ps2
+        del mc, pc, ms2, ps2
         torch.cuda.empty_cache()
     return out
 
@@ -323,6 +469,11 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}), flush=True)
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,12 +481,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--kernel", default="row_flux", choices=sorted(KERNEL_IDS))
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the reverse-mode cost run (0 = skip)")
     ap.add_argument("--sequential", action="store_true", help="run the instances one after another on one stream")
-    ap.add_argument("--precision-steps", type=int, default=10, help="steps per form of the precision comparison (0 = skip)")
-    ap.add_argument("--ensemble-steps", type=int, default=20, help="steps of the ensemble comparison (0 = skip)")
+    ap.add_argument("--precision-steps", type=int, default=200, help="steps per form of the precision comparison (0 = skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=500, help="steps of the batched ensemble run (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--profile-case", default="", help="only run N:form:steps:ndim time steps (for kernel traces)")
     args = ap.parse_args()
@@ -351,6 +502,13 @@ def main():
         profile_case(args.profile_case)
         return
 
+    N = args.n
+    # the CPU baseline runs first, in worker processes started before anything
+    # touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(N, args.cpu_steps)
+    if cpu is not None:
+        progress("cpu baseline done: %.3g grid-point-steps/s on %d cores" % (cpu["value"], cpu["cores"]))
+
     import numpy as np
     import torch
 
@@ -358,7 +516,6 @@ def main():
     from paper_2606_06720_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    N = args.n
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     inst = []
     for gam in GAMMAS:
@@ -448,6 +605,20 @@ def main():
     }
     finite = all(torch.isfinite(it["m"]).all().item() for it in inst)
 
+    # context: the gamma = 0.75 instance alone on one stream over the same steps
+    solo = inst[1]
+    solo["m"].copy_(solo["m0"])
+    solo["p"].zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ws = solo["w"]
+    si = solo["g"].run(ws["c2"], ws["D2"], ws["gamma"], ws["dt"], args.steps, solo["m"], solo["p"], solo["r"],
+                       solo["S"], rtol=ws["rtol"], max_iter=1000)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    single = {"gamma": ws["gamma"], "grid_point_steps_per_s": N * N * args.steps / t_solo,
+              "ms_per_step": 1e3 * t_solo / args.steps, "pcg_iters_per_time_step": si.total_cg_iters / args.steps}
+
     out = {
         "metric": "grid-point-steps/s at 2D 1024^2 (PCG incl.)",
         "value": value,
@@ -469,18 +640,24 @@ def main():
             "instances": len(GAMMAS),
             "grid_points_per_step": total_points,
             "pcg_iters_per_time_step": cg_iters / (len(GAMMAS) * args.steps),
+            "grid_point_iters_per_s": N * N * cg_iters / elapsed,
             "finite": bool(finite),
         },
         "roofline": roofline,
+        "single_instance": single,
     }
+    progress("headline done: %.4g grid-point-steps/s, %.3f ms per step" % (value, 1e3 * elapsed / args.steps))
     if args.adjoint_steps > 0:
         out["adjoint_cost"] = adjoint_cost(N, args.adjoint_steps)
+        progress("adjoint block done")
     if args.precision_steps > 0:
         out["precision_form"] = precision_form(((N, 2), (4096, 2), (256, 3)), args.precision_steps)
+        progress("precision block done")
     if args.ensemble_steps > 0:
         out["ensemble"] = ensemble_cost(args.ensemble_steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
+        progress("ensemble block done")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     for it in inst:
         it["g"].close()
     print(json.dumps(out), flush=True)
