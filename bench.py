@@ -414,6 +414,12 @@ def ensemble_cost(steps, check_steps=20, mix=None):
         ts = time.perf_counter() - t0
         for g in gs:
             g.close()
+        # the tile variants the tuner chose for each grid shape (a handle of an
+        # already tuned shape reads them from the process-wide choice)
+        variants = {}
+        for N_, _ in (mix or W.ENSEMBLE_MIX):
+            with NF.Grid((N_, N_), dtype=dt_) as gq:
+                variants["%d^2" % N_] = gq.tuning()
         progress("ensemble %s: batch %.3g grid-point-steps/s" % (name, npts * steps / tb))
         out[name] = {
             "batch_grid_point_steps_per_s": npts * steps / tb,
@@ -426,6 +432,7 @@ def ensemble_cost(steps, check_steps=20, mix=None):
             "first_steps_bitwise_equal_to_one_by_one": all(torch.equal(a, c) for a, c in zip(mc, ms2)),
             "partitions": parts,
             "tuning_ms_two_steps_by_partition_count": [round(t, 2) for t in tune_ms],
+            "tile_variants": variants,
         }
         del mc, pc, ms2, ps2
         torch.cuda.empty_cache()
@@ -645,6 +652,8 @@ def main():
         },
         "roofline": roofline,
         "single_instance": single,
+        # tile variants of the PCG loop chosen by the tuner for the 1024^2 FP64 handles
+        "tile_variants": inst[0]["g"].tuning(),
     }
     progress("headline done: %.4g grid-point-steps/s, %.3f ms per step" % (value, 1e3 * elapsed / args.steps))
     if args.adjoint_steps > 0:

@@ -322,6 +322,49 @@ int nf_batch_partitions(const nf_batch *b, double *tune_ms);
 const char *nf_batch_last_error(const nf_batch *b);
 
 /*
+ * Tile tuning of the PCG loop (2D grids with a side of 256 to 4096, powers of
+ * two).  The three passes of a PCG iteration (operator middle: x transforms
+ * and the flux (m m^T + r I) grad p; operator end: y transform, divergence and
+ * the inner products; update) exist in several tile variants: rows per
+ * workgroup of the operator middle, columns per workgroup of the other two,
+ * and the order of the radix-8 and radix-4 stages of their transforms.  When
+ * autotuning is on (the default), the first nf_create_grid of a grid shape
+ * and precision in a process times every variant of each pass on the new
+ * handle's workspace and keeps the fastest (the default tile unless a variant
+ * is more than 3% faster); later handles, ensembles and allocation-free solves
+ * of that shape use the same choice, so their results agree bit for bit.
+ * The variants change the work split and the rounding of the transforms and
+ * inner products only.
+ * nf_set_autotune: 1 on, 0 off (default tiles for handles created afterwards);
+ *   NF_EINVAL otherwise.
+ * nf_tuning: the variants of a handle.  us / us_default: time per launch of the
+ *   chosen variant / the default tile measured by the tuner (0 if not tuned);
+ *   candidates: variants timed per pass.
+ */
+typedef struct {
+  int tuned;          /* 1 if the variants were set by the tuner */
+  int flux_rows;      /* operator middle: grid rows per workgroup */
+  int flux_plan;      /* 0: radix-8 stages first, 1: radix-4 stages first */
+  int div_cols;       /* operator end: spectral columns per workgroup */
+  int div_plan;
+  int update_cols;    /* update: spectral columns per workgroup */
+  int update_plan;
+  int candidates[3];  /* operator middle, operator end, update */
+  double us[3];
+  double us_default[3];
+} nf_tuning_info;
+int nf_set_autotune(int on);
+int nf_tuning(const nf_grid *g, nf_tuning_info *out);
+/*
+ * Fix the variants of one handle (2D), overriding the tuner: variant code v
+ * selects half (v % 3 == 0), the default (1) or twice (2) the default rows
+ * (operator middle) or columns (operator end, update) per workgroup, and the
+ * radix plan v / 3 (v in [0, 5]; 1 is the untuned pass, -1 keeps the current
+ * one).  NF_EINVAL if a variant does not exist for the grid and precision.
+ */
+int nf_set_tiles(nf_grid *g, int flux_var, int div_var, int update_var);
+
+/*
  * Kernel timing: nf_time_kernel(g, k) makes the PCG-loop kernel k (NF_KERNEL_*)
  * stamp, for every loop iteration, the start of its first and the end of its
  * last workgroup on the device wall clock; after each PCG loop the handle adds

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnf.so")
 
-SOURCES = ["nf_kernels.hip", "nf_kernels3d.hip", "nf_api.cpp", "nf_batch.cpp", "nf_noalloc.hip"]
+SOURCES = ["nf_kernels.hip", "nf_kernels3d.hip", "nf_api.cpp", "nf_batch.cpp", "nf_noalloc.hip", "nf_tune.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

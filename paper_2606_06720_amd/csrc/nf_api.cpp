@@ -380,7 +380,7 @@ int pcg(nf_grid* g, const double* m, const double* r, XSource src, const double*
     if (g->dim == 3)
       LCHK(g, launch3_copy_tot(G, SLOT_RR, 1, 11, s));
     else
-      LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, col_nwg(G), 11, s));
+      LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_RR), 1, rr_nwg(G, false), 11, s));
     rc = read_status(g, &fin);
     if (rc) return rc;
     fin.rr[0] = fin.out[11];
@@ -624,8 +624,16 @@ int nf_create_grid(nf_grid** out, int ndim, const int64_t n[3], const double L[3
   G.tot = g->part + (size_t)NSLOTS * SLOT_K * pstride;
   G.tclk = nullptr;
   G.tkind = -1;
+  for (int k = 0; k < 2; ++k) G.var_flux[k] = G.var_div[k] = G.var_upd[k] = VAR_DEFAULT;
   g->geo32 = G;
   g->geo32.tw = g->tw32;
+  // tile variants of the PCG loop for this grid shape (tuned once per process)
+  rc = nf::tune_handle(g);
+  if (rc != NF_OK) {
+    create_err = g->err;
+    nf_destroy_grid(g);
+    return rc;
+  }
   *out = g;
   return rc;
 }
@@ -851,6 +859,14 @@ int nf_pressure_solve_noalloc(const int64_t n[2], const double L[2], void* strea
   Gg.tot = g->part + (size_t)NSLOTS * SLOT_K * MAX_WG;
   Gg.tclk = nullptr;
   Gg.tkind = -1;
+  // the tile variants tuned for this shape by an earlier nf_create_grid, if any
+  int var[3] = {VAR_DEFAULT, VAR_DEFAULT, VAR_DEFAULT};
+  (void)nf::tune_lookup(g->device, g->nx, g->ny, false, var);
+  for (int k = 0; k < 2; ++k) {
+    Gg.var_flux[k] = var[0];
+    Gg.var_div[k] = var[1];
+    Gg.var_upd[k] = var[2];
+  }
   // the array keeps the previous call's contents: clear the partial sums (a
   // fill kernel, no memset node) before the solve resets the status
   int rc = check_launch(g, launch_zero_doubles(g->part, part_doubles, g->stream), "clear workspace");

@@ -325,7 +325,7 @@ int batch_solve(Part* b, bool first, double* const* p, double rtol, int max_iter
     if (rc) return rc;
     // final convergence test of solves stopped by max_iter, on the last residual
     for (auto& G : b->groups)
-      BCHK(b, launchb_sum_slot(G.t.sum_rr, (int)G.idx.size(), 1, col_nwg(G.shape), 11, s));
+      BCHK(b, launchb_sum_slot(G.t.sum_rr, (int)G.idx.size(), 1, rr_nwg(G.shape, false), 11, s));
     rc = read_all(b);
     if (rc) return rc;
     int mx = 0;

@@ -123,31 +123,38 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 
 // ---------------------------------------------------------------- radix plan
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
-// Radix of stage s for a length-2^p transform: 8s first, tails 4 or 4,4 or a lone 2.
+// Radices of a length-2^p transform: as many 8s as possible with a tail of 4,
+// 4,4 or a lone 2.  Plan 0 runs the 8s first, plan 1 the tail first (the two
+// differ when p is not a multiple of 3); the run-time tuner picks between them.
 constexpr int plan_nstages(int p) {
   return p <= 2 ? 1 : (p % 3 == 0 ? p / 3 : (p % 3 == 2 ? p / 3 + 1 : p / 3 + 1));
 }
-constexpr int plan_radix(int p, int s) {
+constexpr int plan_radix(int p, int s, int pl = 0) {
   if (p == 1) return 2;
   if (p == 2) return 4;
   if (p % 3 == 0) return 8;
-  if (p % 3 == 2) return s < p / 3 ? 8 : 4;
-  // p % 3 == 1: (p/3 - 1) eights then 4, 4
-  return s < p / 3 - 1 ? 8 : 4;
+  // number of tail stages: one 4 (p % 3 == 2) or two 4s (p % 3 == 1)
+  const int nt = p % 3 == 2 ? 1 : 2;
+  const int n8 = plan_nstages(p) - nt;
+  return pl == 0 ? (s < n8 ? 8 : 4) : (s < nt ? 4 : 8);
 }
-constexpr int plan_ns(int p, int s) {  // product of radices before stage s
-  return s == 0 ? 1 : plan_ns(p, s - 1) * plan_radix(p, s - 1);
+constexpr int plan_ns(int p, int s, int pl = 0) {  // product of radices before stage s
+  return s == 0 ? 1 : plan_ns(p, s - 1, pl) * plan_radix(p, s - 1, pl);
 }
+// whether plan 1 differs from plan 0 for a length-2^p transform
+constexpr bool plan_has_alt(int p) { return p > 2 && p % 3 != 0; }
 // Lengths n = 5^k 2^p: k radix-5 stages first, then the power-of-two plan above.
 constexpr int f5(int n) { return n % 5 == 0 ? 1 + f5(n / 5) : 0; }
 constexpr int pow5(int k) { return k == 0 ? 1 : 5 * pow5(k - 1); }
 constexpr int mplan_nstages(int n) {
   return f5(n) + (n / pow5(f5(n)) == 1 ? 0 : plan_nstages(ilog2(n / pow5(f5(n)))));
 }
-constexpr int mplan_radix(int n, int s) {
-  return s < f5(n) ? 5 : plan_radix(ilog2(n / pow5(f5(n))), s - f5(n));
+constexpr int mplan_radix(int n, int s, int pl = 0) {
+  return s < f5(n) ? 5 : plan_radix(ilog2(n / pow5(f5(n))), s - f5(n), pl);
 }
-constexpr int mplan_ns(int n, int s) { return s == 0 ? 1 : mplan_ns(n, s - 1) * mplan_radix(n, s - 1); }
+constexpr int mplan_ns(int n, int s, int pl = 0) {
+  return s == 0 ? 1 : mplan_ns(n, s - 1, pl) * mplan_radix(n, s - 1, pl);
+}
 constexpr bool plan_ok(int n) { return pow5(f5(n)) * (1 << ilog2(n / pow5(f5(n)))) == n; }
 
 // Twiddle e^{DIR 2 pi i t / M} from the table tw[u] = e^{-2 pi i u / TWN}, where
@@ -233,22 +240,23 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
   __syncthreads();
 }
 
-template <typename T, int DIR, int L, int B, int LS, int NT, int S>
+template <typename T, int DIR, int L, int B, int LS, int NT, int S, int PL>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
   static_assert(plan_ok(L), "transform lengths are 5^k 2^p");
   if constexpr (S < mplan_nstages(L)) {
     constexpr bool PAD = lpad_use(L) && LS >= lpad_len(L);
-    fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S), mplan_ns(L, S), PAD && (S > 0),
+    fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S, PL), mplan_ns(L, S, PL), PAD && (S > 0),
               PAD && (S + 1 < mplan_nstages(L))>(buf, tw, twn);
-    fft_stages<T, DIR, L, B, LS, NT, S + 1>(buf, tw, twn);
+    fft_stages<T, DIR, L, B, LS, NT, S + 1, PL>(buf, tw, twn);
   }
 }
 
-// In-LDS FFT of B lines of length L (line stride LS), all NT threads taking part.
+// In-LDS FFT of B lines of length L (line stride LS), all NT threads taking part,
+// with radix plan PL (see plan_radix).
 // Caller must __syncthreads() before (data written) -- the routine ends with a barrier.
-template <typename T, int DIR, int L, int B, int LS, int NT>
+template <typename T, int DIR, int L, int B, int LS, int NT, int PL = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
-  fft_stages<T, DIR, L, B, LS, NT, 0>(buf, tw, twn);
+  fft_stages<T, DIR, L, B, LS, NT, 0, PL>(buf, tw, twn);
 }
 
 // ------------------------------------------------- real <-> half-complex (x axis)

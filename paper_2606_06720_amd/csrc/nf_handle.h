@@ -53,4 +53,20 @@ struct nf_grid {
   double wall_khz = 0.0;                // device wall-clock ticks per ms
   double timed_ms = 0.0;
   int64_t timed_count = 0;
+  // tile variants of the PCG-loop passes (Geo::var_*): whether they came from
+  // the tuner, and for the operator middle, end and update the number of
+  // candidates timed, the chosen variant's and the default tile's time per launch
+  int tuned = 0;
+  int tune_ncand[3] = {1, 1, 1};
+  double tune_us[3] = {0.0, 0.0, 0.0};
+  double tune_us_default[3] = {0.0, 0.0, 0.0};
 };
+
+namespace nf {
+// Set the handle's tile variants for its grid shape and real type: from the
+// process-wide cache, else by timing the candidates on its buffers (2D grids
+// with tuned sizes, when autotuning is on); otherwise the default tiles.
+int tune_handle(nf_grid* g);
+// The cached variants (operator middle, end, update) of a shape, if any.
+bool tune_lookup(int device, int nx, int ny, bool f32, int var[3]);
+}  // namespace nf

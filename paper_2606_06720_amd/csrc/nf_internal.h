@@ -67,9 +67,17 @@ struct Geo {
   // tclk[2 (it TCLK_W + (block mod TCLK_W))]; the host reduces them
   unsigned long long* tclk;
   int tkind;
+  // tile variants of the PCG-loop passes chosen by the tuner (index 0: FP64
+  // passes, 1: FP32 passes; VAR_DEFAULT = 1 is the untuned tile): operator
+  // middle (row variant), operator end and update (column variants).  Read by
+  // the launchers only.
+  int var_flux[2], var_div[2], var_upd[2];
 };
 
-enum { TCLK_CAP = 2048, TCLK_W = 64 };  // timed iterations per PCG loop, stamp slots per iteration
+enum { TCLK_CAP = 2048, TCLK_W = 64 };
+// tile variants of the PCG-loop passes (codes 0 .. NVAR-1, see nf_tiles.hpp);
+// VAR_DEFAULT is the untuned tile
+enum { VAR_DEFAULT = 1, NVAR = 6 };  // timed iterations per PCG loop, stamp slots per iteration
 
 __host__ __device__ inline double* slot_ptr(double* part, int slot) {
   return part + (size_t)slot * SLOT_K * MAX_WG;
@@ -234,6 +242,22 @@ hipError_t launch_zero_spec(const Geo& g, void* xh, hipStream_t s);
 // row passes (physical <-> mixed)
 int row_nwg(const Geo& g);
 int col_nwg(const Geo& g);
+// workgroups of the row variant rv of the operator middle / column variant cv
+// of the operator end and update
+int row_nwg_var(const Geo& g, int rv);
+int col_nwg_var(const Geo& g, int cv);
+// whether a variant exists for the grid of g and the real type (f32) and can run
+bool flux_var_valid(const Geo& g, bool f32, int rv);
+bool div_var_valid(const Geo& g, bool f32, int cv);
+// partial sums of ||r||^2 written by the update of the PCG loop
+int rr_nwg(const Geo& g, bool f32);
+// rows per workgroup of row variant rv, columns per workgroup of column variant cv
+int flux_var_rows(const Geo& g, int rv);
+int div_var_cols(const Geo& g, int cv);
+// whether the grid sizes have tuned variants at all
+bool var_grid(const Geo& g);
+// fill n doubles with a value (a kernel, so that no memset node is recorded)
+hipError_t launch_fill_doubles(double* p, size_t n, double v, hipStream_t s);
 hipError_t launch_row_r2c(const Geo& g, const double* f, void* out_mixed, double* schk_slot, hipStream_t s);
 hipError_t launch_row_c2r(const Geo& g, const void* in_mixed, double* f, hipStream_t s);
 // e0/e1: optional start/stop events timestamped by the dispatch (nullptr = none)

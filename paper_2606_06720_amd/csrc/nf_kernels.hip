@@ -153,11 +153,11 @@ __global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_c2r(Geo g, const cd*
 // kernel's partials) <= tol2 * status.bb ends the solve at iteration it.
 // T is the arithmetic and storage type of the transforms and fields; the
 // reductions are FP64 in both instantiations.
-template <int NX, typename T>
+template <int NX, typename T, int RV>
 __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
                                                   const T* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2, float* lo) {
-  using C = Row2D<NX, 2>;
+  using C = FluxCfg<NX, RV>;
   using V = cx<T>;
   using P = typename vec2<T>::type;
   if (it >= 0 ? g.st->conv_at <= it : g.st->outer_done != 0) return;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   rowT_put<C>(buf, tv);
   __syncthreads();
   irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, +1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   // m and r are loaded only now: held across the transform they would cost
   // about 48 registers, and a workgroup with fewer registers shares a compute
   // unit more easily with the passes of concurrent solves
@@ -232,7 +232,7 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
     }
   }
   __syncthreads();
-  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, -1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<C, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
   if (kslot) {
@@ -241,16 +241,16 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   }
   tclk_end(g, 0, it);
 }
-template <int NX, typename T>
-__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
+template <int NX, typename T, int RV>
+__global__ void __launch_bounds__((FluxCfg<NX, RV>::NT)) k_row_flux(Geo g, cx<T>* G0, cx<T>* G1, const T* __restrict__ m,
                                                   const T* __restrict__ r, int it, double* kslot, int nwg_col,
                                                   double tol2, float* lo) {
-  row_flux_body<NX, T>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo);
+  row_flux_body<NX, T, RV>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo);
 }
-template <int NX, typename T>
-__global__ void __launch_bounds__((Row2D<NX, 2>::NT)) kb_row_flux(const FluxArgs* __restrict__ A, int it, int nwg_col, double tol2) {
+template <int NX, typename T, int RV>
+__global__ void __launch_bounds__((FluxCfg<NX, RV>::NT)) kb_row_flux(const FluxArgs* __restrict__ A, int it, int nwg_col, double tol2) {
   const FluxArgs& a = A[blockIdx.y];
-  row_flux_body<NX, T>(a.g, (cx<T>*)a.G0, (cx<T>*)a.G1, (const T*)a.m, (const T*)a.r, it, (double*)a.kslot, nwg_col, tol2, (float*)a.lo);
+  row_flux_body<NX, T, RV>(a.g, (cx<T>*)a.G0, (cx<T>*)a.G1, (const T*)a.m, (const T*)a.r, it, (double*)a.kslot, nwg_col, tol2, (float*)a.lo);
 }
 
 // Split update, pointwise part: p = F^-1 x_hat (written out), g = grad p,
@@ -615,9 +615,9 @@ __global__ void __launch_bounds__((Row2D<NX, 4>::NT)) k_row_adj2(Geo g, const cd
 // ================================================================ column kernels
 // Write the gradient multipliers i xi_c f_hat / n of one spectral value into
 // the two gradient lines of the column block.
-template <int NY, int NF, typename T>
+template <class C, typename T>
 __device__ __forceinline__ void put_grad(cx<T>* buf, int c, int ky, int kx, const cx<T> v, const Geo& g) {
-  using C = ColCfg<NY, NF>;
+  constexpr int NY = C::NYv;
   const T sx = (T)(xi_col(kx, g.lx) * g.inv_n), sy = (T)(xi_tilde(ky, NY, g.ly) * g.inv_n);
   buf[c * C::LS + ky] = mk<T>(-sx * v.y, sx * v.x);
   buf[(C::C + c) * C::LS + ky] = mk<T>(-sy * v.y, sy * v.x);
@@ -633,8 +633,8 @@ __device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   cd tv[C::ET];
-  colT_gload<NY, 2, 1>(tv, in, nullptr, kx0, g.h);
-  colT_put<NY, 2, 1>(buf, tv);
+  colT_gload<C, 1>(tv, in, nullptr, kx0, g.h);
+  colT_put<C, 1>(buf, tv);
   __syncthreads();
   lds_fft<double, -1, NY, C::C, C::LS, C::NT>(buf, tw, g.twn);
   cd v[C::EP];
@@ -652,11 +652,11 @@ __device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
-    if (p < C::CN) put_grad<NY, 2>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
+    if (p < C::CN) put_grad<C>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
   }
   __syncthreads();
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
 __global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
@@ -678,19 +678,19 @@ __device__ __forceinline__ void col_grad_body(Geo g, const cd* __restrict__ xh, 
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   cd v[C::EP];
-  colP_gload<NY, GRAD ? 2 : 1>(v, xh, kx0, g.h);
+  colP_gload<C>(v, xh, kx0, g.h);
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
     if (p < C::CN) {
-      if (GRAD) put_grad<NY, 2>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
+      if (GRAD) put_grad<C>(buf, p / NY, p % NY, kx0 + p / NY, v[i], g);
       else buf[(p / NY) * C::LS + p % NY] = scl(v[i], g.inv_n);
     }
   }
   __syncthreads();
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  if (GRAD) colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
-  else colT_store<NY, 1, 1>(buf, P, nullptr, kx0, g.h);
+  if (GRAD) colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
+  else colT_store<C, 1>(buf, P, nullptr, kx0, g.h);
 }
 template <int NY, bool GRAD>
 __global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
@@ -710,12 +710,13 @@ __global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) kb_col_grad(const ColGra
 // else: q_hat stored, partials <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>,
 //       <r,M^-1 r>, <r,r>.
 // INIT exists for T = double only (the residual of the refinement is FP64).
-template <int NY, bool INIT, typename T>
+template <int NY, bool INIT, typename T, int CV>
 __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx,
                                                  const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
                                                  const cx<T>* __restrict__ dh, cx<T>* rh,
                                                  const cx<T>* __restrict__ bh, int it, int nwg_row) {
-  using C = ColCfg<NY, 2>;
+  using C = DivCfg<NY, CV>;
+  static_assert(!INIT || CV == VAR_DEFAULT, "the INIT pass uses the default tile");
   using V = cx<T>;
   static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
   if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
@@ -726,7 +727,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   const V* tw = (const V*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   V tv[C::ET];
-  colT_gload<NY, 2, 2>(tv, Fx, Fy, kx0, g.h);
+  colT_gload<C, 2>(tv, Fx, Fy, kx0, g.h);
   if (INIT) {
     double kb[4], sc[2];
     sum_partials<C::NT, 4>(slot_ptr(g.part, SLOT_KBAR), nwg_row, MAX_WG, kb, red);
@@ -744,17 +745,17 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   } else if (threadIdx.x < 4) {
     Ks[threadIdx.x] = g.st->kbar[threadIdx.x];
   }
-  colT_put<NY, 2, 2>(buf, tv);
+  colT_put<C, 2>(buf, tv);
   __syncthreads();
-  lds_fft<T, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  lds_fft<T, -1, NY, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   // the vectors of the dot products are loaded after the transform (fewer
   // registers held across it)
   V av[C::EP], bv[C::EP];
   if (INIT) {
-    colP_gload<NY, 2>(av, bh, kx0, g.h);
+    colP_gload<C>(av, bh, kx0, g.h);
   } else {
-    colP_gload<NY, 2>(av, dh, kx0, g.h);
-    colP_gload<NY, 2>(bv, rh, kx0, g.h);
+    colP_gload<C>(av, dh, kx0, g.h);
+    colP_gload<C>(bv, rh, kx0, g.h);
   }
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -801,17 +802,17 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   write_partials<C::NT>(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
   if (!INIT) tclk_end(g, 1, it);
 }
-template <int NY, bool INIT, typename T>
+template <int NY, bool INIT, typename T, int CV>
 __global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
                                                  const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
                                                  const cx<T>* __restrict__ dh, cx<T>* rh,
                                                  const cx<T>* __restrict__ bh, int it, int nwg_row) {
-  col_div_body<NY, INIT, T>(g, Fx, Fy, qh, dh, rh, bh, it, nwg_row);
+  col_div_body<NY, INIT, T, CV>(g, Fx, Fy, qh, dh, rh, bh, it, nwg_row);
 }
-template <int NY, bool INIT, typename T>
+template <int NY, bool INIT, typename T, int CV>
 __global__ void __launch_bounds__(2 * TPF) kb_col_div(const DivArgs* __restrict__ A, int it, int nwg_row) {
   const DivArgs& a = A[blockIdx.y];
-  col_div_body<NY, INIT, T>(a.g, (const cx<T>*)a.Fx, (const cx<T>*)a.Fy, (cx<T>*)a.qh, (const cx<T>*)a.dh, (cx<T>*)a.rh, (const cx<T>*)a.bh, it, nwg_row);
+  col_div_body<NY, INIT, T, CV>(a.g, (const cx<T>*)a.Fx, (const cx<T>*)a.Fy, (cx<T>*)a.qh, (const cx<T>*)a.dh, (cx<T>*)a.rh, (const cx<T>*)a.bh, it, nwg_row);
 }
 
 // PCG scalar step + vector update + next direction + its gradient (mixed).
@@ -822,11 +823,11 @@ __global__ void __launch_bounds__(2 * TPF) kb_col_div(const DivArgs* __restrict_
 // new residual is taken by the next pass from its direct norm (SLOT_RR).
 // The scalars are FP64; the vector updates run in T.  `first` exists for
 // T = double only (the single-precision solve starts in k_col_refine_start).
-template <int NY, typename T>
+template <int NY, typename T, int CV>
 __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
                                                     const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
-  using C = ColCfg<NY, 2>;
+  using C = DivCfg<NY, CV>;
   using V = cx<T>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
@@ -842,11 +843,11 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
   // vectors of the block, loaded before the scalar reduction so that both
   // latencies overlap
   V xv[C::EP], rv0[C::EP], dv0[C::EP], qv[C::EP];
-  colP_gload<NY, 2>(rv0, rh, kx0, g.h);
+  colP_gload<C>(rv0, rh, kx0, g.h);
   if (!first) {
-    colP_gload<NY, 2>(xv, xh, kx0, g.h);
-    colP_gload<NY, 2>(dv0, dh, kx0, g.h);
-    colP_gload<NY, 2>(qv, qh, kx0, g.h);
+    colP_gload<C>(xv, xh, kx0, g.h);
+    colP_gload<C>(dv0, dh, kx0, g.h);
+    colP_gload<C>(qv, qh, kx0, g.h);
   }
   double alpha = 0.0, beta = 0.0;
   bool stop = false, zero_x = false;
@@ -922,7 +923,7 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
         }
       }
     }
-    if (!stop && p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, d, g);
+    if (!stop && p < C::CN) put_grad<C>(buf, c, ky, kx, d, g);
   }
   if (!first && !zero_x) {
     block_sum<C::NT, 1>(rrp, red);
@@ -933,20 +934,20 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
     return;
   }
   __syncthreads();
-  lds_fft<T, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  lds_fft<T, +1, NY, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
+  colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
   tclk_end(g, 2, tit);
 }
-template <int NY, typename T>
+template <int NY, typename T, int CV>
 __global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
                                                     const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
-  col_update_body<NY, T>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg_col);
+  col_update_body<NY, T, CV>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg_col);
 }
-template <int NY, typename T>
+template <int NY, typename T, int CV>
 __global__ void __launch_bounds__(2 * TPF) kb_col_update(const UpdArgs* __restrict__ A, int first, int it, int max_iter, double tol2, int nwg_col) {
   const UpdArgs& a = A[blockIdx.y];
-  col_update_body<NY, T>(a.g, first, (cx<T>*)a.xh, (cx<T>*)a.rh, (cx<T>*)a.dh, (const cx<T>*)a.qh, (cx<T>*)a.Gx, (cx<T>*)a.Gy, it, max_iter, tol2, nwg_col);
+  col_update_body<NY, T, CV>(a.g, first, (cx<T>*)a.xh, (cx<T>*)a.rh, (cx<T>*)a.dh, (const cx<T>*)a.qh, (cx<T>*)a.Gx, (cx<T>*)a.Gy, it, max_iter, tol2, nwg_col);
 }
 
 // Start of one correction of the mixed-precision solve (iterative refinement
@@ -982,7 +983,7 @@ __device__ __forceinline__ void col_refine_start_body(Geo g, const cd* __restric
   double K[4];
   for (int i = 0; i < 4; ++i) K[i] = st->kbar[i];
   cd rv[C::EP];
-  colP_gload<NY, 2>(rv, r64, kx0, g.h);
+  colP_gload<C>(rv, r64, kx0, g.h);
   double s[3];
   sum_partials<C::NT, 3>(slot_ptr(g.part, SLOT_P3INIT), nwg_col, MAX_WG, s, red);
   const double rho = s[0], rr = s[1], bb = s[2];
@@ -1045,11 +1046,11 @@ __device__ __forceinline__ void col_refine_start_body(Geo g, const cd* __restric
       d32[idx] = d;
       x32[idx] = vzero<V>();
     }
-    if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, d, g);
+    if (p < C::CN) put_grad<C>(buf, c, ky, kx, d, g);
   }
   __syncthreads();
   lds_fft<float, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
 __global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
@@ -1083,8 +1084,8 @@ __device__ __forceinline__ void col_refine_acc_body(Geo g, cd* x64, const cx<flo
   }
   cd xv[C::EP];
   cx<float> ev[C::EP];
-  colP_gload<NY, 2>(xv, x64, kx0, g.h);
-  colP_gload<NY, 2>(ev, x32, kx0, g.h);
+  colP_gload<C>(xv, x64, kx0, g.h);
+  colP_gload<C>(ev, x32, kx0, g.h);
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -1095,11 +1096,11 @@ __device__ __forceinline__ void col_refine_acc_body(Geo g, cd* x64, const cx<flo
       x = mk<double>(fma(sc, (double)ev[i].x, xv[i].x), fma(sc, (double)ev[i].y, xv[i].y));
       x64[(size_t)kx * NY + ky] = x;
     }
-    if (p < C::CN) put_grad<NY, 2>(buf, c, ky, kx, x, g);
+    if (p < C::CN) put_grad<C>(buf, c, ky, kx, x, g);
   }
   __syncthreads();
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  colT_store<NY, 2, 2>(buf, Gx, Gy, kx0, g.h);
+  colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
 __global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
@@ -1125,8 +1126,8 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
   const int kx0 = blockIdx.x * C::C;
   const double xnyq = TWO_PI * (g.nx / 2) / g.lx;  // full wavenumber of the kx = Nx/2 column
   cd tv[C::ET];
-  colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
-  colT_put<NY, 2, 2>(buf, tv);
+  colT_gload<C, 2>(tv, Mx, My, kx0, g.h);
+  colT_put<C, 2>(buf, tv);
   __syncthreads();
   lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[1] = {0.0};
@@ -1172,7 +1173,7 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
   }
   __syncthreads();
   lds_fft<double, +1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  colT_store<NY, 2, 2>(buf, Mx, My, kx0, g.h);
+  colT_store<C, 2>(buf, Mx, My, kx0, g.h);
   if (eslot) {
     block_sum<C::NT, 1>(s, red);
     write_partials<C::NT>(eslot, s, 1);
@@ -1198,8 +1199,8 @@ __global__ void __launch_bounds__(2 * TPF) k_col_divrhs(Geo g, const cd* __restr
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   cd tv[C::ET];
-  colT_gload<NY, 2, 2>(tv, V0, V1, kx0, g.h);
-  colT_put<NY, 2, 2>(buf, tv);
+  colT_gload<C, 2>(tv, V0, V1, kx0, g.h);
+  colT_put<C, 2>(buf, tv);
   __syncthreads();
   lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   for (int p = threadIdx.x; p < C::CN; p += C::NT) {
@@ -1229,8 +1230,8 @@ __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __res
   const cd* tw = (const cd*)g.tw;
   const int kx0 = blockIdx.x * C::C;
   cd tv[C::ET];
-  colT_gload<NY, 2, 2>(tv, Mx, My, kx0, g.h);
-  colT_put<NY, 2, 2>(buf, tv);
+  colT_gload<C, 2>(tv, Mx, My, kx0, g.h);
+  colT_put<C, 2>(buf, tv);
   __syncthreads();
   lds_fft<double, -1, NY, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   double s[1] = {0.0};
@@ -1279,7 +1280,10 @@ __global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __res
     else hipLaunchKernelGGL(K, GRID, BLK, 0, S, __VA_ARGS__);                      \
   } while (0)
 
-static int row_threads(int nx, int nf) { return row_tile(nx, nf) / 8 * nf; }
+static int row_threads(int nx, int nf) {
+  const int t = row_tile(nx, nf) / 8 * nf;
+  return t > 1024 ? 1024 : t;
+}
 static int row_nwg(const Geo& g, int nf) {
   const int R = tile_rows(g.nx / 2, row_tile(g.nx, nf));
   return (g.ny + R - 1) / R;
@@ -1294,6 +1298,191 @@ int col_nwg(const Geo& g) {
   const int C = col_cols(g.ny);
   return (g.h + C - 1) / C;
 }
+int row_nwg_var(const Geo& g, int rv) {
+  if (rv == VAR_DEFAULT) return row_nwg(g, 2);
+  const int R = rv_rows(g.nx, rv);
+  return (g.ny + R - 1) / R;
+}
+int col_nwg_var(const Geo& g, int cv) {
+  if (cv == VAR_DEFAULT) return col_nwg(g);
+  const int C = cv_cols(g.ny, cv);
+  return (g.h + C - 1) / C;
+}
+bool flux_var_valid(const Geo& g, bool f32, int rv) {
+  if (rv == VAR_DEFAULT) return true;
+  const int es = f32 ? 8 : 16;
+  return var_size(g.nx) && g.nz == 1 && rv_ok(g.nx, g.ny, rv, es);
+}
+bool div_var_valid(const Geo& g, bool f32, int cv) {
+  if (cv == VAR_DEFAULT) return true;
+  const int es = f32 ? 8 : 16;
+  return var_size(g.ny) && g.nz == 1 && cv_ok(g.ny, g.h, cv, es);
+}
+__global__ void k_fill_d(double* p, size_t n, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_doubles(double* p, size_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// Variant dispatch of the PCG-loop passes: a switch over the variant code that
+// instantiates only the variants that exist for the size and real type.
+template <int NX, typename T, int RV>
+static hipError_t flux_go(const Geo& g, cx<T>* G0, cx<T>* G1, const T* m, const T* r, int it, double* kslot,
+                          int nwg_col, double tol2, float* lo, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (flux_var_exists<NX, RV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(row_nwg_var(g, RV)), blk(FluxCfg<NX, RV>::NT);
+    NF_LAUNCH((k_row_flux<NX, T, RV>), grid, blk, s, e0, e1, g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NX, typename T>
+static hipError_t flux_var(int rv, const Geo& g, cx<T>* G0, cx<T>* G1, const T* m, const T* r, int it,
+                           double* kslot, int nwg_col, double tol2, float* lo, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1) {
+  switch (rv) {
+#define V_(K) \
+  case K: return flux_go<NX, T, K>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo, s, e0, e1);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NX, typename T, int RV>
+static hipError_t fluxb_go(const Geo& g, const FluxArgs* A, int count, int it, int nwg_col, double tol2,
+                           hipStream_t s) {
+  if constexpr (flux_var_exists<NX, RV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(row_nwg_var(g, RV), count), blk(FluxCfg<NX, RV>::NT);
+    hipLaunchKernelGGL((kb_row_flux<NX, T, RV>), grid, blk, 0, s, A, it, nwg_col, tol2);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NX, typename T>
+static hipError_t fluxb_var(int rv, const Geo& g, const FluxArgs* A, int count, int it, int nwg_col, double tol2,
+                            hipStream_t s) {
+  switch (rv) {
+#define V_(K) \
+  case K: return fluxb_go<NX, T, K>(g, A, count, it, nwg_col, tol2, s);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T, int CV>
+static hipError_t div_go(const Geo& g, const cx<T>* Fx, const cx<T>* Fy, cx<T>* qh, const cx<T>* dh, cx<T>* rh,
+                         int it, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(col_nwg_var(g, CV)), blk(2 * TPF);
+    NF_LAUNCH((k_col_div<NY, false, T, CV>), grid, blk, s, e0, e1, g, Fx, Fy, qh, dh, rh, (const cx<T>*)nullptr, it,
+              0);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T>
+static hipError_t div_var(int cv, const Geo& g, const cx<T>* Fx, const cx<T>* Fy, cx<T>* qh, const cx<T>* dh,
+                          cx<T>* rh, int it, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  switch (cv) {
+#define V_(K) \
+  case K: return div_go<NY, T, K>(g, Fx, Fy, qh, dh, rh, it, s, e0, e1);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T, int CV>
+static hipError_t divb_go(const Geo& g, const DivArgs* A, int count, int it, hipStream_t s) {
+  if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(col_nwg_var(g, CV), count), blk(2 * TPF);
+    hipLaunchKernelGGL((kb_col_div<NY, false, T, CV>), grid, blk, 0, s, A, it, 0);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T>
+static hipError_t divb_var(int cv, const Geo& g, const DivArgs* A, int count, int it, hipStream_t s) {
+  switch (cv) {
+#define V_(K) \
+  case K: return divb_go<NY, T, K>(g, A, count, it, s);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T, int CV>
+static hipError_t upd_go(const Geo& g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh, const cx<T>* qh, cx<T>* Gx,
+                         cx<T>* Gy, int it, int max_iter, double tol2, int nwg, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+  if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(col_nwg_var(g, CV)), blk(2 * TPF);
+    NF_LAUNCH((k_col_update<NY, T, CV>), grid, blk, s, e0, e1, g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2,
+              nwg);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T>
+static hipError_t upd_var(int cv, const Geo& g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh, const cx<T>* qh,
+                          cx<T>* Gx, cx<T>* Gy, int it, int max_iter, double tol2, int nwg, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
+  switch (cv) {
+#define V_(K) \
+  case K: return upd_go<NY, T, K>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg, s, e0, e1);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T, int CV>
+static hipError_t updb_go(const Geo& g, const UpdArgs* A, int count, int first, int it, int max_iter, double tol2,
+                          int nwg, hipStream_t s) {
+  if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
+    const dim3 grid(col_nwg_var(g, CV), count), blk(2 * TPF);
+    hipLaunchKernelGGL((kb_col_update<NY, T, CV>), grid, blk, 0, s, A, first, it, max_iter, tol2, nwg);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+template <int NY, typename T>
+static hipError_t updb_var(int cv, const Geo& g, const UpdArgs* A, int count, int first, int it, int max_iter,
+                           double tol2, int nwg, hipStream_t s) {
+  switch (cv) {
+#define V_(K) \
+  case K: return updb_go<NY, T, K>(g, A, count, first, it, max_iter, tol2, nwg, s);
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+#undef V_
+    default: return hipErrorInvalidValue;
+  }
+}
+// variant codes in use (a variant that cannot run on this grid falls back to the default)
+static int use_rv(const Geo& g, bool f32, int it) {
+  const int rv = it >= 0 ? g.var_flux[f32 ? 1 : 0] : VAR_DEFAULT;
+  return flux_var_valid(g, f32, rv) ? rv : VAR_DEFAULT;
+}
+static int use_cvd(const Geo& g, bool f32) {
+  const int cv = g.var_div[f32 ? 1 : 0];
+  return div_var_valid(g, f32, cv) ? cv : VAR_DEFAULT;
+}
+static int use_cvu(const Geo& g, bool f32) {
+  const int cv = g.var_upd[f32 ? 1 : 0];
+  return div_var_valid(g, f32, cv) ? cv : VAR_DEFAULT;
+}
+int rr_nwg(const Geo& g, bool f32) { return col_nwg_var(g, use_cvu(g, f32)); }
+int flux_var_rows(const Geo& g, int rv) {
+  return rv == VAR_DEFAULT ? tile_rows(g.nx / 2, row_tile(g.nx, 2)) : rv_rows(g.nx, rv);
+}
+int div_var_cols(const Geo& g, int cv) { return cv == VAR_DEFAULT ? col_cols(g.ny) : cv_cols(g.ny, cv); }
+bool var_grid(const Geo& g) { return g.nz == 1 && (var_size(g.nx) || var_size(g.ny)); }
 
 hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s) {
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, g.st, full);
@@ -1323,27 +1512,29 @@ hipError_t launch_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s
 #undef L_
   return hipGetLastError();
 }
+// The operator middle: the initial pass (it < 0, which may write the Kbar
+// partials read with the default workgroup count) uses the default tile, the
+// loop passes the tuned variant; the stopping test of the loop reads the
+// partials of the update's variant.
 hipError_t launch_row_flux(const Geo& g, void* G0, void* G1, const double* m, const double* r, int it,
                            double* kslot, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* lo) {
-  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
-  const int nwg_col = col_nwg(g);
-#define L_(N)                                                                                                    \
-  NF_LAUNCH((k_row_flux<N, double>), grid, blk, s, e0, e1, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2, \
-            lo)
+  const int rv = use_rv(g, false, it);
+  const int nwg_col = rr_nwg(g, false);
+#define L_(N) return flux_var<N, double>(rv, g, (cd*)G0, (cd*)G1, m, r, it, kslot, nwg_col, tol2, lo, s, e0, e1)
   NF_DISPATCH(g.nx, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32, const float* r32, int it,
                              double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const dim3 grid(row_nwg(g, 2)), blk(row_threads(g.nx, 2));
-  const int nwg_col = col_nwg(g);
-#define L_(N)                                                                                                     \
-  NF_LAUNCH((k_row_flux<N, float>), grid, blk, s, e0, e1, g, (cx<float>*)G0, (cx<float>*)G1, m32, r32, it,        \
-            (double*)nullptr, nwg_col, tol2, (float*)nullptr)
+  const int rv = use_rv(g, true, it);
+  const int nwg_col = rr_nwg(g, true);
+#define L_(N)                                                                                                  \
+  return flux_var<N, float>(rv, g, (cx<float>*)G0, (cx<float>*)G1, m32, r32, it, (double*)nullptr, nwg_col,    \
+                            tol2, (float*)nullptr, s, e0, e1)
   NF_DISPATCH(g.nx, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
@@ -1394,59 +1585,62 @@ hipError_t launch_col_grad(const Geo& g, const void* xh, void* P, void* Gx, void
   }
   return hipGetLastError();
 }
+// The operator end: the initial (INIT) pass uses the default tile, the loop
+// passes the tuned variant.
 hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy, void* qh, const void* dh,
                           void* rh, const void* bh, int it, int nwg_row, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
   if (init) {
-#define L_(N)                                                                                                 \
-  NF_LAUNCH((k_col_div<N, true, double>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,     \
-            (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
+    const dim3 grid(col_nwg(g)), blk(2 * TPF);
+#define L_(N)                                                                                                  \
+  NF_LAUNCH((k_col_div<N, true, double, VAR_DEFAULT>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy,  \
+            (cd*)qh, (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
-  } else {
-#define L_(N)                                                                                                 \
-  NF_LAUNCH((k_col_div<N, false, double>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh,    \
-            (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
-    NF_DISPATCH(g.ny, L_)
-#undef L_
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  const int cv = use_cvd(g, false);
+#define L_(N) \
+  return div_var<N, double>(cv, g, (const cd*)Fx, (const cd*)Fy, (cd*)qh, (const cd*)dh, (cd*)rh, it, s, e0, e1)
+  NF_DISPATCH(g.ny, L_)
+#undef L_
+  return hipErrorInvalidValue;
 }
 hipError_t launch_col_div32(const Geo& g, const void* Fx, const void* Fy, void* qh, const void* dh, void* rh, int it,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   typedef cx<float> cf;
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
-#define L_(N)                                                                                                 \
-  NF_LAUNCH((k_col_div<N, false, float>), grid, blk, s, e0, e1, g, (const cf*)Fx, (const cf*)Fy, (cf*)qh,     \
-            (const cf*)dh, (cf*)rh, (const cf*)nullptr, it, 0)
+  const int cv = use_cvd(g, true);
+#define L_(N) \
+  return div_var<N, float>(cv, g, (const cf*)Fx, (const cf*)Fy, (cf*)qh, (const cf*)dh, (cf*)rh, it, s, e0, e1)
   NF_DISPATCH(g.ny, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
+// The update: the first one reads the partials of the INIT pass (default
+// tile), the others those of the operator end's variant.
 hipError_t launch_col_update(const Geo& g, int first, void* xh, void* rh, void* dh, const void* qh, void* Gx,
                              void* Gy, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
-  const int nwg = col_nwg(g);
-#define L_(N)                                                                                                  \
-  NF_LAUNCH((k_col_update<N, double>), grid, blk, s, e0, e1, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, \
-            (cd*)Gx, (cd*)Gy, it, max_iter, tol2, nwg)
+  const int cv = use_cvu(g, false);
+  const int nwg = first ? col_nwg(g) : col_nwg_var(g, use_cvd(g, false));
+#define L_(N)                                                                                                    \
+  return upd_var<N, double>(cv, g, first, (cd*)xh, (cd*)rh, (cd*)dh, (const cd*)qh, (cd*)Gx, (cd*)Gy, it,        \
+                            max_iter, tol2, nwg, s, e0, e1)
   NF_DISPATCH(g.ny, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const void* qh, void* Gx, void* Gy, int it,
                                int max_iter, double tol2, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   typedef cx<float> cf;
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
-  const int nwg = col_nwg(g);
-#define L_(N)                                                                                                  \
-  NF_LAUNCH((k_col_update<N, float>), grid, blk, s, e0, e1, g, 0, (cf*)xh, (cf*)rh, (cf*)dh, (const cf*)qh,    \
-            (cf*)Gx, (cf*)Gy, it, max_iter, tol2, nwg)
+  const int cv = use_cvu(g, true);
+  const int nwg = col_nwg_var(g, use_cvd(g, true));
+#define L_(N)                                                                                                    \
+  return upd_var<N, float>(cv, g, 0, (cf*)xh, (cf*)rh, (cf*)dh, (const cf*)qh, (cf*)Gx, (cf*)Gy, it, max_iter,  \
+                           tol2, nwg, s, e0, e1)
   NF_DISPATCH(g.ny, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launch_col_refine_start(const Geo& g, const void* r64, void* x64, void* x32, void* r32, void* d32,
                                    void* Gx, void* Gy, double tol2, double floor_in, int max_iter, hipStream_t s) {
@@ -1521,51 +1715,54 @@ hipError_t launchb_col_grad(const Geo& g, const ColGradArgs* A, int count, bool 
 }
 hipError_t launchb_row_flux(const Geo& g, bool f32, const FluxArgs* A, int count, int it, double tol2,
                             hipStream_t s) {
-  const dim3 grid(row_nwg(g, 2), count), blk(row_threads(g.nx, 2));
-  const int nwg_col = col_nwg(g);
+  const int rv = use_rv(g, f32, it);
+  const int nwg_col = rr_nwg(g, f32);
   if (f32) {
-#define L_(N) hipLaunchKernelGGL((kb_row_flux<N, float>), grid, blk, 0, s, A, it, nwg_col, tol2)
+#define L_(N) return fluxb_var<N, float>(rv, g, A, count, it, nwg_col, tol2, s)
     NF_DISPATCH(g.nx, L_)
 #undef L_
   } else {
-#define L_(N) hipLaunchKernelGGL((kb_row_flux<N, double>), grid, blk, 0, s, A, it, nwg_col, tol2)
+#define L_(N) return fluxb_var<N, double>(rv, g, A, count, it, nwg_col, tol2, s)
     NF_DISPATCH(g.nx, L_)
 #undef L_
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launchb_col_div(const Geo& g, bool f32, bool init, const DivArgs* A, int count, int it, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
-  const int nwg_row = row_nwg(g);
   if (init) {
-#define L_(N) hipLaunchKernelGGL((kb_col_div<N, true, double>), grid, blk, 0, s, A, it, nwg_row)
+    const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+    const int nwg_row = row_nwg(g);
+#define L_(N) hipLaunchKernelGGL((kb_col_div<N, true, double, VAR_DEFAULT>), grid, blk, 0, s, A, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
 #undef L_
-  } else if (f32) {
-#define L_(N) hipLaunchKernelGGL((kb_col_div<N, false, float>), grid, blk, 0, s, A, it, nwg_row)
+    return hipGetLastError();
+  }
+  const int cv = use_cvd(g, f32);
+  if (f32) {
+#define L_(N) return divb_var<N, float>(cv, g, A, count, it, s)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   } else {
-#define L_(N) hipLaunchKernelGGL((kb_col_div<N, false, double>), grid, blk, 0, s, A, it, nwg_row)
+#define L_(N) return divb_var<N, double>(cv, g, A, count, it, s)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launchb_col_update(const Geo& g, bool f32, const UpdArgs* A, int count, int first, int it, int max_iter,
                               double tol2, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
-  const int nwg = col_nwg(g);
+  const int cv = use_cvu(g, f32);
+  const int nwg = (first && !f32) ? col_nwg(g) : col_nwg_var(g, use_cvd(g, f32));
   if (f32) {
-#define L_(N) hipLaunchKernelGGL((kb_col_update<N, float>), grid, blk, 0, s, A, 0, it, max_iter, tol2, nwg)
+#define L_(N) return updb_var<N, float>(cv, g, A, count, 0, it, max_iter, tol2, nwg, s)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   } else {
-#define L_(N) hipLaunchKernelGGL((kb_col_update<N, double>), grid, blk, 0, s, A, first, it, max_iter, tol2, nwg)
+#define L_(N) return updb_var<N, double>(cv, g, A, count, first, it, max_iter, tol2, nwg, s)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launchb_row_split(const Geo& g, const SplitArgs* A, int count, hipStream_t s) {
   const dim3 grid(row_nwg(g, 3), count), blk(row_threads(g.nx, 3));

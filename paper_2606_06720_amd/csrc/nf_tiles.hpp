@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "nf_fft.hpp"
 #include "nf_internal.h"
 
@@ -35,12 +37,15 @@ __host__ __device__ constexpr int tile_rows(int h, int t) { return t / h < 1 ? 1
 // passes over three and four fields keep TILE.
 __host__ __device__ constexpr int row_tile(int nx, int nf) { return (nf <= 2 && nx >= 4096) ? nx : TILE; }
 
-template <int NX, int NF, int RT = TILE>
+template <int NX, int NF, int RT = TILE, int PL = 0>
 struct RowCfg {
   static constexpr int H = NX / 2;
   static constexpr int R = tile_rows(H, RT);                    // rows per workgroup
   static constexpr int NFv = NF;
-  static constexpr int NT = (RT / 8) * NF;
+  static constexpr int PLAN = PL;                               // radix plan of the x transforms
+  // one radix-8 butterfly per thread, at most 1024 threads (wider tiles give
+  // each thread several butterflies per stage)
+  static constexpr int NT = (RT / 8) * NF > 1024 ? 1024 : (RT / 8) * NF;
   static constexpr int LS = lpad_use(H) ? lpad_len(H) + 1 : H + 2;  // LDS line stride (room for the FFT's padded layout)
   static constexpr int RH = R * H;                              // pairs per field in the block
   static constexpr int NB = NF * R;                             // LDS lines
@@ -51,10 +56,12 @@ struct RowCfg {
 template <int NX, int NF>
 using Row2D = RowCfg<NX, NF, row_tile(NX, NF)>;
 
-template <int NY, int NF>
+template <int NY, int NF, int CT = TILE, int PL = 0>
 struct ColCfg {
-  static constexpr int C0 = TILE / NY;
+  static constexpr int C0 = CT / NY;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
+  static constexpr int PLAN = PL;                               // radix plan of the y transforms
+  static constexpr int NYv = NY;
   static constexpr int NT = TPF * NF;
   static constexpr int LS = lpad_use(NY) ? lpad_len(NY) : NY;   // room for the FFT's padded layout
   static constexpr int CN = C * NY;                             // elements per field in the block
@@ -62,6 +69,64 @@ struct ColCfg {
   static constexpr int ET = (NF * CN + NT - 1) / NT;
   static constexpr int EP = (CN + NT - 1) / NT;
 };
+
+// ---------------------------------------------------------------- tuned variants
+// The PCG-loop passes (operator middle, operator end, update) come in variants
+// that a run-time tuner chooses between per grid shape and real type:
+//   row variant rv (operator middle): rows per workgroup RD/2, RD or 2 RD for
+//     rv % 3 = 0, 1, 2 (RD the default rows of Row2D<NX, 2>), radix plan rv / 3;
+//   column variant cv (operator end, update): columns per workgroup CD/2, CD or
+//     2 CD for cv % 3 = 0, 1, 2 (CD the default of ColCfg<NY, 2>), radix plan cv / 3.
+// Variant 1 (default tile, plan 0) is the untuned pass.  Variants that would
+// repeat another (a radix plan without an alternative), fall below one row or
+// column, or exceed the LDS of a workgroup do not exist.
+enum { LDS_LIMIT = 160 * 1024 };  // VAR_DEFAULT, NVAR: nf_internal.h
+
+__host__ __device__ constexpr int rv_rows(int nx, int rv) {
+  const int rd = tile_rows(nx / 2, row_tile(nx, 2));
+  return rv % 3 == 0 ? rd / 2 : (rv % 3 == 1 ? rd : 2 * rd);
+}
+__host__ __device__ constexpr int cv_cols_default(int ny) {
+  return TILE / ny < 1 ? 1 : (TILE / ny > 64 ? 64 : TILE / ny);
+}
+__host__ __device__ constexpr int cv_cols(int ny, int cv) {
+  return cv % 3 == 0 ? cv_cols_default(ny) / 2 : (cv % 3 == 1 ? cv_cols_default(ny) : 2 * cv_cols_default(ny));
+}
+// LDS bytes of the operator-middle and operator-end passes for element size es
+__host__ __device__ constexpr int flux_lds(int nx, int rows, int es) {
+  return 2 * rows * ((lpad_use(nx / 2) ? lpad_len(nx / 2) + 1 : nx / 2 + 2) * es);
+}
+__host__ __device__ constexpr int div_lds(int ny, int cols, int es) {
+  return 2 * cols * ((lpad_use(ny) ? lpad_len(ny) : ny) * es);
+}
+__host__ __device__ constexpr bool rv_ok(int nx, int ny, int rv, int es) {
+  return rv >= 0 && rv < NVAR && (rv / 3 == 0 || plan_has_alt(ilog2(nx / 2))) && rv_rows(nx, rv) >= 1 &&
+         rv_rows(nx, rv) <= 64 && (rv % 3 != 2 || rv_rows(nx, rv) <= ny) &&
+         flux_lds(nx, rv_rows(nx, rv), es) + 4096 <= LDS_LIMIT;
+}
+__host__ __device__ constexpr bool cv_ok(int ny, int h, int cv, int es) {
+  return cv >= 0 && cv < NVAR && (cv / 3 == 0 || plan_has_alt(ilog2(ny))) && cv_cols(ny, cv) >= 1 &&
+         cv_cols(ny, cv) <= 64 && (cv % 3 != 2 || cv_cols(ny, cv) <= h) &&
+         div_lds(ny, cv_cols(ny, cv), es) + 4096 <= LDS_LIMIT;
+}
+// grid sizes that have tuned variants (every size has the default)
+__host__ __device__ constexpr bool var_size(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
+// configurations of the variants (the default is exactly the untuned tile)
+template <int NX, int RV>
+using FluxCfg = typename std::conditional<RV == VAR_DEFAULT, Row2D<NX, 2>,
+                                          RowCfg<NX, 2, rv_rows(NX, RV) * (NX / 2), RV / 3>>::type;
+template <int NY, int CV>
+using DivCfg = typename std::conditional<CV == VAR_DEFAULT, ColCfg<NY, 2>,
+                                         ColCfg<NY, 2, cv_cols(NY, CV) * NY, CV / 3>>::type;
+// variants that can be built for a size (the row count against Ny is checked at run time)
+template <int NX, int RV, int ES>
+constexpr bool flux_var_exists() {
+  return RV == VAR_DEFAULT || (var_size(NX) && rv_ok(NX, 1 << 20, RV, ES));
+}
+template <int NY, int CV, int ES>
+constexpr bool div_var_exists() {
+  return CV == VAR_DEFAULT || (var_size(NY) && cv_ok(NY, 1 << 20, CV, ES));
+}
 
 // first-derivative wavenumber (Nyquist zeroed) and full wavenumber
 __device__ __forceinline__ double xi_tilde(int k, int n, double L) {
@@ -167,9 +232,10 @@ __device__ __forceinline__ void rowP_gload(P (&v)[(C::EP)], const S* __restrict_
 }
 
 // ---------------------------------------------------------------- column images
-template <int NY, int NF, int NFL, typename V>
-__device__ __forceinline__ void colT_gload(V (&v)[(ColCfg<NY, NF>::ET)], const V* s0, const same<V>* s1, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
+// C is a ColCfg: C::NYv lines of C::C columns per field.
+template <class C, int NFL, typename V>
+__device__ __forceinline__ void colT_gload(V (&v)[(C::ET)], const V* s0, const same<V>* s1, int kx0, int h) {
+  constexpr int NY = C::NYv;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -178,9 +244,9 @@ __device__ __forceinline__ void colT_gload(V (&v)[(ColCfg<NY, NF>::ET)], const V
     v[i] = (e < NFL * C::CN && kx0 + c < h) ? (f == 0 ? s0 : s1)[(size_t)(kx0 + c) * NY + ky] : vzero<V>();
   }
 }
-template <int NY, int NF, int NFL, typename V>
-__device__ __forceinline__ void colT_put(V* buf, const V (&v)[(ColCfg<NY, NF>::ET)]) {
-  using C = ColCfg<NY, NF>;
+template <class C, int NFL, typename V>
+__device__ __forceinline__ void colT_put(V* buf, const V (&v)[(C::ET)]) {
+  constexpr int NY = C::NYv;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -188,9 +254,9 @@ __device__ __forceinline__ void colT_put(V* buf, const V (&v)[(ColCfg<NY, NF>::E
     if (e < NFL * C::CN) buf[(f * C::C + ee / NY) * C::LS + ee % NY] = v[i];
   }
 }
-template <int NY, int NF, int NFS, typename V>
+template <class C, int NFS, typename V>
 __device__ __forceinline__ void colT_store(const V* buf, same<V>* d0, same<V>* d1, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
+  constexpr int NY = C::NYv;
   for (int e = threadIdx.x; e < NFS * C::CN; e += C::NT) {
     const int f = e / C::CN, ee = e % C::CN;
     const int c = ee / NY, ky = ee % NY;
@@ -198,9 +264,9 @@ __device__ __forceinline__ void colT_store(const V* buf, same<V>* d0, same<V>* d
   }
 }
 // pointwise image of one field: p -> column p / NY, row p % NY
-template <int NY, int NF, typename V>
-__device__ __forceinline__ void colP_gload(V (&v)[(ColCfg<NY, NF>::EP)], const V* __restrict__ src, int kx0, int h) {
-  using C = ColCfg<NY, NF>;
+template <class C, typename V>
+__device__ __forceinline__ void colP_gload(V (&v)[(C::EP)], const V* __restrict__ src, int kx0, int h) {
+  constexpr int NY = C::NYv;
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;

@@ -1,0 +1,257 @@
+// Run-time tuner of the tile variants of the PCG-loop passes (2D grids).
+//
+// For a grid shape and the real type of its inner solve, every variant of the
+// operator middle (rows per workgroup, radix plan of the x transforms) and of
+// the operator end and update (columns per workgroup, radix plan of the y
+// transforms) that exists for the shape is timed on the new handle's own
+// buffers, and the fastest of each pass is kept.  The default tile stays unless
+// a variant is more than 3% faster.  The choice is made once per process for
+// each (Nx, Ny, real type) and cached, so every handle, ensemble and
+// allocation-free solve of that shape runs the same kernels (their results then
+// agree bit for bit).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "nf.h"
+#include "nf_handle.h"
+#include "nf_internal.h"
+
+namespace nf {
+
+namespace {
+
+struct Choice {
+  int var[3] = {VAR_DEFAULT, VAR_DEFAULT, VAR_DEFAULT};  // flux, div, update
+  int ncand[3] = {1, 1, 1};
+  double us[3] = {0.0, 0.0, 0.0};
+  double us_default[3] = {0.0, 0.0, 0.0};
+};
+
+std::mutex cache_mu;
+std::map<std::tuple<int, int, int, int>, Choice> cache;  // (device, nx, ny, f32)
+int autotune_on = 1;
+
+void apply(nf_grid* g, bool f32, const Choice& c, int tuned) {
+  const int k = f32 ? 1 : 0;
+  for (Geo* G : {&g->geo, &g->geo32}) {
+    G->var_flux[k] = c.var[0];
+    G->var_div[k] = c.var[1];
+    G->var_upd[k] = c.var[2];
+  }
+  g->tuned = tuned;
+  for (int i = 0; i < 3; ++i) {
+    g->tune_ncand[i] = c.ncand[i];
+    g->tune_us[i] = c.us[i];
+    g->tune_us_default[i] = c.us_default[i];
+  }
+}
+
+// Time `reps` launches of one pass (after two untimed ones); milliseconds per launch.
+template <class F>
+hipError_t time_pass(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F&& launch, double* ms) {
+  hipError_t e;
+  for (int i = 0; i < 2; ++i)
+    if ((e = launch()) != hipSuccess) return e;
+  const int reps = 5;
+  if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  for (int i = 0; i < reps; ++i)
+    if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+  float t = 0.0f;
+  if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+  *ms = (double)t / reps;
+  return hipSuccess;
+}
+
+hipError_t run_tuning(nf_grid* g, bool f32, Choice* out) {
+  Geo& G = f32 ? g->geo32 : g->geo;
+  const int k = f32 ? 1 : 0;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny;
+  hipError_t e = hipSuccess;
+  // stand-ins for m and r (the passes' timing does not depend on the values)
+  void* mr = nullptr;
+  if (f32) {
+    mr = g->lo;
+  } else if ((e = hipMalloc(&mr, 3 * n * sizeof(double))) != hipSuccess) {
+    return e;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!f32 && mr) (void)hipFree(mr);
+  };
+#define TCHK(expr)             \
+  do {                         \
+    if ((e = (expr)) != hipSuccess) { \
+      cleanup();               \
+      return e;                \
+    }                          \
+  } while (0)
+  TCHK(hipEventCreate(&e0));
+  TCHK(hipEventCreate(&e1));
+  // a running solver state for the loop passes: no stop recorded, and partial
+  // sums of the operator end that give finite, non-stopping PCG scalars
+  TCHK(launch_status_reset(G, 1, s));
+  TCHK(launch_fill_doubles(slot_ptr(g->part, SLOT_P3), (size_t)SLOT_K * MAX_WG, 1.0, s));
+  void* M0 = f32 ? g->mix32[0] : g->mix[0];
+  void* M1 = f32 ? g->mix32[1] : g->mix[1];
+  void* X = f32 ? g->x32 : g->xh;
+  void* R = f32 ? g->r32 : g->rh;
+  void* D = f32 ? g->d32 : g->dh;
+  void* Q = f32 ? g->q32 : g->qh;
+  for (int pass = 0; pass < 3; ++pass) {
+    double best[NVAR];
+    for (int v = 0; v < NVAR; ++v) best[v] = -1.0;
+    int nc = 0;
+    for (int round = 0; round < 2; ++round) {
+      for (int v = 0; v < NVAR; ++v) {
+        const bool ok = pass == 0 ? flux_var_valid(G, f32, v) : div_var_valid(G, f32, v);
+        if (!ok) continue;
+        if (round == 0) ++nc;
+        double ms = 0.0;
+        if (pass == 0) {
+          G.var_flux[k] = v;
+          TCHK(time_pass(s, e0, e1, [&]() {
+            return f32 ? launch_row_flux32(G, M0, M1, (const float*)mr, (const float*)mr + 2 * n, 0, 0.0, s)
+                       : launch_row_flux(G, M0, M1, (const double*)mr, (const double*)mr + 2 * n, 0, nullptr, 0.0, s);
+          }, &ms));
+        } else if (pass == 1) {
+          G.var_div[k] = v;
+          TCHK(time_pass(s, e0, e1, [&]() {
+            return f32 ? launch_col_div32(G, M0, M1, Q, D, R, 0, s)
+                       : launch_col_div(G, 0, M0, M1, Q, D, R, g->bh, 0, 0, s);
+          }, &ms));
+        } else {
+          G.var_upd[k] = v;
+          TCHK(time_pass(s, e0, e1, [&]() {
+            return f32 ? launch_col_update32(G, X, R, D, Q, M0, M1, 1, INT_MAX, 0.0, s)
+                       : launch_col_update(G, 0, X, R, D, Q, M0, M1, 1, INT_MAX, 0.0, s);
+          }, &ms));
+        }
+        if (best[v] < 0.0 || ms < best[v]) best[v] = ms;
+      }
+    }
+    // the fastest overall, kept only if it beats the default by more than 3%
+    // (smaller differences are within the run-to-run spread of the timing)
+    double bmin = best[VAR_DEFAULT];
+    int arg = VAR_DEFAULT;
+    for (int v = 0; v < NVAR; ++v)
+      if (best[v] >= 0.0 && best[v] < bmin) {
+        bmin = best[v];
+        arg = v;
+      }
+    const int pick = bmin < 0.97 * best[VAR_DEFAULT] ? arg : VAR_DEFAULT;
+    out->var[pass] = pick;
+    out->ncand[pass] = nc;
+    out->us[pass] = 1e3 * best[pick];
+    out->us_default[pass] = 1e3 * best[VAR_DEFAULT];
+    if (pass == 0) G.var_flux[k] = pick;
+    if (pass == 1) G.var_div[k] = pick;
+    if (pass == 2) G.var_upd[k] = pick;
+  }
+  // leave the handle as a fresh one: status, partial sums and iterate cleared
+  TCHK(launch_status_reset(G, 1, s));
+  TCHK(launch_zero_doubles(g->part, (size_t)NSLOTS * SLOT_K * MAX_WG, s));
+  TCHK(launch_zero_spec(g->geo, g->xh, s));
+  TCHK(hipStreamSynchronize(s));
+#undef TCHK
+  cleanup();
+  return hipSuccess;
+}
+
+}  // namespace
+
+int tune_handle(nf_grid* g) {
+  const bool f32 = g->dtype == NF_F32_REFINED;
+  Choice c;
+  std::lock_guard<std::mutex> lock(cache_mu);
+  if (g->dim != 2 || !autotune_on || !var_grid(g->geo)) {
+    apply(g, f32, c, 0);
+    return NF_OK;
+  }
+  const auto key = std::make_tuple(g->device, g->nx, g->ny, f32 ? 1 : 0);
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    apply(g, f32, it->second, 1);
+    return NF_OK;
+  }
+  hipError_t e = run_tuning(g, f32, &c);
+  if (e != hipSuccess) {
+    g->err = std::string("tile tuning: ") + hipGetErrorString(e);
+    return NF_EDEVICE;
+  }
+  cache[key] = c;
+  apply(g, f32, c, 1);
+  return NF_OK;
+}
+
+bool tune_lookup(int device, int nx, int ny, bool f32, int var[3]) {
+  std::lock_guard<std::mutex> lock(cache_mu);
+  if (!autotune_on) return false;
+  auto it = cache.find(std::make_tuple(device, nx, ny, f32 ? 1 : 0));
+  if (it == cache.end()) return false;
+  for (int i = 0; i < 3; ++i) var[i] = it->second.var[i];
+  return true;
+}
+
+}  // namespace nf
+
+extern "C" {
+
+int nf_set_autotune(int on) {
+  if (on != 0 && on != 1) return NF_EINVAL;
+  std::lock_guard<std::mutex> lock(nf::cache_mu);
+  nf::autotune_on = on;
+  return NF_OK;
+}
+
+int nf_set_tiles(nf_grid* g, int flux_var, int div_var, int update_var) {
+  if (!g) return NF_EINVAL;
+  if (g->dim != 2) return NF_EINVAL;
+  const bool f32 = g->dtype == NF_F32_REFINED;
+  const int k = f32 ? 1 : 0;
+  nf::Geo& G = f32 ? g->geo32 : g->geo;
+  const int v[3] = {flux_var < 0 ? G.var_flux[k] : flux_var, div_var < 0 ? G.var_div[k] : div_var,
+                    update_var < 0 ? G.var_upd[k] : update_var};
+  if (!nf::flux_var_valid(G, f32, v[0]) || !nf::div_var_valid(G, f32, v[1]) || !nf::div_var_valid(G, f32, v[2])) {
+    g->err = "tile variant does not exist for this grid and precision";
+    return NF_EINVAL;
+  }
+  for (nf::Geo* H : {&g->geo, &g->geo32}) {
+    H->var_flux[k] = v[0];
+    H->var_div[k] = v[1];
+    H->var_upd[k] = v[2];
+  }
+  g->tuned = 0;
+  return NF_OK;
+}
+
+int nf_tuning(const nf_grid* g, nf_tuning_info* out) {
+  if (!g || !out) return NF_EINVAL;
+  const bool f32 = g->dtype == NF_F32_REFINED;
+  const nf::Geo& G = f32 ? g->geo32 : g->geo;
+  const int k = f32 ? 1 : 0;
+  const int vf = G.var_flux[k], vd = G.var_div[k], vu = G.var_upd[k];
+  out->tuned = g->tuned;
+  out->flux_rows = nf::flux_var_rows(G, vf);
+  out->flux_plan = vf / 3;
+  out->div_cols = nf::div_var_cols(G, vd);
+  out->div_plan = vd / 3;
+  out->update_cols = nf::div_var_cols(G, vu);
+  out->update_plan = vu / 3;
+  for (int i = 0; i < 3; ++i) {
+    out->candidates[i] = g->tune_ncand[i];
+    out->us[i] = g->tune_us[i];
+    out->us_default[i] = g->tune_us_default[i];
+  }
+  return NF_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,13 @@ class nf_run_info(ctypes.Structure):
                 ("total_cg_iters", ctypes.c_int64), ("unconverged_solves", ctypes.c_int64)]
 
 
+class nf_tuning_info(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int), ("flux_rows", ctypes.c_int), ("flux_plan", ctypes.c_int),
+                ("div_cols", ctypes.c_int), ("div_plan", ctypes.c_int), ("update_cols", ctypes.c_int),
+                ("update_plan", ctypes.c_int), ("candidates", ctypes.c_int * 3), ("us", ctypes.c_double * 3),
+                ("us_default", ctypes.c_double * 3)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libnf.so is not built (run __graft_entry__.build()): " + LIB_PATH)
@@ -98,6 +105,9 @@ def _load():
     lib.nf_transform_inverse.argtypes = [vp, vp, vp]
     lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
     lib.nf_set_inner_tolerance.argtypes = [vp, dp]
+    lib.nf_set_autotune.argtypes = [ctypes.c_int]
+    lib.nf_tuning.argtypes = [vp, ctypes.POINTER(nf_tuning_info)]
+    lib.nf_set_tiles.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.nf_time_kernel.argtypes = [vp, ctypes.c_int]
     lib.nf_time_kernel_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.nf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_double),
@@ -118,7 +128,8 @@ def _load():
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_pressure_solve_noalloc",
               "nf_step", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
-              "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_batch_create", "nf_batch_destroy",
+              "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_set_autotune", "nf_tuning", "nf_set_tiles",
+              "nf_batch_create", "nf_batch_destroy",
               "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions",
               "nf_batch_set_graphs"):
         getattr(lib, f).restype = ctypes.c_int
@@ -295,6 +306,18 @@ class Grid:
 
 
     # diagnostics -----------------------------------------------------------
+    def tuning(self):
+        """nf_tuning: the tile variants of the PCG loop of this handle, as a dict."""
+        t = nf_tuning_info()
+        self._check(_lib.nf_tuning(self._h, ctypes.byref(t)))
+        return {"tuned": bool(t.tuned), "flux_rows": t.flux_rows, "flux_plan": t.flux_plan, "div_cols": t.div_cols,
+                "div_plan": t.div_plan, "update_cols": t.update_cols, "update_plan": t.update_plan,
+                "candidates": list(t.candidates), "us": list(t.us), "us_default": list(t.us_default)}
+
+    def set_tiles(self, flux_var=-1, div_var=-1, update_var=-1):
+        """nf_set_tiles: fix this handle's tile variants (codes 0..5, -1 keeps)."""
+        self._check(_lib.nf_set_tiles(self._h, int(flux_var), int(div_var), int(update_var)))
+
     def set_inner_tolerance(self, floor_rtol):
         self._check(_lib.nf_set_inner_tolerance(self._h, float(floor_rtol)))
 
@@ -465,6 +488,21 @@ def nf_energy(g, c2, D2, gamma, m, r, S, p=None):
 def nf_step_adjoint(g, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol=1e-12,
                     max_iter=2000):
     return g.step_adjoint(c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol, max_iter)
+
+
+def nf_set_autotune(on):
+    """Process-wide: tune the tile variants at the first nf_create_grid of a shape (1) or not (0)."""
+    rc = _lib.nf_set_autotune(int(on))
+    if rc != NF_OK:
+        raise NfError(rc, "nf_set_autotune: on must be 0 or 1")
+
+
+def nf_tuning(g):
+    return g.tuning()
+
+
+def nf_set_tiles(g, flux_var=-1, div_var=-1, update_var=-1):
+    return g.set_tiles(flux_var, div_var, update_var)
 
 
 def nf_set_inner_tolerance(g, floor_rtol):

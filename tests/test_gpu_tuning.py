@@ -1,0 +1,110 @@
+"""Tile variants of the PCG loop and their run-time tuner.
+
+Every variant that exists for a grid (rows per workgroup of the operator
+middle, columns per workgroup of the operator end and of the update, and the
+radix plan of each) is fixed on a handle in turn and the pressure solve is
+compared with the oracle at 1e-10 relative L2, for FP64 and FP32-refined
+handles.  The tuner's record is checked (it times every candidate, keeps the
+default unless a variant is faster) and handles of one shape share the choice,
+so that their results agree bit for bit."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+TOL = 1e-10
+
+SHAPES = [((256, 256), (1.0, 1.0)), ((512, 1024), (1.0, 2.0)), ((4096, 32), (1.0, 1.0 / 128)),
+          ((1024, 256), (2.0, 0.5))]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2606_06720_amd import nf as NF
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Z = lambda shape: torch.zeros(shape, dtype=torch.float64, device=dev)
+    return NF, T, Z, torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def fields(n, seed):
+    rng = np.random.default_rng(seed)
+    shape = n[::-1]
+    m = rng.uniform(-1.0, 1.0, (2,) + shape)
+    r = rng.uniform(0.05, 0.15, shape)
+    S = rng.standard_normal(shape)
+    S -= S.mean()
+    return m, r, S
+
+
+@pytest.mark.parametrize("n,L", SHAPES)
+def test_every_tile_variant_matches_oracle(env, n, L):
+    NF, T, Z, torch = env
+    m, r, S = fields(n, 31)
+    p_or, info_or = O.pressure_pcg(m, r, S, None, 1e-12, 4000, L)
+    for dtype in (NF.NF_F64, NF.NF_F32_REFINED):
+        ran = 0
+        with NF.Grid(n, L, dtype=dtype) as g:
+            for which in range(3):
+                for v in range(6):
+                    codes = [1, 1, 1]
+                    codes[which] = v
+                    try:
+                        g.set_tiles(*codes)
+                    except NF.NfError as e:
+                        assert e.code == NF.NF_EINVAL
+                        continue
+                    print("variant", n, dtype, which, v, flush=True)
+                    p = Z(n[::-1])
+                    rc, info = g.pressure_solve(T(m), T(r), T(S), p, rtol=1e-12, max_iter=4000)
+                    assert info.converged
+                    if dtype == NF.NF_F64:
+                        assert abs(info.iters - info_or.iters) <= 1
+                    assert rel(p.cpu().numpy(), p_or) <= TOL, (which, v)
+                    ran += 1
+        # the default of each pass plus at least one alternative somewhere
+        assert ran >= 4
+
+
+def test_tuner_record_and_shared_choice(env):
+    NF, T, Z, torch = env
+    n, L = (1024, 1024), (1.0, 1.0)
+    m, r, S = fields(n, 37)
+    outs = []
+    for _ in range(2):
+        with NF.Grid(n, L) as g:
+            t = g.tuning()
+            p = Z(n[::-1])
+            g.pressure_solve(T(m), T(r), T(S), p, rtol=1e-10)
+            outs.append((t, p))
+    t0, t1 = outs[0][0], outs[1][0]
+    assert t0["tuned"] and t1["tuned"]
+    assert all(c >= 2 for c in t0["candidates"])
+    for a, b in zip(t0["us"], t0["us_default"]):
+        assert 0.0 < a <= b
+    # the second handle of the shape reuses the first one's choice: same kernels, same bits
+    assert {k: t0[k] for k in t0 if k not in ("us", "us_default")} == {k: t1[k] for k in t1 if k not in ("us", "us_default")}
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def test_autotune_off_gives_default_tiles(env):
+    NF, T, Z, torch = env
+    NF.nf_set_autotune(0)
+    try:
+        with NF.Grid((256, 512)) as g:
+            t = g.tuning()
+    finally:
+        NF.nf_set_autotune(1)
+    assert not t["tuned"] and t["flux_plan"] == 0 and t["div_plan"] == 0 and t["update_plan"] == 0
+    with pytest.raises(NF.NfError):
+        NF.nf_set_autotune(2)
