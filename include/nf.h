@@ -326,8 +326,9 @@ const char *nf_batch_last_error(const nf_batch *b);
  * two).  The three passes of a PCG iteration (operator middle: x transforms
  * and the flux (m m^T + r I) grad p; operator end: y transform, divergence and
  * the inner products; update) exist in several tile variants: rows per
- * workgroup of the operator middle, columns per workgroup of the other two,
- * and the order of the radix-8 and radix-4 stages of their transforms.  When
+ * workgroup of the operator middle, columns and threads per workgroup of the
+ * other two, and the order of the radix-8 and radix-4 stages of their
+ * transforms.  When
  * autotuning is on (the default), the first nf_create_grid of a grid shape
  * and precision in a process times every variant of each pass on the new
  * handle's workspace and keeps the fastest (the default tile unless a variant
@@ -335,8 +336,13 @@ const char *nf_batch_last_error(const nf_batch *b);
  * of that shape use the same choice, so their results agree bit for bit.
  * The variants change the work split and the rounding of the transforms and
  * inner products only.
- * nf_set_autotune: 1 on, 0 off (default tiles for handles created afterwards);
- *   NF_EINVAL otherwise.
+ * nf_set_autotune: 2 (the default) times each candidate's throughput with three
+ *   concurrent launches on separate buffers (the choice for solves that share
+ *   the GPU, as ensemble partitions and concurrent handles do; the tuning then
+ *   allocates two scratch copies of the loop's buffers, freed before
+ *   nf_create_grid returns); 1 times each candidate alone; 0 turns tuning off
+ *   (default tiles for handles created afterwards).  Shapes already tuned
+ *   keep their choice.  NF_EINVAL for other values.
  * nf_tuning: the variants of a handle.  us / us_default: time per launch of the
  *   chosen variant / the default tile measured by the tuner (0 if not tuned);
  *   candidates: variants timed per pass.
@@ -347,20 +353,25 @@ typedef struct {
   int flux_plan;      /* 0: radix-8 stages first, 1: radix-4 stages first */
   int div_cols;       /* operator end: spectral columns per workgroup */
   int div_plan;
+  int div_threads;    /* threads per workgroup */
   int update_cols;    /* update: spectral columns per workgroup */
   int update_plan;
+  int update_threads;
   int candidates[3];  /* operator middle, operator end, update */
   double us[3];
   double us_default[3];
 } nf_tuning_info;
-int nf_set_autotune(int on);
+int nf_set_autotune(int mode);
 int nf_tuning(const nf_grid *g, nf_tuning_info *out);
 /*
  * Fix the variants of one handle (2D), overriding the tuner: variant code v
  * selects half (v % 3 == 0), the default (1) or twice (2) the default rows
- * (operator middle) or columns (operator end, update) per workgroup, and the
- * radix plan v / 3 (v in [0, 5]; 1 is the untuned pass, -1 keeps the current
- * one).  NF_EINVAL if a variant does not exist for the grid and precision.
+ * (operator middle) or columns (operator end, update) per workgroup; v / 3
+ * selects the radix plan (0: radix-8 stages first, 1: radix-4 first) and, for
+ * the operator end and update only, v / 3 = 2 or 3 the first plan with twice
+ * or four times the threads.  Codes: operator middle [0, 5], the others
+ * [0, 11]; 1 is the untuned pass, -1 keeps the current one.  NF_EINVAL if a
+ * variant does not exist for the grid and precision.
  */
 int nf_set_tiles(nf_grid *g, int flux_var, int div_var, int update_var);
 

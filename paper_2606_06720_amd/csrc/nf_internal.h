@@ -34,7 +34,7 @@ enum { FLAG_NONFINITE = 1, FLAG_INCOMPAT = 2 };
 // Slots of the partial-sum area; each slot holds up to SLOT_K arrays of
 // MAX_WG doubles.
 enum {
-  SLOT_P3 = 0,      // <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>, <r,M^-1 r>, <r,r>
+  SLOT_P3 = 0,      // <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,M^-1 r>
   SLOT_P3INIT = 1,  // <r,M^-1 r>, <r,r>, <b,b>
   SLOT_KBAR = 2,    // sum mx^2, mx my, my^2, r
   SLOT_SCHK = 3,    // sum S, sum |S|
@@ -77,7 +77,7 @@ struct Geo {
 enum { TCLK_CAP = 2048, TCLK_W = 64 };
 // tile variants of the PCG-loop passes (codes 0 .. NVAR-1, see nf_tiles.hpp);
 // VAR_DEFAULT is the untuned tile
-enum { VAR_DEFAULT = 1, NVAR = 6 };  // timed iterations per PCG loop, stamp slots per iteration
+enum { VAR_DEFAULT = 1, NVAR = 12 };  // timed iterations per PCG loop, stamp slots per iteration
 
 __host__ __device__ inline double* slot_ptr(double* part, int slot) {
   return part + (size_t)slot * SLOT_K * MAX_WG;
@@ -254,6 +254,7 @@ int rr_nwg(const Geo& g, bool f32);
 // rows per workgroup of row variant rv, columns per workgroup of column variant cv
 int flux_var_rows(const Geo& g, int rv);
 int div_var_cols(const Geo& g, int cv);
+int div_var_threads(const Geo& g, int cv);
 // whether the grid sizes have tuned variants at all
 bool var_grid(const Geo& g);
 // fill n doubles with a value (a kernel, so that no memset node is recorded)

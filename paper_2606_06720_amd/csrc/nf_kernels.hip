@@ -168,8 +168,10 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
-  V tv[C::ET];
-  rowT_gload<C>(tv, G0, G1, nullptr, g.ny, y0, nrow);
+  // the pairs (k, H - k) of each line, so that the pre-processing of the
+  // inverse real transform happens on the way into LDS
+  V ta[RowPairs<C>::ETP], tb[RowPairs<C>::ETP];
+  rowTP_gload<C>(ta, tb, G0, G1, nullptr, g.ny, y0, nrow);
   if (it >= 1) {
     double rr[1];
     sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
@@ -185,9 +187,8 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
       return;
     }
   }
-  rowT_put<C>(buf, tv);
+  rowTP_put_pre<C>(buf, ta, tb, tw, g.twn);
   __syncthreads();
-  irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   lds_fft<T, +1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   // m and r are loaded only now: held across the transform they would cost
   // about 48 registers, and a workgroup with fewer registers shares a compute
@@ -233,8 +234,8 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   }
   __syncthreads();
   lds_fft<T, -1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
-  rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  rowT_store<C, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
+  // post-processing of the forward real transform on the way out
+  rowTP_store_post<C, 2>(buf, G0, G1, nullptr, tw, g.twn, g.ny, y0, nrow);
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
     write_partials<C::NT>(kslot, ks, 4);
@@ -707,8 +708,8 @@ __global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) kb_col_grad(const ColGra
 // Operator end: forward y transform of the fluxes, q_hat = -i xi . F_hat.
 // INIT: r_hat = b_hat - q_hat (stored), partials <r,M^-1 r>, <r,r>, <b,b>;
 //       also reduces the Kbar and compatibility partials of the row pass.
-// else: q_hat stored, partials <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>,
-//       <r,M^-1 r>, <r,r>.
+// else: q_hat stored, partials <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,M^-1 r> (the
+//       inner products the update's alpha and beta need).
 // INIT exists for T = double only (the residual of the refinement is FP64).
 template <int NY, bool INIT, typename T, int CV>
 __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx,
@@ -722,7 +723,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
   if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
   if (!INIT) tclk_start(g, 1, it);
   __shared__ V buf[C::NB * C::LS];
-  __shared__ double red[7 * (C::NT / 64)];
+  __shared__ double red[4 * (C::NT / 64)];
   __shared__ double Ks[4];
   const V* tw = (const V*)g.tw;
   const int kx0 = blockIdx.x * C::C;
@@ -757,7 +758,7 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
     colP_gload<C>(av, dh, kx0, g.h);
     colP_gload<C>(bv, rh, kx0, g.h);
   }
-  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -790,27 +791,29 @@ __device__ __forceinline__ void col_div_body(Geo g, const cx<T>* __restrict__ Fx
         s[0] += w * (dx * qx + dy * qy);
         s[1] += w * sig * rq;
         s[2] += w * sig * qq;
-        s[3] += w * rq;
-        s[4] += w * qq;
-        const double r2 = rx * rx + ry * ry;
-        s[5] += w * sig * r2;
-        s[6] += w * r2;
+        s[3] += w * sig * (rx * rx + ry * ry);
       }
     }
   }
-  block_sum<C::NT, 7>(s, red);
-  write_partials<C::NT>(slot_ptr(g.part, INIT ? SLOT_P3INIT : SLOT_P3), s, INIT ? 3 : 7);
+  if (INIT) {
+    double s3[3] = {s[0], s[1], s[2]};
+    block_sum<C::NT, 3>(s3, red);
+    write_partials<C::NT>(slot_ptr(g.part, SLOT_P3INIT), s3, 3);
+  } else {
+    block_sum<C::NT, 4>(s, red);
+    write_partials<C::NT>(slot_ptr(g.part, SLOT_P3), s, 4);
+  }
   if (!INIT) tclk_end(g, 1, it);
 }
 template <int NY, bool INIT, typename T, int CV>
-__global__ void __launch_bounds__(2 * TPF) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
+__global__ void __launch_bounds__((DivCfg<NY, CV>::NT)) k_col_div(Geo g, const cx<T>* __restrict__ Fx,
                                                  const cx<T>* __restrict__ Fy, cx<T>* __restrict__ qh,
                                                  const cx<T>* __restrict__ dh, cx<T>* rh,
                                                  const cx<T>* __restrict__ bh, int it, int nwg_row) {
   col_div_body<NY, INIT, T, CV>(g, Fx, Fy, qh, dh, rh, bh, it, nwg_row);
 }
 template <int NY, bool INIT, typename T, int CV>
-__global__ void __launch_bounds__(2 * TPF) kb_col_div(const DivArgs* __restrict__ A, int it, int nwg_row) {
+__global__ void __launch_bounds__((DivCfg<NY, CV>::NT)) kb_col_div(const DivArgs* __restrict__ A, int it, int nwg_row) {
   const DivArgs& a = A[blockIdx.y];
   col_div_body<NY, INIT, T, CV>(a.g, (const cx<T>*)a.Fx, (const cx<T>*)a.Fy, (cx<T>*)a.qh, (const cx<T>*)a.dh, (cx<T>*)a.rh, (const cx<T>*)a.bh, it, nwg_row);
 }
@@ -877,9 +880,9 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
   } else {
     // rho = <r,M^-1 r> of the residual the last operator pass read, computed
     // directly from it
-    double s[7];
-    sum_partials<C::NT, 7>(slot_ptr(g.part, SLOT_P3), nwg_col, MAX_WG, s, red);
-    const double rho = s[5];
+    double s[4];
+    sum_partials<C::NT, 4>(slot_ptr(g.part, SLOT_P3), nwg_col, MAX_WG, s, red);
+    const double rho = s[3];
     alpha = rho / s[0];
     const double rhon = rho - 2.0 * alpha * s[1] + alpha * alpha * s[2];
     beta = rhon / rho;
@@ -939,13 +942,13 @@ __device__ __forceinline__ void col_update_body(Geo g, int first, cx<T>* xh, cx<
   tclk_end(g, 2, tit);
 }
 template <int NY, typename T, int CV>
-__global__ void __launch_bounds__(2 * TPF) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
+__global__ void __launch_bounds__((DivCfg<NY, CV>::NT)) k_col_update(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh,
                                                     const cx<T>* __restrict__ qh, cx<T>* Gx, cx<T>* Gy, int it,
                                                     int max_iter, double tol2, int nwg_col) {
   col_update_body<NY, T, CV>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg_col);
 }
 template <int NY, typename T, int CV>
-__global__ void __launch_bounds__(2 * TPF) kb_col_update(const UpdArgs* __restrict__ A, int first, int it, int max_iter, double tol2, int nwg_col) {
+__global__ void __launch_bounds__((DivCfg<NY, CV>::NT)) kb_col_update(const UpdArgs* __restrict__ A, int first, int it, int max_iter, double tol2, int nwg_col) {
   const UpdArgs& a = A[blockIdx.y];
   col_update_body<NY, T, CV>(a.g, first, (cx<T>*)a.xh, (cx<T>*)a.rh, (cx<T>*)a.dh, (const cx<T>*)a.qh, (cx<T>*)a.Gx, (cx<T>*)a.Gy, it, max_iter, tol2, nwg_col);
 }
@@ -1347,7 +1350,7 @@ static hipError_t flux_var(int rv, const Geo& g, cx<T>* G0, cx<T>* G1, const T* 
   switch (rv) {
 #define V_(K) \
   case K: return flux_go<NX, T, K>(g, G0, G1, m, r, it, kslot, nwg_col, tol2, lo, s, e0, e1);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1369,7 +1372,7 @@ static hipError_t fluxb_var(int rv, const Geo& g, const FluxArgs* A, int count, 
   switch (rv) {
 #define V_(K) \
   case K: return fluxb_go<NX, T, K>(g, A, count, it, nwg_col, tol2, s);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1378,7 +1381,7 @@ template <int NY, typename T, int CV>
 static hipError_t div_go(const Geo& g, const cx<T>* Fx, const cx<T>* Fy, cx<T>* qh, const cx<T>* dh, cx<T>* rh,
                          int it, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
-    const dim3 grid(col_nwg_var(g, CV)), blk(2 * TPF);
+    const dim3 grid(col_nwg_var(g, CV)), blk(DivCfg<NY, CV>::NT);
     NF_LAUNCH((k_col_div<NY, false, T, CV>), grid, blk, s, e0, e1, g, Fx, Fy, qh, dh, rh, (const cx<T>*)nullptr, it,
               0);
     return hipGetLastError();
@@ -1392,7 +1395,7 @@ static hipError_t div_var(int cv, const Geo& g, const cx<T>* Fx, const cx<T>* Fy
   switch (cv) {
 #define V_(K) \
   case K: return div_go<NY, T, K>(g, Fx, Fy, qh, dh, rh, it, s, e0, e1);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1400,7 +1403,7 @@ static hipError_t div_var(int cv, const Geo& g, const cx<T>* Fx, const cx<T>* Fy
 template <int NY, typename T, int CV>
 static hipError_t divb_go(const Geo& g, const DivArgs* A, int count, int it, hipStream_t s) {
   if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
-    const dim3 grid(col_nwg_var(g, CV), count), blk(2 * TPF);
+    const dim3 grid(col_nwg_var(g, CV), count), blk(DivCfg<NY, CV>::NT);
     hipLaunchKernelGGL((kb_col_div<NY, false, T, CV>), grid, blk, 0, s, A, it, 0);
     return hipGetLastError();
   } else {
@@ -1412,7 +1415,7 @@ static hipError_t divb_var(int cv, const Geo& g, const DivArgs* A, int count, in
   switch (cv) {
 #define V_(K) \
   case K: return divb_go<NY, T, K>(g, A, count, it, s);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1422,7 +1425,7 @@ static hipError_t upd_go(const Geo& g, int first, cx<T>* xh, cx<T>* rh, cx<T>* d
                          cx<T>* Gy, int it, int max_iter, double tol2, int nwg, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
-    const dim3 grid(col_nwg_var(g, CV)), blk(2 * TPF);
+    const dim3 grid(col_nwg_var(g, CV)), blk(DivCfg<NY, CV>::NT);
     NF_LAUNCH((k_col_update<NY, T, CV>), grid, blk, s, e0, e1, g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2,
               nwg);
     return hipGetLastError();
@@ -1437,7 +1440,7 @@ static hipError_t upd_var(int cv, const Geo& g, int first, cx<T>* xh, cx<T>* rh,
   switch (cv) {
 #define V_(K) \
   case K: return upd_go<NY, T, K>(g, first, xh, rh, dh, qh, Gx, Gy, it, max_iter, tol2, nwg, s, e0, e1);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1446,7 +1449,7 @@ template <int NY, typename T, int CV>
 static hipError_t updb_go(const Geo& g, const UpdArgs* A, int count, int first, int it, int max_iter, double tol2,
                           int nwg, hipStream_t s) {
   if constexpr (div_var_exists<NY, CV, (int)sizeof(cx<T>)>()) {
-    const dim3 grid(col_nwg_var(g, CV), count), blk(2 * TPF);
+    const dim3 grid(col_nwg_var(g, CV), count), blk(DivCfg<NY, CV>::NT);
     hipLaunchKernelGGL((kb_col_update<NY, T, CV>), grid, blk, 0, s, A, first, it, max_iter, tol2, nwg);
     return hipGetLastError();
   } else {
@@ -1459,7 +1462,7 @@ static hipError_t updb_var(int cv, const Geo& g, const UpdArgs* A, int count, in
   switch (cv) {
 #define V_(K) \
   case K: return updb_go<NY, T, K>(g, A, count, first, it, max_iter, tol2, nwg, s);
-    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5)
+    V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     default: return hipErrorInvalidValue;
   }
@@ -1482,6 +1485,7 @@ int flux_var_rows(const Geo& g, int rv) {
   return rv == VAR_DEFAULT ? tile_rows(g.nx / 2, row_tile(g.nx, 2)) : rv_rows(g.nx, rv);
 }
 int div_var_cols(const Geo& g, int cv) { return cv == VAR_DEFAULT ? col_cols(g.ny) : cv_cols(g.ny, cv); }
+int div_var_threads(const Geo& g, int cv) { return 2 * TPF * (cv == VAR_DEFAULT ? 1 : cv_tm(cv)); }
 bool var_grid(const Geo& g) { return g.nz == 1 && (var_size(g.nx) || var_size(g.ny)); }
 
 hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s) {

@@ -599,7 +599,8 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
   zT_put<NZ, 3, 3>(buf, tv);
   __syncthreads();
   lds_fft<T, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  constexpr int KP = INIT ? 3 : 4;  // partial sums stored (see below)
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -633,15 +634,15 @@ __global__ void __launch_bounds__(3 * TPF) k3_zdiv(Geo g, const cx<T>* F0, const
         s[0] += w * (dx * qx + dy * qy);
         s[1] += w * sig * rq;
         s[2] += w * sig * qq;
-        s[3] += w * rq;
-        s[4] += w * qq;
-        const double r2 = rx * rx + ry * ry;
-        s[5] += w * sig * r2;
-        s[6] += w * r2;
+        s[3] += w * sig * (rx * rx + ry * ry);
       }
     }
   }
-  store_partials<C::NT, 7>(s, g, INIT ? SLOT_P3INIT : SLOT_P3, red);
+  // INIT: <r,M^-1 r>, <r,r>, <b,b>; else <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,M^-1 r>
+  double sk[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) sk[k] = s[k];
+  store_partials<C::NT, KP>(sk, g, INIT ? SLOT_P3INIT : SLOT_P3, red);
   if (!INIT) tclk_end(g, 1, it);
 }
 
@@ -698,7 +699,7 @@ __global__ void __launch_bounds__(3 * TPF) k3_zupdate(Geo g, int first, cx<T>* x
     stop = zero_x;
   } else {
     const double* s = g.tot + SLOT_P3 * SLOT_K;
-    const double rho = s[5];
+    const double rho = s[3];
     alpha = rho / s[0];
     const double rhon = rho - 2.0 * alpha * s[1] + alpha * alpha * s[2];
     beta = rhon / rho;
@@ -1125,7 +1126,7 @@ hipError_t launch3_zdiv(const Geo& g, bool f32, int init, const void* F0, const 
 #undef L_
   }
   const hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : launch3_sum_tot(g, init ? SLOT_P3INIT : SLOT_P3, 7, nwg3_z(g), s);
+  return e != hipSuccess ? e : launch3_sum_tot(g, init ? SLOT_P3INIT : SLOT_P3, init ? 3 : 4, nwg3_z(g), s);
 }
 hipError_t launch3_zupdate(const Geo& g, bool f32, int first, void* xh, void* rh, void* dh, const void* qh, void* G0,
                            void* G1, void* G2, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0,
@@ -1186,6 +1187,8 @@ hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s) 
   switch (K) {
     case 1: hipLaunchKernelGGL(k3_sum_tot<1>, dim3(1), dim3(256), 0, s, g, slot, n); break;
     case 2: hipLaunchKernelGGL(k3_sum_tot<2>, dim3(1), dim3(256), 0, s, g, slot, n); break;
+    case 3: hipLaunchKernelGGL(k3_sum_tot<3>, dim3(1), dim3(256), 0, s, g, slot, n); break;
+    case 4: hipLaunchKernelGGL(k3_sum_tot<4>, dim3(1), dim3(256), 0, s, g, slot, n); break;
     case 7: hipLaunchKernelGGL(k3_sum_tot<7>, dim3(1), dim3(256), 0, s, g, slot, n); break;
     default: return hipErrorInvalidValue;
   }

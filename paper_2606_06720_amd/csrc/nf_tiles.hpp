@@ -56,13 +56,13 @@ struct RowCfg {
 template <int NX, int NF>
 using Row2D = RowCfg<NX, NF, row_tile(NX, NF)>;
 
-template <int NY, int NF, int CT = TILE, int PL = 0>
+template <int NY, int NF, int CT = TILE, int PL = 0, int TM = 1>
 struct ColCfg {
   static constexpr int C0 = CT / NY;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
   static constexpr int PLAN = PL;                               // radix plan of the y transforms
   static constexpr int NYv = NY;
-  static constexpr int NT = TPF * NF;
+  static constexpr int NT = TPF * NF * TM;                      // TM: thread multiple of the tile
   static constexpr int LS = lpad_use(NY) ? lpad_len(NY) : NY;   // room for the FFT's padded layout
   static constexpr int CN = C * NY;                             // elements per field in the block
   static constexpr int NB = NF * C;                             // LDS lines
@@ -76,10 +76,14 @@ struct ColCfg {
 //   row variant rv (operator middle): rows per workgroup RD/2, RD or 2 RD for
 //     rv % 3 = 0, 1, 2 (RD the default rows of Row2D<NX, 2>), radix plan rv / 3;
 //   column variant cv (operator end, update): columns per workgroup CD/2, CD or
-//     2 CD for cv % 3 = 0, 1, 2 (CD the default of ColCfg<NY, 2>), radix plan cv / 3.
+//     2 CD for cv % 3 = 0, 1, 2 (CD the default of ColCfg<NY, 2>); cv / 3 = 0:
+//     radix plan 0, 1: plan 1, 2 and 3: plan 0 with twice and four times the
+//     threads (long columns, where each thread of the default tile would
+//     otherwise run several butterflies per stage, one wave per SIMD).
 // Variant 1 (default tile, plan 0) is the untuned pass.  Variants that would
 // repeat another (a radix plan without an alternative), fall below one row or
-// column, or exceed the LDS of a workgroup do not exist.
+// column, leave threads without a radix-8 butterfly, or exceed the LDS of a
+// workgroup do not exist.  Row variants use the codes below 6 only.
 enum { LDS_LIMIT = 160 * 1024 };  // VAR_DEFAULT, NVAR: nf_internal.h
 
 __host__ __device__ constexpr int rv_rows(int nx, int rv) {
@@ -99,15 +103,17 @@ __host__ __device__ constexpr int flux_lds(int nx, int rows, int es) {
 __host__ __device__ constexpr int div_lds(int ny, int cols, int es) {
   return 2 * cols * ((lpad_use(ny) ? lpad_len(ny) : ny) * es);
 }
+__host__ __device__ constexpr int cv_plan(int cv) { return cv / 3 == 1 ? 1 : 0; }
+__host__ __device__ constexpr int cv_tm(int cv) { return cv / 3 == 2 ? 2 : (cv / 3 == 3 ? 4 : 1); }
 __host__ __device__ constexpr bool rv_ok(int nx, int ny, int rv, int es) {
-  return rv >= 0 && rv < NVAR && (rv / 3 == 0 || plan_has_alt(ilog2(nx / 2))) && rv_rows(nx, rv) >= 1 &&
+  return rv >= 0 && rv < 6 && (rv / 3 == 0 || plan_has_alt(ilog2(nx / 2))) && rv_rows(nx, rv) >= 1 &&
          rv_rows(nx, rv) <= 64 && (rv % 3 != 2 || rv_rows(nx, rv) <= ny) &&
          flux_lds(nx, rv_rows(nx, rv), es) + 4096 <= LDS_LIMIT;
 }
 __host__ __device__ constexpr bool cv_ok(int ny, int h, int cv, int es) {
-  return cv >= 0 && cv < NVAR && (cv / 3 == 0 || plan_has_alt(ilog2(ny))) && cv_cols(ny, cv) >= 1 &&
+  return cv >= 0 && cv < NVAR && (cv / 3 != 1 || plan_has_alt(ilog2(ny))) && cv_cols(ny, cv) >= 1 &&
          cv_cols(ny, cv) <= 64 && (cv % 3 != 2 || cv_cols(ny, cv) <= h) &&
-         div_lds(ny, cv_cols(ny, cv), es) + 4096 <= LDS_LIMIT;
+         cv_cols(ny, cv) * ny >= cv_tm(cv) * TILE && div_lds(ny, cv_cols(ny, cv), es) + 4096 <= LDS_LIMIT;
 }
 // grid sizes that have tuned variants (every size has the default)
 __host__ __device__ constexpr bool var_size(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
@@ -117,7 +123,7 @@ using FluxCfg = typename std::conditional<RV == VAR_DEFAULT, Row2D<NX, 2>,
                                           RowCfg<NX, 2, rv_rows(NX, RV) * (NX / 2), RV / 3>>::type;
 template <int NY, int CV>
 using DivCfg = typename std::conditional<CV == VAR_DEFAULT, ColCfg<NY, 2>,
-                                         ColCfg<NY, 2, cv_cols(NY, CV) * NY, CV / 3>>::type;
+                                         ColCfg<NY, 2, cv_cols(NY, CV) * NY, cv_plan(CV), cv_tm(CV)>>::type;
 // variants that can be built for a size (the row count against Ny is checked at run time)
 template <int NX, int RV, int ES>
 constexpr bool flux_var_exists() {
@@ -218,6 +224,104 @@ __device__ __forceinline__ void rowT_store(const V* buf, same<V>* d0, same<V>* d
     if (rr < nrow) pickw<V>(f, d0, d1, d2)[(size_t)kx * ny + y0 + rr] = buf[(f * C::R + rr) * C::LS + kx];
   }
 }
+// Pair images of the row passes, which fold the real-transform pre- and
+// post-processing (irfft_pre / rfft_post of nf_fft.hpp, same arithmetic) into
+// the transposed loads and stores: task t -> field t / (R NP), row
+// (t % (R NP)) % R, pair k = (t % (R NP)) / R, covering the entries k and
+// mirror(k) of that line (mirror(0) = H/2, the self-paired entry for even H;
+// mirror(k) = H - k otherwise).  Consecutive tasks run along the R rows of one
+// k, as the transposed images do.
+template <class C>
+struct RowPairs {
+  static constexpr int NP = (C::H + 1) / 2;
+  static constexpr int NTK = C::NFv * C::R * NP;          // tasks
+  static constexpr int ETP = (NTK + C::NT - 1) / C::NT;   // tasks per thread
+};
+__host__ __device__ constexpr int pair_mirror(int k, int h) { return k == 0 ? h / 2 : h - k; }
+
+template <class C, typename V>
+__device__ __forceinline__ void rowTP_gload(V (&a)[RowPairs<C>::ETP], V (&b)[RowPairs<C>::ETP], const V* s0,
+                                            const same<V>* s1, const same<V>* s2, int ny, int y0, int nrow) {
+  using PT = RowPairs<C>;
+  constexpr int H = C::H;
+#pragma unroll
+  for (int i = 0; i < PT::ETP; ++i) {
+    const int t = threadIdx.x + i * C::NT;
+    const int f = t / (C::R * PT::NP), u = t % (C::R * PT::NP);
+    const int rr = u % C::R, k = u / C::R;
+    const bool ok = t < PT::NTK && rr < nrow;
+    const V* src = pick<V>(f, s0, s1, s2);
+    a[i] = ok ? src[(size_t)k * ny + y0 + rr] : vzero<V>();
+    b[i] = (ok && (k != 0 || H % 2 == 0)) ? src[(size_t)pair_mirror(k, H) * ny + y0 + rr] : vzero<V>();
+  }
+}
+// Write the loaded pairs into the LDS lines (field * R + row) after the
+// pre-processing of the inverse real transform: rebuilds 2 Z from the packed
+// half spectrum X (see irfft_pre).  Rows beyond nrow carry zeros, as they do
+// in the transposed image.
+template <class C, typename T>
+__device__ __forceinline__ void rowTP_put_pre(cx<T>* buf, const cx<T> (&a)[RowPairs<C>::ETP],
+                                              const cx<T> (&b)[RowPairs<C>::ETP], const cx<T>* __restrict__ tw,
+                                              int twn) {
+  using PT = RowPairs<C>;
+  constexpr int H = C::H;
+  const int mult = twn / (2 * H);
+#pragma unroll
+  for (int i = 0; i < PT::ETP; ++i) {
+    const int t = threadIdx.x + i * C::NT;
+    if (t >= PT::NTK) continue;
+    const int f = t / (C::R * PT::NP), u = t % (C::R * PT::NP);
+    const int rr = u % C::R, k = u / C::R;
+    cx<T>* l = buf + (f * C::R + rr) * C::LS;
+    if (k == 0) {
+      const cx<T> p = a[i];  // X[0] + i X[H]
+      l[0] = mk<T>(p.x + p.y, p.x - p.y);
+      if (H % 2 == 0) {
+        const cx<T> xh = b[i];
+        l[H / 2] = mk<T>(xh.x + xh.x, -(xh.y + xh.y));
+      }
+    } else {
+      const cx<T> xk = a[i], xm = b[i];
+      const cx<T> w = tw[k * mult];
+      const cx<T> e1 = add(xk, conj(xm)), o1 = sub(xk, conj(xm));
+      const cx<T> e2 = add(xm, conj(xk)), o2 = sub(xm, conj(xk));
+      l[k] = add(e1, mul_i<+1>(mul(conj(w), o1)));
+      l[H - k] = add(e2, mul_i<-1>(mul(w, o2)));
+    }
+  }
+}
+// Post-processing of the forward real transform (see rfft_post) of the first
+// NFS fields' lines, stored straight to the mixed layout.
+template <class C, int NFS, typename T>
+__device__ __forceinline__ void rowTP_store_post(const cx<T>* buf, same<cx<T>>* d0, same<cx<T>>* d1,
+                                                 same<cx<T>>* d2, const cx<T>* __restrict__ tw, int twn, int ny,
+                                                 int y0, int nrow) {
+  using PT = RowPairs<C>;
+  constexpr int H = C::H;
+  const int mult = twn / (2 * H);
+  for (int t = threadIdx.x; t < NFS * C::R * PT::NP; t += C::NT) {
+    const int f = t / (C::R * PT::NP), u = t % (C::R * PT::NP);
+    const int rr = u % C::R, k = u / C::R;
+    if (rr >= nrow) continue;
+    const cx<T>* l = buf + (f * C::R + rr) * C::LS;
+    cx<T>* dst = pickw<cx<T>>(f, d0, d1, d2) + y0 + rr;
+    if (k == 0) {
+      const cx<T> z0 = l[0];
+      dst[0] = mk<T>(z0.x + z0.y, z0.x - z0.y);
+      if (H % 2 == 0) dst[(size_t)(H / 2) * ny] = conj(l[H / 2]);
+    } else {
+      const cx<T> zk = l[k], zm = l[H - k];
+      const cx<T> w = tw[k * mult];
+      const cx<T> e1 = add(zk, conj(zm)), o1 = sub(zk, conj(zm));
+      const cx<T> e2 = add(zm, conj(zk)), o2 = sub(zm, conj(zk));
+      const cx<T> t1 = mul_i<-1>(mul(w, o1));
+      const cx<T> t2 = mul_i<+1>(mul(conj(w), o2));
+      dst[(size_t)k * ny] = scl(add(e1, t1), (T)0.5);
+      dst[(size_t)(H - k) * ny] = scl(add(e2, t2), (T)0.5);
+    }
+  }
+}
+
 // "P" image of a physical field: element p -> row p / H, pair p % H (the
 // grid points 2j, 2j+1 of the row), coalesced over the row-major layout
 template <class C, typename P, typename S>

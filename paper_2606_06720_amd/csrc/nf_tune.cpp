@@ -5,7 +5,11 @@
 // the operator end and update (columns per workgroup, radix plan of the y
 // transforms) that exists for the shape is timed on the new handle's own
 // buffers, and the fastest of each pass is kept.  The default tile stays unless
-// a variant is more than 3% faster.  The choice is made once per process for
+// a variant is more than 3% faster.  By default each candidate is timed with
+// three concurrent launches, each on its own copy of the buffers, so that the
+// choice holds for solves that share the GPU (ensembles, concurrent
+// instances); a variant that is faster alone but takes more of a compute
+// unit's resources can lose there.  The choice is made once per process for
 // each (Nx, Ny, real type) and cached, so every handle, ensemble and
 // allocation-free solve of that shape runs the same kernels (their results then
 // agree bit for bit).
@@ -15,6 +19,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "nf.h"
 #include "nf_handle.h"
@@ -33,7 +38,10 @@ struct Choice {
 
 std::mutex cache_mu;
 std::map<std::tuple<int, int, int, int>, Choice> cache;  // (device, nx, ny, f32)
-int autotune_on = 1;
+// 0: off; 1: tune each pass alone; 2: tune its throughput with three
+// concurrent launches (the default: solves of one process often run
+// concurrently, as the instances of an ensemble do)
+int autotune_mode = 2;
 
 void apply(nf_grid* g, bool f32, const Choice& c, int tuned) {
   const int k = f32 ? 1 : 0;
@@ -50,63 +58,115 @@ void apply(nf_grid* g, bool f32, const Choice& c, int tuned) {
   }
 }
 
-// Time `reps` launches of one pass (after two untimed ones); milliseconds per launch.
+// Time `reps` rounds of launches of one pass (after two untimed rounds), each
+// round launching the pass once on every stream (launch(k) on stream k);
+// milliseconds per launch.  With several streams the launches of a round run
+// concurrently, so the figure is the pass's throughput under that contention.
 template <class F>
-hipError_t time_pass(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F&& launch, double* ms) {
+hipError_t time_pass(const std::vector<hipStream_t>& ss, hipEvent_t e0, hipEvent_t e1, std::vector<hipEvent_t>& ej,
+                     F&& launch, double* ms) {
   hipError_t e;
+  const int ns = (int)ss.size();
   for (int i = 0; i < 2; ++i)
-    if ((e = launch()) != hipSuccess) return e;
+    for (int k = 0; k < ns; ++k)
+      if ((e = launch(k)) != hipSuccess) return e;
   const int reps = 5;
-  if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(e0, ss[0])) != hipSuccess) return e;
+  for (int k = 1; k < ns; ++k)
+    if ((e = hipStreamWaitEvent(ss[k], e0, 0)) != hipSuccess) return e;
   for (int i = 0; i < reps; ++i)
-    if ((e = launch()) != hipSuccess) return e;
-  if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    for (int k = 0; k < ns; ++k)
+      if ((e = launch(k)) != hipSuccess) return e;
+  for (int k = 1; k < ns; ++k) {
+    if ((e = hipEventRecord(ej[k], ss[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ss[0], ej[k], 0)) != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(e1, ss[0])) != hipSuccess) return e;
   if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
   float t = 0.0f;
   if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
-  *ms = (double)t / reps;
+  *ms = (double)t / (reps * ns);
   return hipSuccess;
 }
 
-hipError_t run_tuning(nf_grid* g, bool f32, Choice* out) {
+// Buffers one stream of the tuning works on: two mixed fields, the four PCG
+// vectors and stand-ins for m and r (3 n values).
+struct TuneBufs {
+  void* M0;
+  void* M1;
+  void* X;
+  void* R;
+  void* D;
+  void* Q;
+  void* mr;
+};
+
+hipError_t run_tuning(nf_grid* g, bool f32, int nstreams, Choice* out) {
   Geo& G = f32 ? g->geo32 : g->geo;
-  const int k = f32 ? 1 : 0;
+  const int k32 = f32 ? 1 : 0;
   hipStream_t s = g->stream;
   const size_t n = (size_t)g->nx * g->ny;
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const size_t spec = n * es;  // one half-spectrum field (n/2 complex values)
   hipError_t e = hipSuccess;
-  // stand-ins for m and r (the passes' timing does not depend on the values)
-  void* mr = nullptr;
-  if (f32) {
-    mr = g->lo;
-  } else if ((e = hipMalloc(&mr, 3 * n * sizeof(double))) != hipSuccess) {
-    return e;
-  }
+  std::vector<TuneBufs> bufs(nstreams);
+  std::vector<hipStream_t> ss(nstreams, nullptr);
+  std::vector<hipEvent_t> ej(nstreams, nullptr);
+  std::vector<void*> owned;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (!f32 && mr) (void)hipFree(mr);
+    for (hipStream_t q : ss)
+      if (q) (void)hipStreamSynchronize(q);
+    for (int k = 1; k < nstreams; ++k) {
+      if (ej[k]) (void)hipEventDestroy(ej[k]);
+      if (ss[k]) (void)hipStreamDestroy(ss[k]);
+    }
+    for (void* q : owned) (void)hipFree(q);
   };
-#define TCHK(expr)             \
-  do {                         \
+#define TCHK(expr)                    \
+  do {                                \
     if ((e = (expr)) != hipSuccess) { \
-      cleanup();               \
-      return e;                \
-    }                          \
+      cleanup();                      \
+      return e;                       \
+    }                                 \
   } while (0)
+  // stream 0 works on the handle's own buffers (m and r stand-ins: the FP32
+  // copies of a refined handle, else a scratch array); the others on scratch
+  // copies, so that concurrent launches touch distinct memory
+  ss[0] = s;
+  bufs[0] = {f32 ? g->mix32[0] : g->mix[0], f32 ? g->mix32[1] : g->mix[1], f32 ? g->x32 : g->xh,
+             f32 ? g->r32 : g->rh,          f32 ? g->d32 : g->dh,          f32 ? g->q32 : g->qh,
+             f32 ? (void*)g->lo : nullptr};
+  if (!f32) {
+    void* q = nullptr;
+    TCHK(hipMalloc(&q, 3 * n * es));
+    owned.push_back(q);
+    bufs[0].mr = q;
+  }
+  for (int k = 1; k < nstreams; ++k) {
+    void* q = nullptr;
+    TCHK(hipMalloc(&q, 6 * spec + 3 * n * es));
+    owned.push_back(q);
+    char* c = (char*)q;
+    bufs[k] = {c, c + spec, c + 2 * spec, c + 3 * spec, c + 4 * spec, c + 5 * spec, c + 6 * spec};
+    TCHK(hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking));
+    TCHK(hipEventCreateWithFlags(&ej[k], hipEventDisableTiming));
+  }
   TCHK(hipEventCreate(&e0));
   TCHK(hipEventCreate(&e1));
-  // a running solver state for the loop passes: no stop recorded, and partial
-  // sums of the operator end that give finite, non-stopping PCG scalars
+  // a running solver state for the loop passes: no stop recorded
   TCHK(launch_status_reset(G, 1, s));
-  TCHK(launch_fill_doubles(slot_ptr(g->part, SLOT_P3), (size_t)SLOT_K * MAX_WG, 1.0, s));
-  void* M0 = f32 ? g->mix32[0] : g->mix[0];
-  void* M1 = f32 ? g->mix32[1] : g->mix[1];
-  void* X = f32 ? g->x32 : g->xh;
-  void* R = f32 ? g->r32 : g->rh;
-  void* D = f32 ? g->d32 : g->dh;
-  void* Q = f32 ? g->q32 : g->qh;
+  TCHK(hipStreamSynchronize(s));
   for (int pass = 0; pass < 3; ++pass) {
+    if (pass == 2) {
+      // partial sums of the operator end that give the update finite,
+      // non-stopping PCG scalars (the timed operator end overwrote them)
+      TCHK(launch_fill_doubles(slot_ptr(g->part, SLOT_P3), (size_t)SLOT_K * MAX_WG, 1.0, s));
+      TCHK(launch_status_reset(G, 1, s));
+      TCHK(hipStreamSynchronize(s));
+    }
     double best[NVAR];
     for (int v = 0; v < NVAR; ++v) best[v] = -1.0;
     int nc = 0;
@@ -117,22 +177,27 @@ hipError_t run_tuning(nf_grid* g, bool f32, Choice* out) {
         if (round == 0) ++nc;
         double ms = 0.0;
         if (pass == 0) {
-          G.var_flux[k] = v;
-          TCHK(time_pass(s, e0, e1, [&]() {
-            return f32 ? launch_row_flux32(G, M0, M1, (const float*)mr, (const float*)mr + 2 * n, 0, 0.0, s)
-                       : launch_row_flux(G, M0, M1, (const double*)mr, (const double*)mr + 2 * n, 0, nullptr, 0.0, s);
+          G.var_flux[k32] = v;
+          TCHK(time_pass(ss, e0, e1, ej, [&](int k) {
+            const TuneBufs& b = bufs[k];
+            return f32 ? launch_row_flux32(G, b.M0, b.M1, (const float*)b.mr, (const float*)b.mr + 2 * n, 0, 0.0,
+                                           ss[k])
+                       : launch_row_flux(G, b.M0, b.M1, (const double*)b.mr, (const double*)b.mr + 2 * n, 0,
+                                         nullptr, 0.0, ss[k]);
           }, &ms));
         } else if (pass == 1) {
-          G.var_div[k] = v;
-          TCHK(time_pass(s, e0, e1, [&]() {
-            return f32 ? launch_col_div32(G, M0, M1, Q, D, R, 0, s)
-                       : launch_col_div(G, 0, M0, M1, Q, D, R, g->bh, 0, 0, s);
+          G.var_div[k32] = v;
+          TCHK(time_pass(ss, e0, e1, ej, [&](int k) {
+            const TuneBufs& b = bufs[k];
+            return f32 ? launch_col_div32(G, b.M0, b.M1, b.Q, b.D, b.R, 0, ss[k])
+                       : launch_col_div(G, 0, b.M0, b.M1, b.Q, b.D, b.R, g->bh, 0, 0, ss[k]);
           }, &ms));
         } else {
-          G.var_upd[k] = v;
-          TCHK(time_pass(s, e0, e1, [&]() {
-            return f32 ? launch_col_update32(G, X, R, D, Q, M0, M1, 1, INT_MAX, 0.0, s)
-                       : launch_col_update(G, 0, X, R, D, Q, M0, M1, 1, INT_MAX, 0.0, s);
+          G.var_upd[k32] = v;
+          TCHK(time_pass(ss, e0, e1, ej, [&](int k) {
+            const TuneBufs& b = bufs[k];
+            return f32 ? launch_col_update32(G, b.X, b.R, b.D, b.Q, b.M0, b.M1, 1, INT_MAX, 0.0, ss[k])
+                       : launch_col_update(G, 0, b.X, b.R, b.D, b.Q, b.M0, b.M1, 1, INT_MAX, 0.0, ss[k]);
           }, &ms));
         }
         if (best[v] < 0.0 || ms < best[v]) best[v] = ms;
@@ -152,9 +217,9 @@ hipError_t run_tuning(nf_grid* g, bool f32, Choice* out) {
     out->ncand[pass] = nc;
     out->us[pass] = 1e3 * best[pick];
     out->us_default[pass] = 1e3 * best[VAR_DEFAULT];
-    if (pass == 0) G.var_flux[k] = pick;
-    if (pass == 1) G.var_div[k] = pick;
-    if (pass == 2) G.var_upd[k] = pick;
+    if (pass == 0) G.var_flux[k32] = pick;
+    if (pass == 1) G.var_div[k32] = pick;
+    if (pass == 2) G.var_upd[k32] = pick;
   }
   // leave the handle as a fresh one: status, partial sums and iterate cleared
   TCHK(launch_status_reset(G, 1, s));
@@ -172,7 +237,7 @@ int tune_handle(nf_grid* g) {
   const bool f32 = g->dtype == NF_F32_REFINED;
   Choice c;
   std::lock_guard<std::mutex> lock(cache_mu);
-  if (g->dim != 2 || !autotune_on || !var_grid(g->geo)) {
+  if (g->dim != 2 || !autotune_mode || !var_grid(g->geo)) {
     apply(g, f32, c, 0);
     return NF_OK;
   }
@@ -182,7 +247,7 @@ int tune_handle(nf_grid* g) {
     apply(g, f32, it->second, 1);
     return NF_OK;
   }
-  hipError_t e = run_tuning(g, f32, &c);
+  hipError_t e = run_tuning(g, f32, autotune_mode == 2 ? 3 : 1, &c);
   if (e != hipSuccess) {
     g->err = std::string("tile tuning: ") + hipGetErrorString(e);
     return NF_EDEVICE;
@@ -194,7 +259,7 @@ int tune_handle(nf_grid* g) {
 
 bool tune_lookup(int device, int nx, int ny, bool f32, int var[3]) {
   std::lock_guard<std::mutex> lock(cache_mu);
-  if (!autotune_on) return false;
+  if (!autotune_mode) return false;
   auto it = cache.find(std::make_tuple(device, nx, ny, f32 ? 1 : 0));
   if (it == cache.end()) return false;
   for (int i = 0; i < 3; ++i) var[i] = it->second.var[i];
@@ -205,10 +270,10 @@ bool tune_lookup(int device, int nx, int ny, bool f32, int var[3]) {
 
 extern "C" {
 
-int nf_set_autotune(int on) {
-  if (on != 0 && on != 1) return NF_EINVAL;
+int nf_set_autotune(int mode) {
+  if (mode < 0 || mode > 2) return NF_EINVAL;
   std::lock_guard<std::mutex> lock(nf::cache_mu);
-  nf::autotune_on = on;
+  nf::autotune_mode = mode;
   return NF_OK;
 }
 
@@ -243,9 +308,11 @@ int nf_tuning(const nf_grid* g, nf_tuning_info* out) {
   out->flux_rows = nf::flux_var_rows(G, vf);
   out->flux_plan = vf / 3;
   out->div_cols = nf::div_var_cols(G, vd);
-  out->div_plan = vd / 3;
+  out->div_plan = vd / 3 == 1 ? 1 : 0;
+  out->div_threads = nf::div_var_threads(G, vd);
   out->update_cols = nf::div_var_cols(G, vu);
-  out->update_plan = vu / 3;
+  out->update_plan = vu / 3 == 1 ? 1 : 0;
+  out->update_threads = nf::div_var_threads(G, vu);
   for (int i = 0; i < 3; ++i) {
     out->candidates[i] = g->tune_ncand[i];
     out->us[i] = g->tune_us[i];

@@ -73,8 +73,9 @@ class nf_run_info(ctypes.Structure):
 
 class nf_tuning_info(ctypes.Structure):
     _fields_ = [("tuned", ctypes.c_int), ("flux_rows", ctypes.c_int), ("flux_plan", ctypes.c_int),
-                ("div_cols", ctypes.c_int), ("div_plan", ctypes.c_int), ("update_cols", ctypes.c_int),
-                ("update_plan", ctypes.c_int), ("candidates", ctypes.c_int * 3), ("us", ctypes.c_double * 3),
+                ("div_cols", ctypes.c_int), ("div_plan", ctypes.c_int), ("div_threads", ctypes.c_int),
+                ("update_cols", ctypes.c_int), ("update_plan", ctypes.c_int), ("update_threads", ctypes.c_int),
+                ("candidates", ctypes.c_int * 3), ("us", ctypes.c_double * 3),
                 ("us_default", ctypes.c_double * 3)]
 
 
@@ -311,11 +312,12 @@ class Grid:
         t = nf_tuning_info()
         self._check(_lib.nf_tuning(self._h, ctypes.byref(t)))
         return {"tuned": bool(t.tuned), "flux_rows": t.flux_rows, "flux_plan": t.flux_plan, "div_cols": t.div_cols,
-                "div_plan": t.div_plan, "update_cols": t.update_cols, "update_plan": t.update_plan,
+                "div_plan": t.div_plan, "div_threads": t.div_threads, "update_cols": t.update_cols,
+                "update_plan": t.update_plan, "update_threads": t.update_threads,
                 "candidates": list(t.candidates), "us": list(t.us), "us_default": list(t.us_default)}
 
     def set_tiles(self, flux_var=-1, div_var=-1, update_var=-1):
-        """nf_set_tiles: fix this handle's tile variants (codes 0..5, -1 keeps)."""
+        """nf_set_tiles: fix this handle's tile variants (operator middle 0..5, others 0..11; -1 keeps)."""
         self._check(_lib.nf_set_tiles(self._h, int(flux_var), int(div_var), int(update_var)))
 
     def set_inner_tolerance(self, floor_rtol):
@@ -490,11 +492,12 @@ def nf_step_adjoint(g, c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, g
     return g.step_adjoint(c2, D2, gamma, dt, m, p, r, S, lam_next, lam_k, grad_r, grad_S, mu, rtol, max_iter)
 
 
-def nf_set_autotune(on):
-    """Process-wide: tune the tile variants at the first nf_create_grid of a shape (1) or not (0)."""
-    rc = _lib.nf_set_autotune(int(on))
+def nf_set_autotune(mode):
+    """Process-wide tuning of the tile variants at the first nf_create_grid of a
+    shape: 2 (default) under three concurrent launches, 1 alone, 0 off."""
+    rc = _lib.nf_set_autotune(int(mode))
     if rc != NF_OK:
-        raise NfError(rc, "nf_set_autotune: on must be 0 or 1")
+        raise NfError(rc, "nf_set_autotune: mode must be 0, 1 or 2")
 
 
 def nf_tuning(g):

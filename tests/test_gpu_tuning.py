@@ -18,7 +18,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarnin
 TOL = 1e-10
 
 SHAPES = [((256, 256), (1.0, 1.0)), ((512, 1024), (1.0, 2.0)), ((4096, 32), (1.0, 1.0 / 128)),
-          ((1024, 256), (2.0, 0.5))]
+          ((1024, 256), (2.0, 0.5)), ((64, 4096), (1.0 / 64, 1.0)), ((128, 2048), (1.0 / 16, 1.0))]
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +56,7 @@ def test_every_tile_variant_matches_oracle(env, n, L):
         ran = 0
         with NF.Grid(n, L, dtype=dtype) as g:
             for which in range(3):
-                for v in range(6):
+                for v in range(6 if which == 0 else 12):
                     codes = [1, 1, 1]
                     codes[which] = v
                     try:
@@ -104,7 +104,8 @@ def test_autotune_off_gives_default_tiles(env):
         with NF.Grid((256, 512)) as g:
             t = g.tuning()
     finally:
-        NF.nf_set_autotune(1)
-    assert not t["tuned"] and t["flux_plan"] == 0 and t["div_plan"] == 0 and t["update_plan"] == 0
-    with pytest.raises(NF.NfError):
         NF.nf_set_autotune(2)
+    assert not t["tuned"] and t["flux_plan"] == 0 and t["div_plan"] == 0 and t["update_plan"] == 0
+    assert t["div_threads"] == t["update_threads"] == 256
+    with pytest.raises(NF.NfError):
+        NF.nf_set_autotune(3)
