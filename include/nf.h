@@ -182,8 +182,11 @@ int nf_pressure_solve_noalloc(const int64_t n[2], const double L[2], void *strea
  *           multiplier exp(-D^2 |xi|^2 dt) in Fourier space (eq.
  *           diffusion_space_discrete), in that order.
  *   m [2][Ny][Nx] in: m^k, out: m^{k+1};  p out: p[m^k].
- * info may be NULL.  Returns NF_OK, NF_ENOTCONV (m is still advanced with the
- * last PCG iterate), NF_EINCOMPAT, NF_ENONFINITE, NF_EINVAL or NF_EDEVICE.
+ * info may be NULL.  Each call forms the transformed right-hand side F(Pi S)
+ * from S again (one forward transform, a few percent of a step; S may change
+ * between calls); nf_run forms it once per run.  Returns NF_OK, NF_ENOTCONV (m
+ * is still advanced with the last PCG iterate), NF_EINCOMPAT, NF_ENONFINITE,
+ * NF_EINVAL or NF_EDEVICE.
  */
 int nf_step(nf_grid *g, const nf_params *prm, double dt, double *m, double *p, const double *r, const double *S,
             double rtol, int max_iter, nf_step_info *info);
@@ -254,11 +257,16 @@ int nf_step_adjoint(nf_grid *g, const nf_params *prm, double dt, const double *m
  *   half spectrum in the same layout.
  * nf_apply_operator: out = A p, the left-hand side of eq. p_discrete for the
  *   given m and r, p [Ny][Nx], out [Ny][Nx].
- * All three are enqueued on the handle's stream and return after synchronising it.
+ * nf_gradient: grad = G f, the spectral gradient of eq. p_discrete (the
+ *   first-derivative multipliers with the Nyquist entry zeroed, Sec. 2.3.3),
+ *   f [Ny][Nx], grad [2][Ny][Nx] (component 0 = d/dx); 2D handles only
+ *   (NF_EINVAL otherwise).
+ * All four are enqueued on the handle's stream and return after synchronising it.
  */
 int nf_transform_forward(nf_grid *g, const double *f, double *out);
 int nf_transform_inverse(nf_grid *g, const double *spec, double *f);
 int nf_apply_operator(nf_grid *g, const double *m, const double *r, const double *p, double *out);
+int nf_gradient(nf_grid *g, const double *f, double *grad);
 
 /*
  * Ensembles: independent instances of the problem of Sec. 2 advanced together.

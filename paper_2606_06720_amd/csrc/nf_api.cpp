@@ -725,6 +725,23 @@ int nf_transform_inverse(nf_grid* g, const double* spec, double* f) {
   return NF_OK;
 }
 
+int nf_gradient(nf_grid* g, const double* f, double* grad) {
+  if (!g) return NF_EINVAL;
+  g->err.clear();
+  int rc = check_fields(g, {f, grad});
+  if (rc) return rc;
+  if (g->dim != 2) return fail(g, NF_EINVAL, "nf_gradient is available for 2D grids only");
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny;
+  LCHK(g, launch_row_r2c(G, f, g->mix[0], nullptr, s));
+  LCHK(g, launch_col_fwd(G, g->mix[0], g->qh, 1, g->mix[1], g->mix[2], s));
+  LCHK(g, launch_row_c2r(G, g->mix[1], grad, s));
+  LCHK(g, launch_row_c2r(G, g->mix[2], grad + n, s));
+  HIPCHK(g, hipStreamSynchronize(s));
+  return NF_OK;
+}
+
 int nf_apply_operator(nf_grid* g, const double* m, const double* r, const double* p, double* out) {
   if (!g) return NF_EINVAL;
   g->err.clear();

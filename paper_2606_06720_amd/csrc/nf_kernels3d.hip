@@ -16,8 +16,9 @@
 // factors of the separable heat kernel, whose x factor is applied in the row
 // pass before the planes are mixed.
 // Inner products use the weights of the 2D path (1 on slot 0, 2 elsewhere).
-// Reductions: every workgroup writes its block sums, the last one to arrive
-// adds them in index order (deterministic) and publishes the totals.
+// Reductions: every workgroup stores its block sums as partials and a
+// one-workgroup pass launched right after the producing pass adds them in
+// index order (deterministic) into the totals (see store_partials).
 #include <hip/hip_ext.h>
 
 #include <climits>

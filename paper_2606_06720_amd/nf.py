@@ -105,6 +105,7 @@ def _load():
     lib.nf_transform_forward.argtypes = [vp, vp, vp]
     lib.nf_transform_inverse.argtypes = [vp, vp, vp]
     lib.nf_apply_operator.argtypes = [vp, vp, vp, vp, vp]
+    lib.nf_gradient.argtypes = [vp, vp, vp]
     lib.nf_set_inner_tolerance.argtypes = [vp, dp]
     lib.nf_set_autotune.argtypes = [ctypes.c_int]
     lib.nf_tuning.argtypes = [vp, ctypes.POINTER(nf_tuning_info)]
@@ -128,7 +129,8 @@ def _load():
     lib.nf_version.restype = ctypes.c_char_p
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_pressure_solve_noalloc",
               "nf_step", "nf_run",
-              "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator", "nf_time_kernel",
+              "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator",
+              "nf_gradient", "nf_time_kernel",
               "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_set_autotune", "nf_tuning", "nf_set_tiles",
               "nf_batch_create", "nf_batch_destroy",
               "nf_batch_set_stream", "nf_batch_run", "nf_batch_set_partitions", "nf_batch_partitions",
@@ -353,6 +355,11 @@ class Grid:
         self._sync_stream()
         self._check(_lib.nf_apply_operator(self._h, _ptr(m, self.vshape, "m"), _ptr(r, self.sshape, "r"),
                                            _ptr(p, self.sshape, "p"), _ptr(out, self.sshape, "out")))
+
+    def gradient(self, f, grad):
+        """nf_gradient: grad [2][Ny][Nx] = spectral gradient of f [Ny][Nx] (2D)."""
+        self._sync_stream()
+        self._check(_lib.nf_gradient(self._h, _ptr(f, self.sshape, "f"), _ptr(grad, self.vshape, "grad")))
 
 
 def _ri(x):

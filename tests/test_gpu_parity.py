@@ -89,6 +89,26 @@ def test_operator_apply_matches_oracle(env, n, L):
     assert np.abs(out.cpu().numpy() - want).max() <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("n,L", [((64, 32), (1.0, 2.0)), ((4096, 16), (1.0, 1.0 / 256)), ((50, 100), (1.0, 2.0))])
+def test_gradient_matches_oracle_and_closed_form(env, n, L):
+    NF, T, Z, torch = env
+    f = np.random.default_rng(8).standard_normal(n[::-1])
+    X, Y = W.grid_coords(n, L)
+    mode = np.cos(2 * np.pi * (3 * X / L[0] - 2 * Y / L[1]) + 0.5)
+    with NF.Grid(n, L) as g:
+        out = Z((2,) + tuple(n[::-1]))
+        g.gradient(T(f), out)
+        want = O.grad(f, L)
+        assert np.abs(out.cpu().numpy() - want).max() <= 1e-12 * np.abs(want).max()
+        g.gradient(T(mode), out)
+        arg = 2 * np.pi * (3 * X / L[0] - 2 * Y / L[1]) + 0.5
+        gx = -2 * np.pi * 3 / L[0] * np.sin(arg)
+        gy = 2 * np.pi * 2 / L[1] * np.sin(arg)
+        got = out.cpu().numpy()
+        assert np.abs(got[0] - gx).max() <= 1e-11 * np.abs(gx).max()
+        assert np.abs(got[1] - gy).max() <= 1e-11 * np.abs(gy).max()
+
+
 # ------------------------------------------------------------------ pressure solve
 
 @pytest.mark.parametrize("n,rtol", [((8, 8), 1e-12), ((16, 32), 1e-12), ((64, 64), 1e-10), ((256, 128), 1e-12),
