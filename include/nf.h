@@ -116,9 +116,10 @@ typedef struct {
  * fields and FP32 copies of m and r) on the current HIP device.
  * Layouts of the caller's fields: 2D p, r, S [Ny][Nx], m [2][Ny][Nx]; 3D
  * p, r, S [Nz][Ny][Nx], m [3][Nz][Ny][Nx]; x fastest.  On 3D handles
- * nf_energy, the energy stopping of nf_run and nf_step_adjoint return
- * NF_EINVAL (they are implemented for 2D grids only).  Returns NF_EINVAL, NF_ENOMEM or NF_EDEVICE on failure
- * (*out is then NULL).
+ * nf_step_adjoint returns NF_EINVAL (it is implemented for 2D grids only).
+ * The first handle of a 2D shape and precision in a process also tunes the
+ * tiles of the PCG loop (see nf_set_autotune).  Returns NF_EINVAL, NF_ENOMEM
+ * or NF_EDEVICE on failure (*out is then NULL).
  */
 int nf_create_grid(nf_grid **out, int ndim, const int64_t n[3], const double L[3], int dtype, void *stream);
 
@@ -214,8 +215,9 @@ int nf_run(nf_grid *g, const nf_params *prm, double dt, int64_t max_steps, doubl
  *   out[2] || |m|^gamma ||^2 / (2 gamma),
  *   out[3] c^2/2 ||m . grad p||^2,
  *   out[4] c^2/2 sum h^d r |grad p|^2,
- * with ||f||^2 = h_x h_y sum f^2 and the spectral gradient.  p must be p[m]; if
- * p is NULL the pressure is solved (cold start, rtol 1e-12, 1000 iterations).
+ * with ||f||^2 = h^d sum f^2 (h^d = hx hy, or hx hy hz on 3D handles) and the
+ * spectral gradient.  p must be p[m]; if p is NULL the pressure is solved
+ * (cold start, rtol 1e-12, 1000 iterations).  2D and 3D handles.
  */
 int nf_energy(nf_grid *g, const nf_params *prm, const double *m, const double *p, const double *r, const double *S,
               double out[5]);

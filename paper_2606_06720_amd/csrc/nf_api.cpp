@@ -483,8 +483,8 @@ int energy_pointwise(nf_grid* g, const nf_params* prm, const double* m, const do
 }
 
 double assemble_energy(const nf_grid* g, const nf_params* prm, double gradm2_phys, const double* pt, double* terms) {
-  const double n = (double)g->nx * g->ny;
-  const double hvol = g->lx * g->ly / n;
+  const double n = (double)g->nx * g->ny * g->nz;
+  const double hvol = g->lx * g->ly * g->lz / n;  // lz = 1, nz = 1 in 2D
   const double e_diff = 0.5 * prm->D2 * hvol * gradm2_phys;
   const double e_relax = hvol * pt[2] / (2.0 * prm->gamma);
   const double e_act = 0.5 * prm->c2 * hvol * pt[1];
@@ -498,6 +498,37 @@ double assemble_energy(const nf_grid* g, const nf_params* prm, double gradm2_phy
     terms[4] = e_flow;
   }
   return tot;
+}
+
+// 3D energy of (m, p = F^-1 x_hat): grad p through the inverse z and y passes
+// and three row passes into physical scratch fields (the PCG vectors r, d, q,
+// free between solves), the pointwise terms, then the three spectra of m into
+// the same scratch fields and their Parseval gradient norm.  Returns E_h and
+// fills terms (5 entries) if non-NULL.
+int energy3(nf_grid* g, const nf_params* prm, const double* m, const double* r, double* e_out, double* terms) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  double* P[3] = {(double*)g->rh, (double*)g->dh, (double*)g->qh};
+  void* const* M = g->mix;
+  LCHK(g, launch3_zinv(G, 2, g->xh, nullptr, M[0], M[1], M[2], s));
+  LCHK(g, launch3_ypass(G, false, 3, +1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+  for (int c = 0; c < 3; ++c) LCHK(g, launch3_row_c2r(G, M[c], P[c], s));
+  LCHK(g, launch3_energy_pt(G, m, r, P[0], P[1], P[2], prm->gamma, s));
+  LCHK(g, launch3_copy_tot(G, SLOT_EPT, 3, 4, s));
+  for (int c = 0; c < 3; ++c) {
+    LCHK(g, launch3_row_r2c(G, m + c * n, M[0], 0, s));
+    LCHK(g, launch3_ypass(G, false, 1, -1, M[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_zfwd(G, M[0], P[c], 0, s));
+  }
+  LCHK(g, launch3_spec_gradnorm(G, P[0], P[1], P[2], s));
+  LCHK(g, launch3_copy_tot(G, SLOT_EGM, 1, 3, s));
+  DevStatus fin;
+  int rc = read_status(g, &fin);
+  if (rc) return rc;
+  const double e = assemble_energy(g, prm, fin.out[3] / (double)n, &fin.out[4], terms);
+  if (e_out) *e_out = e;
+  return NF_OK;
 }
 
 }  // namespace
@@ -986,12 +1017,17 @@ int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p
   int rc = check_fields(g, {m, r, S, out});
   if (rc) return rc;
   if (!prm || !(prm->gamma > 0.0)) return fail(g, NF_EINVAL, "invalid params");
-  if (g->dim != 2) return fail(g, NF_EINVAL, "nf_energy is available for 2D grids only");
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
   if (p) {
-    LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
-    LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 0, nullptr, nullptr, s));
+    if (g->dim == 3) {
+      LCHK(g, launch3_row_r2c(G, p, g->mix[0], 0, s));
+      LCHK(g, launch3_ypass(G, false, 1, -1, g->mix[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+      LCHK(g, launch3_zfwd(G, g->mix[0], g->xh, 0, s));
+    } else {
+      LCHK(g, launch_row_r2c(G, p, g->mix[0], nullptr, s));
+      LCHK(g, launch_col_fwd(G, g->mix[0], g->xh, 0, nullptr, nullptr, s));
+    }
   } else {
     rc = compute_rhs(g, S);
     if (rc) return rc;
@@ -1001,6 +1037,7 @@ int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p
     rc = solve_status_code(g, so);
     if (rc) return rc;
   }
+  if (g->dim == 3) return energy3(g, prm, m, r, nullptr, out);
   const size_t n = (size_t)g->nx * g->ny;
   LCHK(g, launch_row_r2c(G, m, g->mix[0], nullptr, s));
   LCHK(g, launch_row_r2c(G, m + n, g->mix[1], nullptr, s));
@@ -1040,7 +1077,7 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
   ri.total_cg_iters = 0;
   ri.unconverged_solves = 0;
   const bool en = stop_on_energy_increase != 0;
-  if (en && g->dim != 2) return fail(g, NF_EINVAL, "energy stopping is available for 2D grids only");
+  const bool en2 = en && g->dim == 2;  // 2D: the gradient norm comes with the heat pass
   const bool need_sync = en || eps_dm > 0.0;
 
   rc = compute_rhs(g, S);
@@ -1060,7 +1097,11 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
     return rc;
   }
   double e_prev = NAN;
-  if (en) {
+  if (en && g->dim == 3) {
+    rc = energy3(g, prm, m, r, &e_prev, nullptr);
+    if (rc) return rc;
+    ri.last_energy = e_prev;
+  } else if (en) {
     LCHK(g, launch_row_r2c(G, m, g->mix[0], nullptr, s));
     LCHK(g, launch_row_r2c(G, m + n, g->mix[1], nullptr, s));
     LCHK(g, launch_col_gradnorm(G, g->mix[0], g->mix[1], slot_ptr(g->part, SLOT_EGM), s));
@@ -1074,12 +1115,12 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
     ri.last_energy = e_prev;
   }
   while (ri.steps < max_steps) {
-    rc = split_update(g, prm, dt, m, p, en);
+    rc = split_update(g, prm, dt, m, p, en2);
     if (rc) return rc;
     // keep Delta m and ||grad m_new||^2 before the solve reuses the status block
     rc = dm_to_status(g);
     if (rc) return rc;
-    if (en) LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 10, s));
+    if (en2) LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 10, s));
     DevStatus pre;
     if (need_sync) {
       rc = read_status(g, &pre);
@@ -1109,12 +1150,18 @@ int nf_run(nf_grid* g, const nf_params* prm, double dt, int64_t max_steps, doubl
       const double dm = pre.out[9] > 0.0 ? std::sqrt(pre.out[8] / pre.out[9]) / dt : 0.0;
       ri.last_dm = dm;
       if (en) {
-        rc = energy_pointwise(g, prm, m, r);
-        if (rc) return rc;
-        DevStatus t;
-        rc = read_status(g, &t);
-        if (rc) return rc;
-        const double e = assemble_energy(g, prm, pre.out[10] * (double)n, &t.out[4], nullptr);
+        double e = 0.0;
+        if (g->dim == 3) {
+          rc = energy3(g, prm, m, r, &e, nullptr);
+          if (rc) return rc;
+        } else {
+          rc = energy_pointwise(g, prm, m, r);
+          if (rc) return rc;
+          DevStatus t;
+          rc = read_status(g, &t);
+          if (rc) return rc;
+          e = assemble_energy(g, prm, pre.out[10] * (double)n, &t.out[4], nullptr);
+        }
         ri.prev_energy = e_prev;
         ri.last_energy = e;
         if (e >= e_prev) {

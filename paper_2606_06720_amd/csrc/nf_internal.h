@@ -235,6 +235,12 @@ hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G
                                hipStream_t s);
 // reduced totals of a slot into st->out[o..o+K)
 hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s);
+// energy terms (Sec. 2.5) in 3D: totals of sum r|g|^2, sum (m.g)^2, sum |m|^{2 gamma}
+// into the SLOT_EPT totals (g = grad p as three physical fields), and of the
+// Parseval sum of the three spectra of m into the SLOT_EGM total
+hipError_t launch3_energy_pt(const Geo& g, const double* m, const double* r, const double* gx, const double* gy,
+                             const double* gz, double gamma, hipStream_t s);
+hipError_t launch3_spec_gradnorm(const Geo& g, const void* F0, const void* F1, const void* F2, hipStream_t s);
 // g.tot of a slot from the n partials the passes of the PCG loop store (one
 // workgroup; K = 1 or 7 arrays)
 hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s);

@@ -929,6 +929,49 @@ __global__ void k3_copy_tot(Geo g, int slot, int K, int o) {
   if (threadIdx.x < K) g.st->out[o + threadIdx.x] = g.tot[slot * SLOT_K + threadIdx.x];
 }
 
+// ---------------------------------------------------------------- energy (Sec. 2.5)
+// Pointwise terms of the discrete energy: partials of sum r |g|^2,
+// sum (m . g)^2 and sum |m|^{2 gamma} over the physical grid, with g = grad p
+// given as three physical fields.  Grid-stride over the n points.
+__global__ void __launch_bounds__(256) k3_energy_pt(Geo g, const double* __restrict__ m,
+                                                     const double* __restrict__ r, const double* __restrict__ gx,
+                                                     const double* __restrict__ gy, const double* __restrict__ gz,
+                                                     double gamma) {
+  __shared__ double red[3 * 4];
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double mx = m[i], my = m[n + i], mz = m[2 * n + i];
+    const double ax = gx[i], ay = gy[i], az = gz[i];
+    const double mg = mx * ax + my * ay + mz * az;
+    s[0] += r[i] * (ax * ax + ay * ay + az * az);
+    s[1] += mg * mg;
+    const double mm = mx * mx + my * my + mz * mz;
+    s[2] += (mm == 0.0) ? 0.0 : exp(gamma * log(mm));
+  }
+  store_partials<256, 3>(s, g, SLOT_EPT, red);
+}
+
+// Parseval sum w |xi_tilde|^2 |F_c|^2 over three spectral fields ([kx][ky][kz],
+// slot kx = 0 packed as in the other passes, weight 1 there and 2 elsewhere):
+// n times sum_c ||grad m_c||^2 for the spectra of the components of m.
+__global__ void __launch_bounds__(256) k3_spec_gradnorm(Geo g, const cd* __restrict__ F0, const cd* __restrict__ F1,
+                                                         const cd* __restrict__ F2) {
+  __shared__ double red[4];
+  const size_t ns = (size_t)g.h * g.ny * g.nz;
+  double s[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < ns; i += (size_t)gridDim.x * 256) {
+    const int kx = (int)(i / ((size_t)g.ny * g.nz));
+    const int rem = (int)(i % ((size_t)g.ny * g.nz));
+    const int ky = rem / g.nz, kz = rem % g.nz;
+    const double xt = xi_col(kx, g.lx), yt = xi_tilde(ky, g.ny, g.ly), zt = xi_tilde(kz, g.nz, g.lz);
+    const double w = (kx == 0 ? 1.0 : 2.0) * (xt * xt + yt * yt + zt * zt);
+    const cd a = F0[i], b = F1[i], c = F2[i];
+    s[0] += w * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y);
+  }
+  store_partials<256, 1>(s, g, SLOT_EGM, red);
+}
+
 // totals of the n partials of each of the K arrays of a slot, in a fixed order
 template <int K>
 __global__ void __launch_bounds__(256) k3_sum_tot(Geo g, int slot, int n) {
@@ -1179,6 +1222,22 @@ hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G
 #undef L_
   return hipGetLastError();
 }
+// workgroups of the grid-stride energy passes (at most the partial-sum stride)
+static int nwg3_energy(const Geo& g) { return g.pstride < 1024 ? g.pstride : 1024; }
+hipError_t launch3_energy_pt(const Geo& g, const double* m, const double* r, const double* gx, const double* gy,
+                             const double* gz, double gamma, hipStream_t s) {
+  const int nwg = nwg3_energy(g);
+  hipLaunchKernelGGL(k3_energy_pt, dim3(nwg), dim3(256), 0, s, g, m, r, gx, gy, gz, gamma);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch3_sum_tot(g, SLOT_EPT, 3, nwg, s);
+}
+hipError_t launch3_spec_gradnorm(const Geo& g, const void* F0, const void* F1, const void* F2, hipStream_t s) {
+  const int nwg = nwg3_energy(g);
+  hipLaunchKernelGGL(k3_spec_gradnorm, dim3(nwg), dim3(256), 0, s, g, (const cd*)F0, (const cd*)F1, (const cd*)F2);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch3_sum_tot(g, SLOT_EGM, 1, nwg, s);
+}
+
 hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s) {
   hipLaunchKernelGGL(k3_copy_tot, dim3(1), dim3(64), 0, s, g, slot, K, o);
   return hipGetLastError();

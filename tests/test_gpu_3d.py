@@ -1,7 +1,8 @@
 """GPU parity of the 3D path (ndim = 3 handles): transforms against numpy,
 operator apply, pressure solves, time steps and runs against the CPU oracle
-(FP64 bar 1e-10 relative L2), the mixed-precision form against the oracle and
-against the FP64 form at 256^3, and the 3D error paths."""
+(FP64 bar 1e-10 relative L2), the discrete energy of Sec. 2.5 and the run's
+energy stopping against the oracle, the mixed-precision form against the
+oracle and against the FP64 form at 256^3, and the 3D error paths."""
 
 import numpy as np
 import pytest
@@ -211,10 +212,9 @@ def test_3d_error_paths(env):
         _, info_or = O.pressure_pcg(m, r, S, None, 1e-10, 1)
         assert abs(info.rel_res - info_or.rel_res) <= 1e-12 * info_or.rel_res
         with pytest.raises(NF.NfError) as e:
-            g.energy(1.0, 1e-3, 0.75, T(m), T(r), T(S))
-        assert e.value.code == NF.NF_EINVAL
-        with pytest.raises(NF.NfError) as e:
-            g.run(1.0, 1e-3, 0.75, 1e-3, 2, T(m), p, T(r), T(S), stop_on_energy_increase=True)
+            lam = Z((3,) + n[::-1])
+            g.step_adjoint(1.0, 1e-3, 0.75, 1e-3, T(m), p, T(r), T(S), lam, Z((3,) + n[::-1]), Z(n[::-1]),
+                           Z(n[::-1]), Z(n[::-1]))
         assert e.value.code == NF.NF_EINVAL
         with pytest.raises(NF.NfError) as e:
             g.step(1e6, 1e-3, 0.75, 1.0, T(m), Z(n[::-1]), T(r), T(1e3 * S))
@@ -224,3 +224,45 @@ def test_3d_error_paths(env):
     with pytest.raises(NF.NfError) as e:
         NF.Grid((16, 16, 2048))
     assert e.value.code == NF.NF_EINVAL
+
+
+@pytest.mark.parametrize("n,L", [((16, 32, 8), (1.0, 2.0, 0.5)), ((32, 32, 32), (1.0, 1.0, 1.0))])
+def test_energy_matches_oracle_3d(env, n, L):
+    NF, T, Z, torch = env
+    m, r, S = rand_fields(n, 23)
+    prm = (12.0, 3e-3, 0.7)
+    p_or, _ = O.pressure_pcg(m, r, S, None, 1e-13, 4000, L)
+    want = O.energy(m, p_or, r, *prm, L)
+    for dtype in (NF.NF_F64, NF.NF_F32_REFINED):
+        with NF.Grid(n, L, dtype=dtype) as g:
+            e_given = g.energy(*prm, T(m), T(r), T(S), p=T(p_or))
+            e_solve = g.energy(*prm, T(m), T(r), T(S))
+        for got in (e_given, e_solve):
+            for a, b in zip(got, want):
+                assert abs(a - b) <= 1e-11 * abs(want[0])
+
+
+def test_energy_stopping_run_matches_oracle_3d(env):
+    NF, T, Z, torch = env
+    w = W.bump_workload(16, ndim=3)
+    m, p, r, S = T(w["m0"]), Z(w["r"].shape), T(w["r"]), T(w["S"])
+    with NF.Grid(w["n"], w["L"]) as g:
+        ri = g.run(w["c2"], w["D2"], w["gamma"], w["dt"], 6, m, p, r, S, stop_on_energy_increase=True, rtol=1e-12,
+                   max_iter=4000)
+    mo, po, rio = O.run(w["m0"], None, w["r"], w["S"], w["c2"], w["D2"], w["gamma"], w["dt"], 6, stop_on_energy=True,
+                        rtol=1e-12, max_iter=4000)
+    assert ri.steps == rio.steps == 6 and ri.stop_reason == NF.NF_STOP_MAX_STEPS == rio.stop_reason
+    assert ri.last_energy < ri.prev_energy
+    assert abs(ri.last_energy - rio.energies[-1]) <= 1e-10 * abs(rio.energies[-1])
+    assert abs(ri.prev_energy - rio.energies[-2]) <= 1e-10 * abs(rio.energies[-2])
+    assert rel(m.cpu().numpy(), mo) <= TOL
+    assert rel(p.cpu().numpy(), po) <= TOL
+    # a step that raises the energy stops the run (a large activation step)
+    with NF.Grid(w["n"], w["L"]) as g:
+        m2, p2 = T(w["m0"]), Z(w["r"].shape)
+        ri = g.run(100.0, 1e-4, 0.75, 0.05, 10, m2, p2, r, T(14 * w["S"]), stop_on_energy_increase=True)
+    _, _, rio = O.run(w["m0"], None, w["r"], 14 * w["S"], 100.0, 1e-4, 0.75, 0.05, 10, stop_on_energy=True)
+    assert rio.unconverged_solves == 0 and ri.unconverged_solves == 0
+    assert ri.stop_reason == NF.NF_STOP_ENERGY_INCREASE == rio.stop_reason
+    assert ri.steps == rio.steps == 1
+    assert abs(ri.last_energy - rio.energies[-1]) <= 1e-9 * abs(rio.energies[-1])
