@@ -46,7 +46,14 @@ struct RowCfg {
   // one radix-8 butterfly per thread, at most 1024 threads (wider tiles give
   // each thread several butterflies per stage)
   static constexpr int NT = (RT / 8) * NF > 1024 ? 1024 : (RT / 8) * NF;
-  static constexpr int LS = lpad_use(H) ? lpad_len(H) + 1 : H + 2;  // LDS line stride (room for the FFT's padded layout)
+  // LDS line stride: room for the FFT's padded layout, rounded so that the R
+  // rows a group of 8 lanes touches in the row-interleaved phases (transposed
+  // and paired loads and stores, consecutive lanes running over the rows of
+  // one kx) start on different 32-byte quarters of the banks' 128 bytes:
+  // stride = 8 / R (mod 8) complex for R < 8, 1 (mod 8) from R = 8 on
+  static constexpr int LS0 = lpad_use(H) ? lpad_len(H) + 1 : H + 2;
+  static constexpr int LSM = R >= 8 ? 1 : (R == 1 ? LS0 % 8 : 8 / R);
+  static constexpr int LS = LS0 + ((LSM - LS0 % 8) + 8) % 8;
   static constexpr int RH = R * H;                              // pairs per field in the block
   static constexpr int NB = NF * R;                             // LDS lines
   static constexpr int ET = (NF * RH + NT - 1) / NT;            // transposed-image elements per thread
@@ -98,7 +105,7 @@ __host__ __device__ constexpr int cv_cols(int ny, int cv) {
 }
 // LDS bytes of the operator-middle and operator-end passes for element size es
 __host__ __device__ constexpr int flux_lds(int nx, int rows, int es) {
-  return 2 * rows * ((lpad_use(nx / 2) ? lpad_len(nx / 2) + 1 : nx / 2 + 2) * es);
+  return 2 * rows * ((lpad_use(nx / 2) ? lpad_len(nx / 2) + 1 : nx / 2 + 2) + 7) * es;
 }
 __host__ __device__ constexpr int div_lds(int ny, int cols, int es) {
   return 2 * cols * ((lpad_use(ny) ? lpad_len(ny) : ny) * es);
