@@ -178,7 +178,19 @@ __host__ __device__ constexpr int lpad_len(int L) { return L + (L >> 3) + 1; }
 // arithmetic costs more registers than the bank conflicts cost time.
 __host__ __device__ constexpr bool lpad_use(int L) { return L <= 1024; }
 
-template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS, bool PIN, bool POUT>
+// Order the LDS accesses of one wave without a workgroup barrier: the LDS
+// executes a wave's instructions in issue order, so a compiler fence that keeps
+// the accesses of two stages apart is enough when the data stays in the wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// WL: every wave reads and writes only lines it owns (see wave_local_ok), so
+// the stage's barriers are wave-level, except a workgroup barrier after the
+// last stage (LAST) for the cross-wave phase that follows.
+template <typename T, int DIR, int L, int B, int LS, int NT, int R, int NS, bool PIN, bool POUT, bool WL = false,
+          bool LAST = true>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twn) {
   static_assert(!(PIN || POUT) || LS >= lpad_len(L), "line stride too small for the padded layout");
   constexpr int Q = L / R;          // butterflies per line
@@ -213,7 +225,8 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
       }
     }
   }
-  __syncthreads();
+  if constexpr (WL) wave_sync();
+  else __syncthreads();
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int f = tid + b * NT;
@@ -237,7 +250,22 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
       }
     }
   }
-  __syncthreads();
+  if constexpr (WL && !LAST) wave_sync();
+  else __syncthreads();
+}
+
+// Whether every wave owns whole lines, the same ones in every stage: all
+// stages of one radix R0 (so the butterflies per line, Q = L / R0, are the same
+// in each stage), at most 64 butterflies per line with 64 a multiple of Q, and
+// whole waves.
+template <int L, int NT, int PL>
+constexpr bool wave_local_ok() {
+  if (mplan_nstages(L) < 1 || NT % 64 != 0) return false;
+  const int r0 = mplan_radix(L, 0, PL);
+  for (int s = 1; s < mplan_nstages(L); ++s)
+    if (mplan_radix(L, s, PL) != r0) return false;
+  const int q = L / r0;
+  return q <= 64 && 64 % q == 0;
 }
 
 template <typename T, int DIR, int L, int B, int LS, int NT, int S, int PL>
@@ -245,8 +273,9 @@ __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__
   static_assert(plan_ok(L), "transform lengths are 5^k 2^p");
   if constexpr (S < mplan_nstages(L)) {
     constexpr bool PAD = lpad_use(L) && LS >= lpad_len(L);
+    constexpr bool WL = wave_local_ok<L, NT, PL>();
     fft_stage<T, DIR, L, B, LS, NT, mplan_radix(L, S, PL), mplan_ns(L, S, PL), PAD && (S > 0),
-              PAD && (S + 1 < mplan_nstages(L))>(buf, tw, twn);
+              PAD && (S + 1 < mplan_nstages(L)), WL, S + 1 == mplan_nstages(L)>(buf, tw, twn);
     fft_stages<T, DIR, L, B, LS, NT, S + 1, PL>(buf, tw, twn);
   }
 }
