@@ -559,6 +559,11 @@ def main():
                 raise RuntimeError("instance %d failed" % k)
         return infos
 
+    # the kernel's span stamps are on during the warmup too, so that their
+    # first-use costs (buffer set-up, first launches) fall outside the timed
+    # region; switching them on again clears the counts
+    for it in inst:
+        it["g"].time_kernel(KERNEL_IDS[args.kernel])
     if args.warmup > 0:
         run_all(args.warmup)
     for it in inst:

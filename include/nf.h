@@ -347,10 +347,12 @@ const char *nf_batch_last_error(const nf_batch *b);
  * The variants change the work split and the rounding of the transforms and
  * inner products only.
  * nf_set_autotune: 2 (the default) times each candidate's throughput with three
- *   concurrent launches on separate buffers (the choice for solves that share
- *   the GPU, as ensemble partitions and concurrent handles do; the tuning then
- *   allocates two scratch copies of the loop's buffers, freed before
- *   nf_create_grid returns); 1 times each candidate alone; 0 turns tuning off
+ *   concurrent launches on separate buffers on grids of at most 2^21 points
+ *   (the choice for solves that share the GPU, as ensemble partitions and
+ *   concurrent handles do; the tuning then allocates two scratch copies of the
+ *   loop's buffers, freed before nf_create_grid returns) and alone on larger
+ *   grids, which fill the GPU by themselves; 1 times each candidate alone on
+ *   every grid; 0 turns tuning off
  *   (default tiles for handles created afterwards).  Shapes already tuned
  *   keep their choice.  NF_EINVAL for other values.
  * nf_tuning: the variants of a handle.  us / us_default: time per launch of the

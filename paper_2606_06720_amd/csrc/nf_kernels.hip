@@ -168,10 +168,18 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
-  // the pairs (k, H - k) of each line, so that the pre-processing of the
-  // inverse real transform happens on the way into LDS
-  V ta[RowPairs<C>::ETP], tb[RowPairs<C>::ETP];
-  rowTP_gload<C>(ta, tb, G0, G1, nullptr, g.ny, y0, nrow);
+  // Tiles of fewer than 1024 threads load the pairs (k, H - k) of each line, so
+  // that the pre-processing of the inverse real transform happens on the way
+  // into LDS; 1024-thread tiles (at most 128 registers per thread) load the
+  // plain transposed image and pre-process in LDS, since the paired form
+  // spills there.
+  constexpr bool PAIRS = C::NT < 1024;
+  constexpr int NA = PAIRS ? RowPairs<C>::ETP : C::ET, NBP = PAIRS ? RowPairs<C>::ETP : 1;
+  V ta[NA], tb[NBP];
+  if constexpr (PAIRS)
+    rowTP_gload<C>(ta, tb, G0, G1, nullptr, g.ny, y0, nrow);
+  else
+    rowT_gload<C>(ta, G0, G1, nullptr, g.ny, y0, nrow);
   if (it >= 1) {
     double rr[1];
     sum_partials<C::NT, 1>(slot_ptr(g.part, SLOT_RR), nwg_col, MAX_WG, rr, red);
@@ -187,8 +195,14 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
       return;
     }
   }
-  rowTP_put_pre<C>(buf, ta, tb, tw, g.twn);
-  __syncthreads();
+  if constexpr (PAIRS) {
+    rowTP_put_pre<C>(buf, ta, tb, tw, g.twn);
+    __syncthreads();
+  } else {
+    rowT_put<C>(buf, ta);
+    __syncthreads();
+    irfft_pre<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+  }
   lds_fft<T, +1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   // m and r are loaded only now: held across the transform they would cost
   // about 48 registers, and a workgroup with fewer registers shares a compute
@@ -235,7 +249,12 @@ __device__ __forceinline__ void row_flux_body(Geo g, cx<T>* G0, cx<T>* G1, const
   __syncthreads();
   lds_fft<T, -1, C::H, C::NB, C::LS, C::NT, C::PLAN>(buf, tw, g.twn);
   // post-processing of the forward real transform on the way out
-  rowTP_store_post<C, 2>(buf, G0, G1, nullptr, tw, g.twn, g.ny, y0, nrow);
+  if constexpr (PAIRS) {
+    rowTP_store_post<C, 2>(buf, G0, G1, nullptr, tw, g.twn, g.ny, y0, nrow);
+  } else {
+    rfft_post<T, C::H, C::NB, C::LS, C::NT>(buf, tw, g.twn);
+    rowT_store<C, 2>(buf, G0, G1, nullptr, g.ny, y0, nrow);
+  }
   if (kslot) {
     block_sum<C::NT, 4>(ks, red);
     write_partials<C::NT>(kslot, ks, 4);

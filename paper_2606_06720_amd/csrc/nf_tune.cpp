@@ -9,7 +9,7 @@
 // three concurrent launches, each on its own copy of the buffers, so that the
 // choice holds for solves that share the GPU (ensembles, concurrent
 // instances); a variant that is faster alone but takes more of a compute
-// unit's resources can lose there.  The choice is made once per process for
+// unit's resources can lose there.  Grids above 2^21 points are timed alone.  The choice is made once per process for
 // each (Nx, Ny, real type) and cached, so every handle, ensemble and
 // allocation-free solve of that shape runs the same kernels (their results then
 // agree bit for bit).
@@ -40,8 +40,12 @@ std::mutex cache_mu;
 std::map<std::tuple<int, int, int, int>, Choice> cache;  // (device, nx, ny, f32)
 // 0: off; 1: tune each pass alone; 2: tune its throughput with three
 // concurrent launches (the default: solves of one process often run
-// concurrently, as the instances of an ensemble do)
+// concurrently, as the instances of an ensemble do) on grids of at most
+// CONTEND_MAX_POINTS points, alone on larger ones, whose passes fill the GPU
+// by themselves (4096^2: thousands of workgroups per launch) and which run
+// alone in practice
 int autotune_mode = 2;
+constexpr long long CONTEND_MAX_POINTS = 1LL << 21;
 
 void apply(nf_grid* g, bool f32, const Choice& c, int tuned) {
   const int k = f32 ? 1 : 0;
@@ -247,7 +251,8 @@ int tune_handle(nf_grid* g) {
     apply(g, f32, it->second, 1);
     return NF_OK;
   }
-  hipError_t e = run_tuning(g, f32, autotune_mode == 2 ? 3 : 1, &c);
+  const bool contend = autotune_mode == 2 && (long long)g->nx * g->ny <= CONTEND_MAX_POINTS;
+  hipError_t e = run_tuning(g, f32, contend ? 3 : 1, &c);
   if (e != hipSuccess) {
     g->err = std::string("tile tuning: ") + hipGetErrorString(e);
     return NF_EDEVICE;
