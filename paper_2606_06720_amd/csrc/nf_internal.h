@@ -204,7 +204,7 @@ hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s);
 // x and y); spectral buffers hold [kx][ky][kz].
 int nwg3_row(const Geo& g);
 int nwg3_y(const Geo& g);
-int nwg3_z(const Geo& g);
+int nwg3_z(const Geo& g, bool f32 = false);  // workgroups of the z passes (FP32 loop passes: f32)
 hipError_t launch3_row_r2c(const Geo& g, const double* f, void* out, int schk, hipStream_t s);
 hipError_t launch3_row_c2r(const Geo& g, const void* in, double* f, hipStream_t s);
 // lo: FP32 copies of m (3n) then r (n), written when non-null; kbar: write the Kbar partials
