@@ -89,6 +89,8 @@ typedef struct {
 typedef struct {
   nf_solve_info solve;
   double dm_rel;       /* Delta m = ||m^{k+1} - m^k|| / (dt ||m^k||) (Sec. 2.5) */
+  double energy;       /* E_h(m^k) with p[m^k] (Sec. 2.5), if energy_valid */
+  int energy_valid;    /* 1 if the handle evaluates it (nf_set_step_energy), else 0 (energy NaN) */
 } nf_step_info;
 
 typedef struct {
@@ -185,12 +187,18 @@ int nf_pressure_solve_noalloc(const int64_t n[2], const double L[2], void *strea
  *   m [2][Ny][Nx] in: m^k, out: m^{k+1};  p out: p[m^k].
  * info may be NULL.  Each call forms the transformed right-hand side F(Pi S)
  * from S again (one forward transform, a few percent of a step; S may change
- * between calls); nf_run forms it once per run.  Returns NF_OK, NF_ENOTCONV (m
+ * between calls); nf_run forms it once per run.  With nf_set_step_energy(g, 1)
+ * the step also evaluates the discrete energy E_h of the state it starts from,
+ * m^k with the pressure p[m^k] of Step 1 (as nf_energy does, 2D and 3D; a few
+ * passes and one host synchronisation more), into info->energy; successive
+ * calls thus give E_h(m^0), E_h(m^1), ...  Returns NF_OK, NF_ENOTCONV (m
  * is still advanced with the last PCG iterate), NF_EINCOMPAT, NF_ENONFINITE,
  * NF_EINVAL or NF_EDEVICE.
  */
 int nf_step(nf_grid *g, const nf_params *prm, double dt, double *m, double *p, const double *r, const double *S,
             double rtol, int max_iter, nf_step_info *info);
+/* on = 1: nf_step fills info->energy (see nf_step); 0 (the default): it does not.  NF_EINVAL for a NULL handle. */
+int nf_set_step_energy(nf_grid *g, int on);
 
 /*
  * Time loop of Algorithm 1 with the stopping criteria of Sec. 2.5.

@@ -939,6 +939,27 @@ int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, c
   rc = pcg(g, m, r, X_FROM_P, p, rtol, max_iter, false, &so);
   if (rc) return rc;
   if (so.flags & FLAG_INCOMPAT) return solve_status_code(g, so);
+  // E_h(m^k) with p[m^k]: the spectral solution is still in x_hat (as in nf_run)
+  double e_step = NAN;
+  if (g->step_energy) {
+    if (g->dim == 3) {
+      rc = energy3(g, prm, m, r, &e_step, nullptr);
+      if (rc) return rc;
+    } else {
+      const Geo& G = g->geo;
+      const size_t n = (size_t)g->nx * g->ny;
+      LCHK(g, launch_row_r2c(G, m, g->mix[0], nullptr, g->stream));
+      LCHK(g, launch_row_r2c(G, m + n, g->mix[1], nullptr, g->stream));
+      LCHK(g, launch_col_gradnorm(G, g->mix[0], g->mix[1], slot_ptr(g->part, SLOT_EGM), g->stream));
+      LCHK(g, launch_sum_slot(G, slot_ptr(g->part, SLOT_EGM), 1, col_nwg(G), 3, g->stream));
+      rc = energy_pointwise(g, prm, m, r);
+      if (rc) return rc;
+      DevStatus t;
+      rc = read_status(g, &t);
+      if (rc) return rc;
+      e_step = assemble_energy(g, prm, t.out[3] / (double)n, &t.out[4], nullptr);
+    }
+  }
   rc = split_update(g, prm, dt, m, p, false);
   if (rc) return rc;
   rc = dm_to_status(g);
@@ -952,10 +973,18 @@ int nf_step(nf_grid* g, const nf_params* prm, double dt, double* m, double* p, c
     info->solve.rel_res = so.rel_res;
     info->solve.true_rel_res = so.true_rel_res;
     info->dm_rel = fin.out[9] > 0.0 ? std::sqrt(fin.out[8] / fin.out[9]) / dt : 0.0;
+    info->energy = e_step;
+    info->energy_valid = g->step_energy ? 1 : 0;
   }
   if (fin.sticky & FLAG_NONFINITE)
     return fail(g, NF_ENONFINITE, "activation overflow: c^2 |grad p|^2 dt too large for the time step");
   return solve_status_code(g, so);
+}
+
+int nf_set_step_energy(nf_grid* g, int on) {
+  if (!g) return NF_EINVAL;
+  g->step_energy = on ? 1 : 0;
+  return NF_OK;
 }
 
 int nf_step_adjoint(nf_grid* g, const nf_params* prm, double dt, const double* m, const double* p, const double* r,

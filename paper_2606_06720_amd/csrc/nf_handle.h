@@ -48,6 +48,7 @@ struct nf_grid {
   // optional per-kernel timing of one PCG-loop kernel: execution-span stamps
   // written by the kernel itself (Geo::tclk), read back after each PCG loop
   int timed = -1;
+  int step_energy = 0;  // nf_step evaluates E_h(m^k) (nf_set_step_energy)
   unsigned long long* tclk = nullptr;   // device, 2 * TCLK_CAP
   unsigned long long* htclk = nullptr;  // pinned copy
   double wall_khz = 0.0;                // device wall-clock ticks per ms

@@ -62,7 +62,8 @@ class nf_solve_info(ctypes.Structure):
 
 
 class nf_step_info(ctypes.Structure):
-    _fields_ = [("solve", nf_solve_info), ("dm_rel", ctypes.c_double)]
+    _fields_ = [("solve", nf_solve_info), ("dm_rel", ctypes.c_double), ("energy", ctypes.c_double),
+                ("energy_valid", ctypes.c_int)]
 
 
 class nf_run_info(ctypes.Structure):
@@ -97,6 +98,7 @@ def _load():
                                               ctypes.c_int, ctypes.POINTER(nf_solve_info)]
     lib.nf_step.argtypes = [vp, ctypes.POINTER(nf_params), dp, vp, vp, vp, vp, dp, ctypes.c_int,
                             ctypes.POINTER(nf_step_info)]
+    lib.nf_set_step_energy.argtypes = [vp, ctypes.c_int]
     lib.nf_run.argtypes = [vp, ctypes.POINTER(nf_params), dp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp, vp,
                            dp, ctypes.c_int, ctypes.POINTER(nf_run_info)]
     lib.nf_energy.argtypes = [vp, ctypes.POINTER(nf_params), vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
@@ -128,7 +130,7 @@ def _load():
     lib.nf_last_error.restype = ctypes.c_char_p
     lib.nf_version.restype = ctypes.c_char_p
     for f in ("nf_create_grid", "nf_destroy_grid", "nf_set_stream", "nf_pressure_solve", "nf_pressure_solve_noalloc",
-              "nf_step", "nf_run",
+              "nf_step", "nf_set_step_energy", "nf_run",
               "nf_energy", "nf_step_adjoint", "nf_transform_forward", "nf_transform_inverse", "nf_apply_operator",
               "nf_gradient", "nf_time_kernel",
               "nf_time_kernel_read", "nf_set_inner_tolerance", "nf_set_autotune", "nf_tuning", "nf_set_tiles",
@@ -158,6 +160,8 @@ class SolveInfo:
 class StepInfo:
     solve: SolveInfo
     dm_rel: float
+    energy: float = float("nan")  # E_h(m^k) when the handle evaluates it (set_step_energy)
+    energy_valid: bool = False
 
 
 @dataclass
@@ -267,7 +271,11 @@ class Grid:
                           _ptr(p, self.sshape, "p"), _ptr(r, self.sshape, "r"), _ptr(S, self.sshape, "S"),
                           float(rtol), int(max_iter), ctypes.byref(info))
         self._check(rc, (NF_ENOTCONV,) if allow_notconv else ())
-        return rc, StepInfo(_si(info.solve), float(info.dm_rel))
+        return rc, StepInfo(_si(info.solve), float(info.dm_rel), float(info.energy), bool(info.energy_valid))
+
+    def set_step_energy(self, on):
+        """nf_set_step_energy: whether step() also evaluates E_h of the state it starts from."""
+        self._check(_lib.nf_set_step_energy(self._h, 1 if on else 0))
 
     def run(self, c2, D2, gamma, dt, max_steps, m, p, r, S, eps_dm=0.0, stop_on_energy_increase=False,
             rtol=1e-10, max_iter=1000):

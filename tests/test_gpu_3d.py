@@ -266,3 +266,21 @@ def test_energy_stopping_run_matches_oracle_3d(env):
     assert ri.stop_reason == NF.NF_STOP_ENERGY_INCREASE == rio.stop_reason
     assert ri.steps == rio.steps == 1
     assert abs(ri.last_energy - rio.energies[-1]) <= 1e-9 * abs(rio.energies[-1])
+
+
+def test_step_energy_3d_matches_oracle(env):
+    """nf_step on a 3D handle with the step energy on: E_h(m^k) with p[m^k]."""
+    NF, T, Z, torch = env
+    n, L = (16, 8, 32), (1.0, 0.5, 2.0)
+    m, r, S = rand_fields(n, 29)
+    c2, D2, gamma, dt = 12.0, 3e-3, 0.7, 2e-3
+    mo = m.copy()
+    with NF.Grid(n, L) as g:
+        g.set_step_energy(True)
+        mg, pg = T(m), Z(n[::-1])
+        for k in range(2):
+            _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12, max_iter=4000)
+            p_k, _ = O.pressure_pcg(mo, r, S, None, 1e-13, 4000, L)
+            want = O.energy(mo, p_k, r, c2, D2, gamma, L)[0]
+            assert si.energy_valid and abs(si.energy - want) <= 1e-10 * abs(want), (k, si.energy, want)
+            mo, _, _ = O.step(mo, p_k, r, S, c2, D2, gamma, dt, 1e-12, 4000, L)
