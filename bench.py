@@ -295,6 +295,24 @@ def sampled_errors(gold, m, p):
     return out
 
 
+def loop_pass_spans(g, w, m, p, r, S, N, real_bytes, steps=10):
+    """Average execution span of each PCG-loop pass of handle g (stamped by the
+    kernel on the device wall clock) over `steps` further time steps, with the
+    algorithmic bandwidth it gives (bytes per point scaled by real_bytes / 8)."""
+    out = {}
+    for kname, kid in sorted(KERNEL_IDS.items(), key=lambda kv: kv[1]):
+        g.time_kernel(kid)
+        g.run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, m, p, r, S, rtol=w["rtol"])
+        ms, cnt = g.time_kernel_read()
+        g.time_kernel(-1)
+        if not cnt:
+            continue
+        us = 1e3 * ms / cnt
+        gbs = KERNEL_BYTES_PER_POINT[kname] * real_bytes / 8.0 * N * N / (us * 1e-6) / 1e9
+        out[kname] = {"avg_launch_us": us, "launches": cnt, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def precision_form(sizes, steps, warmup=3):
     """FP64 and FP32-refined pressure solves on the same GPU: ms per time step
     of the dipole case (gamma 0.75) at each (N, ndim), the relative L2
@@ -330,8 +348,13 @@ def precision_form(sizes, steps, warmup=3):
                 info = g.run(w["c2"], w["D2"], w["gamma"], w["dt"], steps, m, p, r, S, rtol=w["rtol"])
                 torch.cuda.synchronize()
                 t = time.perf_counter() - t0
-            res[name] = dict(ms_per_step=1e3 * t / steps, pcg_iters_per_step=info.total_cg_iters / steps,
-                             m=m.cpu().numpy(), p=p.cpu().numpy(), err=err)
+                res[name] = dict(ms_per_step=1e3 * t / steps, pcg_iters_per_step=info.total_cg_iters / steps,
+                                 m=m.cpu().numpy(), p=p.cpu().numpy(), err=err)
+                if ndim == 2:
+                    # the PCG-loop passes of this form, one at a time, over a few more steps:
+                    # average execution span per launch (in-kernel stamps) against the
+                    # algorithmic bytes of the pass (half in the FP32 inner solve)
+                    res[name]["passes"] = loop_pass_spans(g, w, m, p, r, S, N, 8 if dt_ == NF.NF_F64 else 4)
             progress("precision %d^%d %s: %.3f ms per step, vs oracle %s" % (N, ndim, name, 1e3 * t / steps, err))
             del m, r, S, p
             torch.cuda.empty_cache()
@@ -351,6 +374,8 @@ def precision_form(sizes, steps, warmup=3):
             "f64_vs_oracle": b["err"],
             "f32_refined_vs_oracle": a["err"],
         }
+        if ndim == 2:
+            out["%d^%d" % (N, ndim)]["loop_passes"] = {"f64": b["passes"], "f32_refined": a["passes"]}
     return {"workload": "dipole case, gamma 0.75, PCG rtol 1e-10, %d steps after %d; vs_oracle: one step from m0 "
                         "against the oracle's stored values at sampled nodes" % (steps, warmup),
             "sizes": out}

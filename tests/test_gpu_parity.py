@@ -276,23 +276,24 @@ def test_step_energy_of_start_state_matches_oracle(env):
     n = (64, 32)
     m, r, S = rand_fields(n, 23)
     c2, D2, gamma, dt = 12.0, 3e-3, 0.7, 2e-3
-    with NF.Grid(n) as g:
-        mg, pg = T(m), Z(n[::-1])
-        _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12)
-        assert not si.energy_valid and np.isnan(si.energy)
-        g.set_step_energy(True)
-        mo, po = m.copy(), None
-        mg, pg = T(m), Z(n[::-1])
-        for k in range(3):
+    for dtype in (NF.NF_F64, NF.NF_F32_REFINED):
+        with NF.Grid(n, dtype=dtype) as g:
+            mg, pg = T(m), Z(n[::-1])
             _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12)
-            p_k, _ = O.pressure_pcg(mo, r, S, None, 1e-13, 2000)
-            want = O.energy(mo, p_k, r, c2, D2, gamma)[0]
-            assert si.energy_valid
-            assert abs(si.energy - want) <= 1e-10 * abs(want), (k, si.energy, want)
-            mo, po, _ = O.step(mo, po, r, S, c2, D2, gamma, dt, 1e-12)
-        g.set_step_energy(False)
-        _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12)
-        assert not si.energy_valid
+            assert not si.energy_valid and np.isnan(si.energy)
+            g.set_step_energy(True)
+            mo, po = m.copy(), None
+            mg, pg = T(m), Z(n[::-1])
+            for k in range(3):
+                _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12)
+                p_k, _ = O.pressure_pcg(mo, r, S, None, 1e-13, 2000)
+                want = O.energy(mo, p_k, r, c2, D2, gamma)[0]
+                assert si.energy_valid
+                assert abs(si.energy - want) <= 1e-10 * abs(want), (dtype, k, si.energy, want)
+                mo, po, _ = O.step(mo, po, r, S, c2, D2, gamma, dt, 1e-12)
+            g.set_step_energy(False)
+            _, si = g.step(c2, D2, gamma, dt, mg, pg, T(r), T(S), rtol=1e-12)
+            assert not si.energy_valid
 
 
 def test_run_stopping_criteria_match_oracle(env):
