@@ -128,7 +128,8 @@ int nf_create_grid(nf_grid **out, int ndim, const int64_t n[3], const double L[3
 /* Release the handle and its workspace (after synchronising its stream). NULL is a no-op. */
 int nf_destroy_grid(nf_grid *g);
 
-/* Change the stream the handle enqueues on. */
+/* Change the stream the handle enqueues on (after synchronising the previous one,
+ * whose queue may still hold the handle's last launches). */
 int nf_set_stream(nf_grid *g, void *stream);
 
 /*

@@ -109,8 +109,10 @@ enum XSource { X_FROM_P = 0, X_FROM_XH = 1, X_ZERO = 2 };
 // Timing hooks: when the handle times kernel `which`, the kernel stamps, for
 // each loop iteration, the earliest workgroup start and the latest workgroup
 // end on the device wall clock (Geo::tclk).  The stamps are cleared before
-// each PCG loop and collected after it; launches queued after the solver
-// stopped (no-ops) are discarded.  The launch events are no longer used.
+// each PCG loop and copied out after it without waiting (pinned buffer, event);
+// the host adds them up before the next copy or when the totals are read, so
+// timing adds no synchronisation to the loop.  Launches queued after the
+// solver stopped (no-ops) are discarded.  The launch events are no longer used.
 int timed_events(nf_grid* g, int which, int it, hipEvent_t* e0, hipEvent_t* e1) {
   (void)g;
   (void)which;
@@ -123,17 +125,12 @@ int timed_reset(nf_grid* g) {
   LCHK(g, launch_tclk_reset(g->tclk, g->stream));
   return NF_OK;
 }
-// called after the stream is synchronised; flux and div of iteration it did
-// work iff it < conv_at, the update stamped with it iff 1 <= it <= conv_at
-int timed_collect(nf_grid* g, int conv_at) {
-  if (g->timed < 0) return NF_OK;
-  const int lo = g->timed == NF_KERNEL_COL_UPDATE ? 1 : 0;
-  int hi = g->timed == NF_KERNEL_COL_UPDATE ? conv_at : conv_at - 1;
-  if (hi > TCLK_CAP - 1) hi = TCLK_CAP - 1;
-  if (hi < lo) return NF_OK;
-  const size_t n = (size_t)(hi + 1) * TCLK_W * 2;
-  HIPCHK(g, hipMemcpy(g->htclk, g->tclk, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  for (int it = lo; it <= hi; ++it) {
+// adds the stamps of the last copy (waits for it if it is still in flight)
+int timed_flush(nf_grid* g) {
+  if (!g->tclk_pending) return NF_OK;
+  g->tclk_pending = 0;
+  HIPCHK(g, hipEventSynchronize(g->tclk_ev));
+  for (int it = g->tclk_lo; it <= g->tclk_hi; ++it) {
     unsigned long long t0 = ~0ULL, t1 = 0;
     for (int w = 0; w < TCLK_W; ++w) {
       const unsigned long long a = g->htclk[2 * ((size_t)it * TCLK_W + w)], b = g->htclk[2 * ((size_t)it * TCLK_W + w) + 1];
@@ -144,6 +141,24 @@ int timed_collect(nf_grid* g, int conv_at) {
     g->timed_ms += (double)(t1 - t0) / g->wall_khz;
     g->timed_count++;
   }
+  return NF_OK;
+}
+// after a PCG loop whose stop iteration is known; flux and div of iteration it
+// did work iff it < conv_at, the update stamped with it iff 1 <= it <= conv_at
+int timed_collect(nf_grid* g, int conv_at) {
+  if (g->timed < 0) return NF_OK;
+  int rc = timed_flush(g);
+  if (rc) return rc;
+  const int lo = g->timed == NF_KERNEL_COL_UPDATE ? 1 : 0;
+  int hi = g->timed == NF_KERNEL_COL_UPDATE ? conv_at : conv_at - 1;
+  if (hi > TCLK_CAP - 1) hi = TCLK_CAP - 1;
+  if (hi < lo) return NF_OK;
+  const size_t n = (size_t)(hi + 1) * TCLK_W * 2;
+  HIPCHK(g, hipMemcpyAsync(g->htclk, g->tclk, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipEventRecord(g->tclk_ev, g->stream));
+  g->tclk_lo = lo;
+  g->tclk_hi = hi;
+  g->tclk_pending = 1;
   return NF_OK;
 }
 
@@ -185,7 +200,7 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
   if (rc) return rc;
   int it = 0;
   int slot = 0, pending = -1;
-  bool first_chunk = true;
+  bool first_chunk = true, stopped = false;
   while (it < max_iter) {
     // up to one iteration short of the last solve's count, then one iteration per
     // chunk: the host polls one chunk behind, so at most about one chunk of
@@ -244,13 +259,23 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
     HIPCHK(g, hipEventRecord(g->ev[slot], s));
     if (pending >= 0) {
       HIPCHK(g, hipEventSynchronize(g->ev[pending]));
-      if (g->hst[pending].conv_at != INT_MAX) break;
+      if (g->hst[pending].conv_at != INT_MAX) {
+        stopped = true;
+        break;
+      }
     }
     pending = slot;
     slot ^= 1;
   }
-  rc = read_status(g, fin);
-  if (rc) return rc;
+  if (stopped) {
+    // Once conv_at is set no later kernel of the loop writes the status, so the
+    // copy that showed the stop is final: no need to wait for the queued tail
+    // (no-op launches), and the caller's next launches queue behind it.
+    *fin = g->hst[pending];
+  } else {
+    rc = read_status(g, fin);
+    if (rc) return rc;
+  }
   if ((rc = timed_collect(g, fin->conv_at))) return rc;
   return NF_OK;
 }
@@ -541,6 +566,9 @@ const char* nf_last_error(const nf_grid* g) { return g ? g->err.c_str() : create
 
 int nf_set_stream(nf_grid* g, void* stream) {
   if (!g) return NF_EINVAL;
+  // A solve returns with its last no-op launches still queued; they must run
+  // before work of the handle on another stream touches the workspace.
+  if ((hipStream_t)stream != g->stream) HIPCHK(g, hipStreamSynchronize(g->stream));
   g->stream = (hipStream_t)stream;
   return NF_OK;
 }
@@ -678,10 +706,16 @@ int nf_set_inner_tolerance(nf_grid* g, double floor_rtol) {
 
 int nf_time_kernel(nf_grid* g, int which) {
   if (!g || which < -1 || which > NF_KERNEL_COL_UPDATE) return NF_EINVAL;
+  if (g->tclk_pending) {
+    // stamps of the previous setting still in flight: let the copy land, drop them
+    HIPCHK(g, hipEventSynchronize(g->tclk_ev));
+    g->tclk_pending = 0;
+  }
   if (which >= 0 && !g->tclk) {
     const size_t nb = 2 * sizeof(unsigned long long) * TCLK_CAP * TCLK_W;
     HIPCHK(g, hipMalloc((void**)&g->tclk, nb));
     HIPCHK(g, hipHostMalloc((void**)&g->htclk, nb, hipHostMallocDefault));
+    HIPCHK(g, hipEventCreateWithFlags(&g->tclk_ev, hipEventDisableTiming));
     int khz = 0;
     HIPCHK(g, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
     if (khz <= 0) return fail(g, NF_EDEVICE, "device wall-clock rate unavailable");
@@ -697,6 +731,8 @@ int nf_time_kernel(nf_grid* g, int which) {
 
 int nf_time_kernel_read(nf_grid* g, double* total_ms, int64_t* count) {
   if (!g || !total_ms || !count) return NF_EINVAL;
+  const int rc = timed_flush(g);
+  if (rc) return rc;
   *total_ms = g->timed_ms;
   *count = g->timed_count;
   return NF_OK;
@@ -714,6 +750,7 @@ int nf_destroy_grid(nf_grid* g) {
   if (g->hst) (void)hipHostFree(g->hst);
   if (g->tclk) (void)hipFree(g->tclk);
   if (g->htclk) (void)hipHostFree(g->htclk);
+  if (g->tclk_ev) (void)hipEventDestroy(g->tclk_ev);
   for (int i = 0; i < 2; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
   delete g;

@@ -51,6 +51,8 @@ struct nf_grid {
   int step_energy = 0;  // nf_step evaluates E_h(m^k) (nf_set_step_energy)
   unsigned long long* tclk = nullptr;   // device, 2 * TCLK_CAP
   unsigned long long* htclk = nullptr;  // pinned copy
+  hipEvent_t tclk_ev = nullptr;         // marks the completion of the last stamp copy
+  int tclk_pending = 0, tclk_lo = 0, tclk_hi = -1;  // iterations of that copy not yet added
   double wall_khz = 0.0;                // device wall-clock ticks per ms
   double timed_ms = 0.0;
   int64_t timed_count = 0;
