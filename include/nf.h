@@ -117,8 +117,7 @@ typedef struct {
  * 3D; with NF_F32_REFINED also 6 (3D: 7) single-precision half-spectrum
  * fields and FP32 copies of m and r) on the current HIP device.
  * Layouts of the caller's fields: 2D p, r, S [Ny][Nx], m [2][Ny][Nx]; 3D
- * p, r, S [Nz][Ny][Nx], m [3][Nz][Ny][Nx]; x fastest.  On 3D handles
- * nf_step_adjoint returns NF_EINVAL (it is implemented for 2D grids only).
+ * p, r, S [Nz][Ny][Nx], m [3][Nz][Ny][Nx]; x fastest.
  * The first handle of a 2D shape and precision in a process also tunes the
  * tiles of the PCG loop (see nf_set_autotune).  Returns NF_EINVAL, NF_ENOMEM
  * or NF_EDEVICE on failure (*out is then NULL).
@@ -240,12 +239,15 @@ int nf_energy(nf_grid *g, const nf_params *prm, const double *m, const double *p
  *   the gradient grad p, and the pressure equation (eq. p_discrete): since the
  *   operator A is symmetric, the adjoint pressure mu solves A mu = Pi G^T lam_g
  *   with the same PCG as nf_pressure_solve.
- * Inputs (device, layouts as above): m = m^k [2][Ny][Nx], p = p[m^k] (as
- * returned by nf_step for that step), r, S, lam_next [2][Ny][Nx].
- * Outputs: lam_k [2][Ny][Nx] = dL/dm^k (overwritten); grad_r, grad_S [Ny][Nx]
- * are ACCUMULATED (+=) with this step's dL/dr and dL/dS; mu [Ny][Nx] is the
- * adjoint pressure (in: warm start, out: solution).  rtol/max_iter as in
- * nf_pressure_solve; info may be NULL.
+ * Inputs (device, layouts as above): m = m^k [d][Ny][Nx] (3D [3][Nz][Ny][Nx]),
+ * p = p[m^k] (as returned by nf_step for that step), r, S, lam_next (as m).
+ * Outputs: lam_k (as m) = dL/dm^k (overwritten); grad_r, grad_S (as p) are
+ * ACCUMULATED (+=) with this step's dL/dr and dL/dS; mu (as p) is the adjoint
+ * pressure (in: warm start, out: solution).  rtol/max_iter as in
+ * nf_pressure_solve; info may be NULL.  2D and 3D handles; on 3D handles the
+ * diffusion stage runs through the passes of the split update with activation
+ * and relaxation switched off, and the pointwise stages as passes over physical
+ * fields.
  * Returns NF_OK, NF_ENOTCONV (outputs written with the last iterate),
  * NF_ENONFINITE, NF_EINVAL or NF_EDEVICE.
  */

@@ -556,6 +556,91 @@ int energy3(nf_grid* g, const nf_params* prm, const double* m, const double* r, 
   return NF_OK;
 }
 
+// end of nf_step_adjoint: wait, report the adjoint solve, map its outcome to a code
+int adjoint_epilogue(nf_grid* g, const SolveOut& so, nf_solve_info* info) {
+  DevStatus fin;
+  int rc = read_status(g, &fin);
+  if (rc) return rc;
+  if (info) {
+    info->iters = so.iters;
+    info->converged = so.converged;
+    info->rel_res = so.rel_res;
+    info->true_rel_res = so.true_rel_res;
+  }
+  if ((so.flags | fin.flags) & FLAG_NONFINITE) return fail(g, NF_ENONFINITE, "non-finite values in the adjoint step");
+  if (!so.converged) return fail(g, NF_ENOTCONV, "adjoint PCG did not reach the tolerance within max_iter");
+  return NF_OK;
+}
+
+// 3D: the gradient of a physical field f as three physical fields (transforms
+// of f into spec, its gradient back through the inverse passes; mix[0..2] are
+// intermediates, out may include spec)
+int grad_phys3(nf_grid* g, const double* f, void* spec, double* const* out) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  void* const* M = g->mix;
+  LCHK(g, launch3_row_r2c(G, f, M[0], 0, s));
+  LCHK(g, launch3_ypass(G, false, 1, -1, M[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+  LCHK(g, launch3_zfwd(G, M[0], spec, 0, s));
+  LCHK(g, launch3_zinv(G, 2, spec, nullptr, M[0], M[1], M[2], s));
+  LCHK(g, launch3_ypass(G, false, 3, +1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+  for (int c = 0; c < 3; ++c) LCHK(g, launch3_row_c2r(G, M[c], out[c], s));
+  return NF_OK;
+}
+
+// Adjoint of one 3D step: the 2D sequence with a third component, the pointwise
+// parts as grid-stride passes over physical fields.
+int step_adjoint3(nf_grid* g, const nf_params* prm, double dt, const double* m, const double* p, const double* r,
+                  const double* lam_next, double* lam_k, double* grad_r, double* grad_S, double* mu, double rtol,
+                  int max_iter, bool want_true, SolveOut* so) {
+  const Geo& G = g->geo;
+  hipStream_t s = g->stream;
+  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  void* const* M = g->mix;
+  const double D2dt = prm->D2 * dt;
+  // diffusion stage (H symmetric): lam_k = H lam_next through the passes of the
+  // split update with activation and relaxation switched off (c^2 = 0, gamma = 1
+  // with factor 1) and a zero pressure (its scratch output goes to qh)
+  HIPCHK(g, hipMemcpyAsync(lam_k, lam_next, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  LCHK(g, launch_zero_doubles((double*)g->xh, n, s));
+  LCHK(g, launch3_zinv(G, 3, g->xh, M[0], M[1], M[2], M[3], s));
+  LCHK(g, launch3_ypass(G, false, 4, +1, M[0], M[1], M[2], M[3], -1, 0, 0.0, -1.0, s));
+  LCHK(g, launch3_row_split(G, M[0], M[1], M[2], M[3], lam_k, (double*)g->qh, 0.0, 1.0, dt, 1.0, D2dt, s));
+  LCHK(g, launch3_ypass(G, false, 3, -1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, D2dt, s));
+  LCHK(g, launch3_zheat(G, M[0], M[1], M[2], D2dt, s));
+  LCHK(g, launch3_ypass(G, false, 3, +1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+  LCHK(g, launch3_row_final(G, M[0], M[1], M[2], lam_k, s));
+  // grad p^k, then the reverse of relaxation and activation: lam_k <- lam_m, Gp <- lam_g
+  double* Gp[3] = {(double*)g->rh, (double*)g->dh, (double*)g->qh};
+  int rc = grad_phys3(g, p, g->bh, Gp);
+  if (rc) return rc;
+  LCHK(g, launch3_adj1(G, m, lam_k, Gp[0], Gp[1], Gp[2], prm->c2 * dt, prm->gamma, dt, std::exp(-dt), s));
+  // adjoint pressure: A mu = Pi G^T lam_g, b_hat = -i xi_tilde . F(lam_g)
+  void* F[3] = {g->xh, M[1], M[2]};
+  for (int c = 0; c < 3; ++c) {
+    LCHK(g, launch3_row_r2c(G, Gp[c], M[0], 0, s));
+    LCHK(g, launch3_ypass(G, false, 1, -1, M[0], nullptr, nullptr, nullptr, -1, 0, 0.0, -1.0, s));
+    LCHK(g, launch3_zfwd(G, M[0], F[c], 0, s));
+  }
+  LCHK(g, launch3_spec_divrhs(G, F[0], F[1], F[2], g->bh, s));
+  // S does not enter: the compatibility totals of the solve's check are cleared
+  LCHK(g, launch_zero_doubles(G.tot + SLOT_SCHK * SLOT_K, 2, s));
+  rc = pcg(g, m, r, X_FROM_P, mu, rtol, max_iter, want_true, so);
+  if (rc) return rc;
+  // mu, grad mu (rh, dh, qh) and grad p^k again (xh, mix[3], bh)
+  rc = write_p(g, mu);
+  if (rc) return rc;
+  LCHK(g, launch3_zinv(G, 2, g->xh, nullptr, M[0], M[1], M[2], s));
+  LCHK(g, launch3_ypass(G, false, 3, +1, M[0], M[1], M[2], nullptr, -1, 0, 0.0, -1.0, s));
+  double* U[3] = {(double*)g->rh, (double*)g->dh, (double*)g->qh};
+  for (int c = 0; c < 3; ++c) LCHK(g, launch3_row_c2r(G, M[c], U[c], s));
+  double* P[3] = {(double*)g->xh, (double*)M[3], (double*)g->bh};
+  rc = grad_phys3(g, p, g->bh, P);
+  if (rc) return rc;
+  LCHK(g, launch3_adj2(G, m, mu, U[0], U[1], U[2], P[0], P[1], P[2], lam_k, grad_r, grad_S, s));
+  return NF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1034,11 +1119,16 @@ int nf_step_adjoint(nf_grid* g, const nf_params* prm, double dt, const double* m
   rc = check_params(g, prm, dt);
   if (rc) return rc;
   if (!(rtol >= 0.0) || max_iter < 0) return fail(g, NF_EINVAL, "rtol must be >= 0 and max_iter >= 0");
-  if (g->dim != 2) return fail(g, NF_EINVAL, "nf_step_adjoint is available for 2D grids only");
   const Geo& G = g->geo;
   hipStream_t s = g->stream;
   const size_t n = (size_t)g->nx * g->ny;
   LCHK(g, launch_status_reset(G, 1, s));
+  if (g->dim == 3) {
+    SolveOut so3;
+    rc = step_adjoint3(g, prm, dt, m, p, r, lam_next, lam_k, grad_r, grad_S, mu, rtol, max_iter, info != nullptr, &so3);
+    if (rc) return rc;
+    return adjoint_epilogue(g, so3, info);
+  }
   // adjoint through the diffusion stage: H lam (H symmetric)
   LCHK(g, launch_row_r2c(G, lam_next, g->mix[0], nullptr, s));
   LCHK(g, launch_row_r2c(G, lam_next + n, g->mix[1], nullptr, s));
@@ -1061,18 +1151,7 @@ int nf_step_adjoint(nf_grid* g, const nf_params* prm, double dt, const double* m
   LCHK(g, launch_row_r2c(G, p, g->rh, nullptr, s));
   LCHK(g, launch_col_fwd(G, g->rh, g->dh, 1, g->rh, g->qh, s));
   LCHK(g, launch_row_adj2(G, g->mix[1], g->mix[2], g->rh, g->qh, m, mu, lam_k, grad_r, grad_S, s));
-  DevStatus fin;
-  rc = read_status(g, &fin);
-  if (rc) return rc;
-  if (info) {
-    info->iters = so.iters;
-    info->converged = so.converged;
-    info->rel_res = so.rel_res;
-    info->true_rel_res = so.true_rel_res;
-  }
-  if ((so.flags | fin.flags) & FLAG_NONFINITE) return fail(g, NF_ENONFINITE, "non-finite values in the adjoint step");
-  if (!so.converged) return fail(g, NF_ENOTCONV, "adjoint PCG did not reach the tolerance within max_iter");
-  return NF_OK;
+  return adjoint_epilogue(g, so, info);
 }
 
 int nf_energy(nf_grid* g, const nf_params* prm, const double* m, const double* p, const double* r, const double* S,

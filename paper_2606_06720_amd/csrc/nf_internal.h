@@ -241,6 +241,16 @@ hipError_t launch3_copy_tot(const Geo& g, int slot, int K, int o, hipStream_t s)
 hipError_t launch3_energy_pt(const Geo& g, const double* m, const double* r, const double* gx, const double* gy,
                              const double* gz, double gamma, hipStream_t s);
 hipError_t launch3_spec_gradnorm(const Geo& g, const void* F0, const void* F1, const void* F2, hipStream_t s);
+// adjoint of one 3D step (grid-stride passes): reverse of activation and
+// relaxation (lam in: after diffusion, out: lam_m; G in: grad p, out: lam_g),
+// the right-hand side -i xi_tilde . F(v) of the adjoint pressure from three
+// spectra, and the final gradient terms (U = grad mu, P = grad p)
+hipError_t launch3_adj1(const Geo& g, const double* m, double* lam, double* G0, double* G1, double* G2, double c2dt,
+                        double gamma, double dt, double relax1, hipStream_t s);
+hipError_t launch3_spec_divrhs(const Geo& g, const void* F0, const void* F1, const void* F2, void* bh, hipStream_t s);
+hipError_t launch3_adj2(const Geo& g, const double* m, const double* mu, const double* U0, const double* U1,
+                        const double* U2, const double* P0, const double* P1, const double* P2, double* lam,
+                        double* grad_r, double* grad_S, hipStream_t s);
 // g.tot of a slot from the n partials the passes of the PCG loop store (one
 // workgroup; K = 1 or 7 arrays)
 hipError_t launch3_sum_tot(const Geo& g, int slot, int K, int n, hipStream_t s);

@@ -978,6 +978,116 @@ __global__ void __launch_bounds__(256) k3_spec_gradnorm(Geo g, const cd* __restr
   store_partials<256, 1>(s, g, SLOT_EGM, red);
 }
 
+// ================================================================ adjoint (grid-stride, physical/spectral)
+// phi1'(z) = (e^z (z - 1) + 1) / z^2, by its Taylor series near 0
+static __device__ __forceinline__ double dphi1_3(double z) {
+  if (fabs(z) < 1e-3) return 0.5 + z * (1.0 / 3.0 + z * (0.125 + z * (1.0 / 30.0)));
+  return (expm1(z) * (z - 1.0) + z) / (z * z);
+}
+
+// Reverse of activation then relaxation at one grid point (m, g = grad p^k and
+// lam = the adjoint after the diffusion stage, three components each): lam_m
+// (through both stages) and lam_g (of g), as the 2D adjoint with a third
+// component.
+static __device__ __forceinline__ void adjoint_point3(const double (&m)[3], const double (&g)[3], const double (&l)[3],
+                                                      double c2dt, double gamma, double dt, double relax1,
+                                                      double (&lm)[3], double (&lg)[3]) {
+  const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  const double z = c2dt * g2;
+  const double kap = c2dt * (z > 0.0 ? expm1(z) / z : 1.0);
+  const double dkap = c2dt * dphi1_3(z);
+  const double gm = g[0] * m[0] + g[1] * m[1] + g[2] * m[2];
+  double sv[3];
+  for (int c = 0; c < 3; ++c) sv[c] = fma(kap * gm, g[c], m[c]);  // m*
+  // relaxation Jacobian (symmetric): fac (I - u u^T) + rho'(s) u u^T, u = m*/|m*|
+  double a[3];
+  if (gamma == 1.0) {
+    for (int c = 0; c < 3; ++c) a[c] = relax1 * l[c];
+  } else {
+    const double s2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+    const double e1 = 1.0 - gamma;
+    if (s2 == 0.0) {
+      for (int c = 0; c < 3; ++c) a[c] = gamma > 1.0 ? l[c] : 0.0;
+    } else {
+      const double u = 2.0 * e1 * dt * exp(-e1 * log(s2));
+      if (u >= 1.0) {
+        a[0] = a[1] = a[2] = 0.0;
+      } else {
+        const double fac = exp(log1p(-u) / (2.0 * e1));        // rho / s
+        const double drho = exp((1.0 - 2.0 * e1) * log(fac));  // rho'(s) = (s / rho)^{2e - 1}
+        const double is = 1.0 / sqrt(s2);
+        double uv[3];
+        for (int c = 0; c < 3; ++c) uv[c] = sv[c] * is;
+        const double ul = uv[0] * l[0] + uv[1] * l[1] + uv[2] * l[2];
+        for (int c = 0; c < 3; ++c) a[c] = fac * (l[c] - uv[c] * ul) + drho * ul * uv[c];
+      }
+    }
+  }
+  // activation: d m*/d m = I + kap g g^T, and the derivative in g
+  const double gl = g[0] * a[0] + g[1] * a[1] + g[2] * a[2];
+  const double t = 2.0 * c2dt * dkap * gm * gl;
+  for (int c = 0; c < 3; ++c) {
+    lm[c] = fma(kap * gl, g[c], a[c]);
+    lg[c] = t * g[c] + kap * gl * m[c] + kap * gm * a[c];
+  }
+}
+
+// lam [3][n] in: the adjoint after the diffusion stage, out: lam_m; G0..G2 in:
+// grad p^k (physical), out: lam_g
+__global__ void __launch_bounds__(256) k3_adj1(Geo g, const double* __restrict__ m, double* lam, double* G0,
+                                                double* G1, double* G2, double c2dt, double gamma, double dt,
+                                                double relax1) {
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double mv[3] = {m[i], m[n + i], m[2 * n + i]};
+    const double gv[3] = {G0[i], G1[i], G2[i]};
+    const double lv[3] = {lam[i], lam[n + i], lam[2 * n + i]};
+    double lm[3], lg[3];
+    adjoint_point3(mv, gv, lv, c2dt, gamma, dt, relax1, lm, lg);
+    lam[i] = lm[0];
+    lam[n + i] = lm[1];
+    lam[2 * n + i] = lm[2];
+    G0[i] = lg[0];
+    G1[i] = lg[1];
+    G2[i] = lg[2];
+  }
+}
+
+// Adjoint right-hand side from the spectra of v (three components, [kx][ky][kz],
+// slot kx = 0 packed): b_hat = -i xi_tilde . F(v), i.e. F(Pi G^T v) (the null
+// modes vanish with xi_tilde; the x multiplier of slot 0 is 0 on both halves)
+__global__ void __launch_bounds__(256) k3_spec_divrhs(Geo g, const cd* __restrict__ F0, const cd* __restrict__ F1,
+                                                       const cd* __restrict__ F2, cd* __restrict__ bh) {
+  const size_t ns = (size_t)g.h * g.ny * g.nz;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < ns; i += (size_t)gridDim.x * 256) {
+    const int kx = (int)(i / ((size_t)g.ny * g.nz));
+    const int rem = (int)(i % ((size_t)g.ny * g.nz));
+    const int ky = rem / g.nz, kz = rem % g.nz;
+    const double xt = xi_col(kx, g.lx), yt = xi_tilde(ky, g.ny, g.ly), zt = xi_tilde(kz, g.nz, g.lz);
+    const cd a = F0[i], b = F1[i], c = F2[i];
+    const double ax = xt * a.x + yt * b.x + zt * c.x, ay = xt * a.y + yt * b.y + zt * c.y;
+    bh[i] = mk<double>(ay, -ax);
+  }
+}
+
+// dL/dS += mu, dL/dr -= grad mu . grad p, lam -= (m.grad p) grad mu + (m.grad mu) grad p
+__global__ void __launch_bounds__(256) k3_adj2(Geo g, const double* __restrict__ m, const double* __restrict__ mu,
+                                                const double* __restrict__ U0, const double* __restrict__ U1,
+                                                const double* __restrict__ U2, const double* __restrict__ P0,
+                                                const double* __restrict__ P1, const double* __restrict__ P2,
+                                                double* lam, double* grad_r, double* grad_S) {
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double mv[3] = {m[i], m[n + i], m[2 * n + i]};
+    const double uv[3] = {U0[i], U1[i], U2[i]}, pv[3] = {P0[i], P1[i], P2[i]};
+    const double mgp = mv[0] * pv[0] + mv[1] * pv[1] + mv[2] * pv[2];
+    const double mgu = mv[0] * uv[0] + mv[1] * uv[1] + mv[2] * uv[2];
+    grad_S[i] += mu[i];
+    grad_r[i] -= uv[0] * pv[0] + uv[1] * pv[1] + uv[2] * pv[2];
+    for (int c = 0; c < 3; ++c) lam[c * n + i] -= mgp * uv[c] + mgu * pv[c];
+  }
+}
+
 // totals of the n partials of each of the K arrays of a slot, in a fixed order
 template <int K>
 __global__ void __launch_bounds__(256) k3_sum_tot(Geo g, int slot, int n) {
@@ -1233,6 +1343,28 @@ hipError_t launch3_zrefine_acc(const Geo& g, void* x64, const void* x32, void* G
 }
 // workgroups of the grid-stride energy passes (at most the partial-sum stride)
 static int nwg3_energy(const Geo& g) { return g.pstride < 1024 ? g.pstride : 1024; }
+static int nwg3_pt(size_t n) {
+  const size_t b = (n + 255) / 256;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+hipError_t launch3_adj1(const Geo& g, const double* m, double* lam, double* G0, double* G1, double* G2, double c2dt,
+                        double gamma, double dt, double relax1, hipStream_t s) {
+  hipLaunchKernelGGL(k3_adj1, dim3(nwg3_pt((size_t)g.nx * g.ny * g.nz)), dim3(256), 0, s, g, m, lam, G0, G1, G2, c2dt,
+                     gamma, dt, relax1);
+  return hipGetLastError();
+}
+hipError_t launch3_spec_divrhs(const Geo& g, const void* F0, const void* F1, const void* F2, void* bh, hipStream_t s) {
+  hipLaunchKernelGGL(k3_spec_divrhs, dim3(nwg3_pt((size_t)g.h * g.ny * g.nz)), dim3(256), 0, s, g, (const cd*)F0,
+                     (const cd*)F1, (const cd*)F2, (cd*)bh);
+  return hipGetLastError();
+}
+hipError_t launch3_adj2(const Geo& g, const double* m, const double* mu, const double* U0, const double* U1,
+                        const double* U2, const double* P0, const double* P1, const double* P2, double* lam,
+                        double* grad_r, double* grad_S, hipStream_t s) {
+  hipLaunchKernelGGL(k3_adj2, dim3(nwg3_pt((size_t)g.nx * g.ny * g.nz)), dim3(256), 0, s, g, m, mu, U0, U1, U2, P0,
+                     P1, P2, lam, grad_r, grad_S);
+  return hipGetLastError();
+}
 hipError_t launch3_energy_pt(const Geo& g, const double* m, const double* r, const double* gx, const double* gy,
                              const double* gz, double gamma, hipStream_t s) {
   const int nwg = nwg3_energy(g);

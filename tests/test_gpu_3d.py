@@ -213,7 +213,7 @@ def test_3d_error_paths(env):
         assert abs(info.rel_res - info_or.rel_res) <= 1e-12 * info_or.rel_res
         with pytest.raises(NF.NfError) as e:
             lam = Z((3,) + n[::-1])
-            g.step_adjoint(1.0, 1e-3, 0.75, 1e-3, T(m), p, T(r), T(S), lam, Z((3,) + n[::-1]), Z(n[::-1]),
+            g.step_adjoint(1.0, 1e-3, 0.75, -1e-3, T(m), p, T(r), T(S), lam, Z((3,) + n[::-1]), Z(n[::-1]),
                            Z(n[::-1]), Z(n[::-1]))
         assert e.value.code == NF.NF_EINVAL
         with pytest.raises(NF.NfError) as e:
@@ -284,3 +284,53 @@ def test_step_energy_3d_matches_oracle(env):
             want = O.energy(mo, p_k, r, c2, D2, gamma, L)[0]
             assert si.energy_valid and abs(si.energy - want) <= 1e-10 * abs(want), (k, si.energy, want)
             mo, _, _ = O.step(mo, p_k, r, S, c2, D2, gamma, dt, 1e-12, 4000, L)
+
+
+@pytest.mark.parametrize("gamma", [0.75, 1.0, 1.25])
+def test_step_adjoint_3d_matches_oracle(env, gamma):
+    """nf_step_adjoint on a 3D handle (non-cubic grid and box) against the
+    oracle's adjoint of one step, which is written for any dimension."""
+    NF, T, Z, torch = env
+    n, L = (16, 8, 32), (1.0, 0.5, 2.0)
+    rng = np.random.default_rng(67)
+    sh = n[::-1]
+    m = rng.uniform(0.2, 1.0, (3,) + sh)
+    r = rng.uniform(0.05, 0.15, sh)
+    S = rng.standard_normal(sh)
+    S -= S.mean()
+    lam = rng.standard_normal((3,) + sh)
+    c2, D2, dt = 30.0, 2e-3, 2e-3
+    p, _ = O.pressure_pcg(m, r, S, None, 1e-13, 4000, L)
+    lk, dr, dS, mu, _ = O.step_adjoint(m, p, r, S, c2, D2, gamma, dt, lam, rtol=1e-13, max_iter=4000, L=L)
+    with NF.Grid(n, L) as g:
+        lam_k = Z((3,) + sh)
+        gr = torch.full(sh, 0.5, dtype=torch.float64, device="cuda:0")   # accumulated into
+        gS, mug = Z(sh), Z(sh)
+        rc, info = g.step_adjoint(c2, D2, gamma, dt, T(m), T(p), T(r), T(S), T(lam), lam_k, gr, gS, mug,
+                                  rtol=1e-13, max_iter=4000)
+    assert info.converged
+    assert rel(lam_k.cpu().numpy(), lk) <= 1e-9
+    assert rel(gr.cpu().numpy() - 0.5, dr) <= 1e-9
+    assert rel(gS.cpu().numpy(), dS) <= 1e-9
+    assert rel(mug.cpu().numpy(), mu) <= 1e-9
+
+
+def test_checkpointed_gradient_3d_matches_oracle(env):
+    """The checkpointed reverse sweep (adjoint.run_gradient) on a 3D handle
+    against the oracle's stored-state sweep."""
+    from paper_2606_06720_amd import adjoint as A
+
+    NF, T, Z, torch = env
+    w = W.bump_workload(16, ndim=3)
+    prm = (w["c2"], w["D2"], w["gamma"])
+    steps = 5
+    m_tgt = O.run(w["m0"], None, w["r"] * 1.5, 1.2 * w["S"], *prm, w["dt"], max_steps=steps, rtol=1e-13,
+                  max_iter=4000, L=w["L"])[0]
+    l_or, gr_or, gS_or = O.run_gradient(w["m0"], w["r"], w["S"], *prm, w["dt"], steps, m_tgt, rtol=1e-13,
+                                        max_iter=4000, L=w["L"])
+    with NF.Grid(w["n"], w["L"]) as g:
+        loss, gr, gS = A.run_gradient(g, prm, w["dt"], steps, T(w["m0"]), T(w["r"]), T(w["S"]), T(m_tgt),
+                                      rtol=1e-13, max_iter=4000, stride=2)
+    assert abs(loss - l_or) <= 1e-8 * l_or
+    assert rel(gr.cpu().numpy(), gr_or) <= 1e-7
+    assert rel(gS.cpu().numpy(), gS_or) <= 1e-7
