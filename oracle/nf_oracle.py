@@ -62,7 +62,8 @@ Pins (tests/test_oracle_pins.py; each is something other than this code)
 * dm_rel: hand-worked example (golden file) and the closed form |a - 1| / dt
   for m^k = a m^{k-1};
 * run: stopping criteria, energy decrease for small dt;
-* step_adjoint, run_gradient: central differences of the forward map.
+* step_adjoint, run_gradient: central differences of the forward map (step_adjoint
+  in 2D and 3D).
 """
 
 from __future__ import annotations

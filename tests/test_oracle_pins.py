@@ -492,6 +492,38 @@ def test_step_adjoint_matches_central_differences(gamma):
         assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3 * abs(fd_m))
 
 
+@pytest.mark.parametrize("gamma", [0.75, 1.0, 1.25])
+def test_step_adjoint_3d_matches_central_differences(gamma):
+    # the same reverse of one step with m in R^3 on a non-cubic grid and box,
+    # against central differences of the forward step
+    rng = np.random.default_rng(71)
+    n, L = (8, 16, 8), (1.0, 2.0, 0.5)
+    sh = n[::-1]
+    m = rng.uniform(0.2, 1.0, (3,) + sh)
+    r = rng.uniform(0.05, 0.15, sh)
+    S = rng.standard_normal(sh)
+    S -= S.mean()
+    c2, D2, dt = 30.0, 2e-3, 2e-3
+    lam = rng.standard_normal((3,) + sh)
+
+    def F(m_, r_, S_):
+        p_, _ = O.pressure_pcg(m_, r_, S_, None, 1e-14, 4000, L)
+        return float(np.sum(lam * O.split_update(m_, p_, c2, D2, gamma, dt, L)))
+
+    p, _ = O.pressure_pcg(m, r, S, None, 1e-14, 4000, L)
+    lk, dr, dS, mu, info = O.step_adjoint(m, p, r, S, c2, D2, gamma, dt, lam, rtol=1e-14, L=L)
+    vm = rng.standard_normal((3,) + sh)
+    vr = rng.standard_normal(sh)
+    vS = rng.standard_normal(sh)
+    vS -= vS.mean()
+    h = 1e-6
+    fd_m = _fd(lambda x: F(x, r, S), m, vm, h)
+    fd_r = _fd(lambda x: F(m, x, S), r, vr, h)
+    fd_S = _fd(lambda x: F(m, r, x), S, vS, h)
+    for fd, ad in ((fd_m, np.sum(lk * vm)), (fd_r, np.sum(dr * vr)), (fd_S, np.sum(dS * vS))):
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3 * abs(fd_m))
+
+
 def test_relaxation_and_activation_derivative_pieces():
     # phi1' by its Taylor series near 0 joins the closed form continuously
     z = np.array([0.0, 1e-8, 9.99e-4, 1.001e-3, 0.3, 2.0])
