@@ -601,7 +601,8 @@ int step_adjoint3(nf_grid* g, const nf_params* prm, double dt, const double* m, 
   // diffusion stage (H symmetric): lam_k = H lam_next through the passes of the
   // split update with activation and relaxation switched off (c^2 = 0, gamma = 1
   // with factor 1) and a zero pressure (its scratch output goes to qh)
-  HIPCHK(g, hipMemcpyAsync(lam_k, lam_next, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (lam_k != lam_next)
+    HIPCHK(g, hipMemcpyAsync(lam_k, lam_next, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   LCHK(g, launch_zero_doubles((double*)g->xh, n, s));
   LCHK(g, launch3_zinv(G, 3, g->xh, M[0], M[1], M[2], M[3], s));
   LCHK(g, launch3_ypass(G, false, 4, +1, M[0], M[1], M[2], M[3], -1, 0, 0.0, -1.0, s));
