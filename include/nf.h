@@ -383,6 +383,7 @@ typedef struct {
   int candidates[3];  /* operator middle, operator end, update */
   double us[3];
   double us_default[3];
+  int flux_threads;   /* operator middle: threads per workgroup */
 } nf_tuning_info;
 int nf_set_autotune(int mode);
 int nf_tuning(const nf_grid *g, nf_tuning_info *out);
@@ -390,11 +391,13 @@ int nf_tuning(const nf_grid *g, nf_tuning_info *out);
  * Fix the variants of one handle (2D), overriding the tuner: variant code v
  * selects half (v % 3 == 0), the default (1) or twice (2) the default rows
  * (operator middle) or columns (operator end, update) per workgroup; v / 3
- * selects the radix plan (0: radix-8 stages first, 1: radix-4 first) and, for
- * the operator end and update only, v / 3 = 2 or 3 the first plan with twice
- * or four times the threads.  Codes: operator middle [0, 5], the others
- * [0, 11]; 1 is the untuned pass, -1 keeps the current one.  NF_EINVAL if a
- * variant does not exist for the grid and precision.
+ * selects the radix plan (0: radix-8 stages first, 1: radix-4 first); for the
+ * operator middle v / 3 = 2 is the first plan with half the threads (only
+ * where the tile would have 1024 threads), for the operator end and update
+ * v / 3 = 2 or 3 the first plan with twice or four times the threads.  Codes:
+ * operator middle [0, 8], the others [0, 11]; 1 is the untuned pass, -1 keeps
+ * the current one.  NF_EINVAL if a variant does not exist for the grid and
+ * precision.
  */
 int nf_set_tiles(nf_grid *g, int flux_var, int div_var, int update_var);
 

@@ -269,6 +269,8 @@ bool div_var_valid(const Geo& g, bool f32, int cv);
 int rr_nwg(const Geo& g, bool f32);
 // rows per workgroup of row variant rv, columns per workgroup of column variant cv
 int flux_var_rows(const Geo& g, int rv);
+int flux_var_threads(const Geo& g, int rv);
+int flux_var_plan(int rv);
 int div_var_cols(const Geo& g, int cv);
 int div_var_threads(const Geo& g, int cv);
 // whether the grid sizes have tuned variants at all

@@ -1503,6 +1503,12 @@ int rr_nwg(const Geo& g, bool f32) { return col_nwg_var(g, use_cvu(g, f32)); }
 int flux_var_rows(const Geo& g, int rv) {
   return rv == VAR_DEFAULT ? tile_rows(g.nx / 2, row_tile(g.nx, 2)) : rv_rows(g.nx, rv);
 }
+int flux_var_plan(int rv) { return rv_plan(rv); }
+int flux_var_threads(const Geo& g, int rv) {
+  const int rt = rv == VAR_DEFAULT ? row_tile(g.nx, 2) : rv_rows(g.nx, rv) * (g.nx / 2);
+  const int nt = (rt / 8) * 2 > 1024 ? 1024 : (rt / 8) * 2;
+  return nt / (rv == VAR_DEFAULT ? 1 : rv_td(rv));
+}
 int div_var_cols(const Geo& g, int cv) { return cv == VAR_DEFAULT ? col_cols(g.ny) : cv_cols(g.ny, cv); }
 int div_var_threads(const Geo& g, int cv) { return 2 * TPF * (cv == VAR_DEFAULT ? 1 : cv_tm(cv)); }
 bool var_grid(const Geo& g) { return g.nz == 1 && (var_size(g.nx) || var_size(g.ny)); }

@@ -37,15 +37,16 @@ __host__ __device__ constexpr int tile_rows(int h, int t) { return t / h < 1 ? 1
 // passes over three and four fields keep TILE.
 __host__ __device__ constexpr int row_tile(int nx, int nf) { return (nf <= 2 && nx >= 4096) ? nx : TILE; }
 
-template <int NX, int NF, int RT = TILE, int PL = 0>
+template <int NX, int NF, int RT = TILE, int PL = 0, int TD = 1>
 struct RowCfg {
   static constexpr int H = NX / 2;
   static constexpr int R = tile_rows(H, RT);                    // rows per workgroup
   static constexpr int NFv = NF;
   static constexpr int PLAN = PL;                               // radix plan of the x transforms
   // one radix-8 butterfly per thread, at most 1024 threads (wider tiles give
-  // each thread several butterflies per stage)
-  static constexpr int NT = (RT / 8) * NF > 1024 ? 1024 : (RT / 8) * NF;
+  // each thread several butterflies per stage); TD divides the thread count
+  // (each thread then runs TD times the butterflies)
+  static constexpr int NT = ((RT / 8) * NF > 1024 ? 1024 : (RT / 8) * NF) / TD;
   // LDS line stride: room for the FFT's padded layout, rounded so that the R
   // rows a group of 8 lanes touches in the row-interleaved phases (transposed
   // and paired loads and stores, consecutive lanes running over the rows of
@@ -81,7 +82,9 @@ struct ColCfg {
 // The PCG-loop passes (operator middle, operator end, update) come in variants
 // that a run-time tuner chooses between per grid shape and real type:
 //   row variant rv (operator middle): rows per workgroup RD/2, RD or 2 RD for
-//     rv % 3 = 0, 1, 2 (RD the default rows of Row2D<NX, 2>), radix plan rv / 3;
+//     rv % 3 = 0, 1, 2 (RD the default rows of Row2D<NX, 2>); rv / 3 = 0: radix
+//     plan 0, 1: plan 1, 2: plan 0 with half the threads, for tiles that would
+//     have 1024 threads (whose 128-register limit per thread makes them spill);
 //   column variant cv (operator end, update): columns per workgroup CD/2, CD or
 //     2 CD for cv % 3 = 0, 1, 2 (CD the default of ColCfg<NY, 2>); cv / 3 = 0:
 //     radix plan 0, 1: plan 1, 2 and 3: plan 0 with twice and four times the
@@ -90,7 +93,7 @@ struct ColCfg {
 // Variant 1 (default tile, plan 0) is the untuned pass.  Variants that would
 // repeat another (a radix plan without an alternative), fall below one row or
 // column, leave threads without a radix-8 butterfly, or exceed the LDS of a
-// workgroup do not exist.  Row variants use the codes below 6 only.
+// workgroup do not exist.  Row variants use the codes below 9 only.
 enum { LDS_LIMIT = 160 * 1024 };  // VAR_DEFAULT, NVAR: nf_internal.h
 
 __host__ __device__ constexpr int rv_rows(int nx, int rv) {
@@ -112,9 +115,12 @@ __host__ __device__ constexpr int div_lds(int ny, int cols, int es) {
 }
 __host__ __device__ constexpr int cv_plan(int cv) { return cv / 3 == 1 ? 1 : 0; }
 __host__ __device__ constexpr int cv_tm(int cv) { return cv / 3 == 2 ? 2 : (cv / 3 == 3 ? 4 : 1); }
+__host__ __device__ constexpr int rv_plan(int rv) { return rv / 3 == 1 ? 1 : 0; }
+__host__ __device__ constexpr int rv_td(int rv) { return rv / 3 == 2 ? 2 : 1; }
 __host__ __device__ constexpr bool rv_ok(int nx, int ny, int rv, int es) {
-  return rv >= 0 && rv < 6 && (rv / 3 == 0 || plan_has_alt(ilog2(nx / 2))) && rv_rows(nx, rv) >= 1 &&
+  return rv >= 0 && rv < 9 && (rv / 3 != 1 || plan_has_alt(ilog2(nx / 2))) && rv_rows(nx, rv) >= 1 &&
          rv_rows(nx, rv) <= 64 && (rv % 3 != 2 || rv_rows(nx, rv) <= ny) &&
+         (rv / 3 != 2 || rv_rows(nx, rv) * (nx / 2) / 8 * 2 >= 1024) &&
          flux_lds(nx, rv_rows(nx, rv), es) + 4096 <= LDS_LIMIT;
 }
 __host__ __device__ constexpr bool cv_ok(int ny, int h, int cv, int es) {
@@ -127,7 +133,7 @@ __host__ __device__ constexpr bool var_size(int n) { return n >= 256 && n <= 409
 // configurations of the variants (the default is exactly the untuned tile)
 template <int NX, int RV>
 using FluxCfg = typename std::conditional<RV == VAR_DEFAULT, Row2D<NX, 2>,
-                                          RowCfg<NX, 2, rv_rows(NX, RV) * (NX / 2), RV / 3>>::type;
+                                          RowCfg<NX, 2, rv_rows(NX, RV) * (NX / 2), rv_plan(RV), rv_td(RV)>>::type;
 template <int NY, int CV>
 using DivCfg = typename std::conditional<CV == VAR_DEFAULT, ColCfg<NY, 2>,
                                          ColCfg<NY, 2, cv_cols(NY, CV) * NY, cv_plan(CV), cv_tm(CV)>>::type;

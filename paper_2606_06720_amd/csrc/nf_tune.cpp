@@ -311,7 +311,8 @@ int nf_tuning(const nf_grid* g, nf_tuning_info* out) {
   const int vf = G.var_flux[k], vd = G.var_div[k], vu = G.var_upd[k];
   out->tuned = g->tuned;
   out->flux_rows = nf::flux_var_rows(G, vf);
-  out->flux_plan = vf / 3;
+  out->flux_plan = nf::flux_var_plan(vf);
+  out->flux_threads = nf::flux_var_threads(G, vf);
   out->div_cols = nf::div_var_cols(G, vd);
   out->div_plan = vd / 3 == 1 ? 1 : 0;
   out->div_threads = nf::div_var_threads(G, vd);

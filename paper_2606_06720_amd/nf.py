@@ -77,7 +77,7 @@ class nf_tuning_info(ctypes.Structure):
                 ("div_cols", ctypes.c_int), ("div_plan", ctypes.c_int), ("div_threads", ctypes.c_int),
                 ("update_cols", ctypes.c_int), ("update_plan", ctypes.c_int), ("update_threads", ctypes.c_int),
                 ("candidates", ctypes.c_int * 3), ("us", ctypes.c_double * 3),
-                ("us_default", ctypes.c_double * 3)]
+                ("us_default", ctypes.c_double * 3), ("flux_threads", ctypes.c_int)]
 
 
 def _load():
@@ -321,13 +321,14 @@ class Grid:
         """nf_tuning: the tile variants of the PCG loop of this handle, as a dict."""
         t = nf_tuning_info()
         self._check(_lib.nf_tuning(self._h, ctypes.byref(t)))
-        return {"tuned": bool(t.tuned), "flux_rows": t.flux_rows, "flux_plan": t.flux_plan, "div_cols": t.div_cols,
+        return {"tuned": bool(t.tuned), "flux_rows": t.flux_rows, "flux_plan": t.flux_plan,
+                "flux_threads": t.flux_threads, "div_cols": t.div_cols,
                 "div_plan": t.div_plan, "div_threads": t.div_threads, "update_cols": t.update_cols,
                 "update_plan": t.update_plan, "update_threads": t.update_threads,
                 "candidates": list(t.candidates), "us": list(t.us), "us_default": list(t.us_default)}
 
     def set_tiles(self, flux_var=-1, div_var=-1, update_var=-1):
-        """nf_set_tiles: fix this handle's tile variants (operator middle 0..5, others 0..11; -1 keeps)."""
+        """nf_set_tiles: fix this handle's tile variants (operator middle 0..8, others 0..11; -1 keeps)."""
         self._check(_lib.nf_set_tiles(self._h, int(flux_var), int(div_var), int(update_var)))
 
     def set_inner_tolerance(self, floor_rtol):

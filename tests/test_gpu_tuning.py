@@ -56,7 +56,7 @@ def test_every_tile_variant_matches_oracle(env, n, L):
         ran = 0
         with NF.Grid(n, L, dtype=dtype) as g:
             for which in range(3):
-                for v in range(6 if which == 0 else 12):
+                for v in range(9 if which == 0 else 12):
                     codes = [1, 1, 1]
                     codes[which] = v
                     try:
