@@ -362,8 +362,10 @@ const char *nf_batch_last_error(const nf_batch *b);
  *   (the choice for solves that share the GPU, as ensemble partitions and
  *   concurrent handles do; the tuning then allocates two scratch copies of the
  *   loop's buffers, freed before nf_create_grid returns) and alone on larger
- *   grids, which fill the GPU by themselves; 1 times each candidate alone on
- *   every grid; 0 turns tuning off
+ *   grids, which fill the GPU by themselves, each timed launch after an
+ *   untimed fill of a 320 MiB scratch buffer (freed likewise) that clears the
+ *   Infinity Cache as the loop's other passes do; 1 times each candidate alone
+ *   on every grid; 0 turns tuning off
  *   (default tiles for handles created afterwards).  Shapes already tuned
  *   keep their choice.  NF_EINVAL for other values.
  * nf_tuning: the variants of a handle.  us / us_default: time per launch of the

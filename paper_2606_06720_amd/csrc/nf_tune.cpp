@@ -66,15 +66,33 @@ void apply(nf_grid* g, bool f32, const Choice& c, int tuned) {
 // round launching the pass once on every stream (launch(k) on stream k);
 // milliseconds per launch.  With several streams the launches of a round run
 // concurrently, so the figure is the pass's throughput under that contention.
+// With a cache-clearing buffer (one stream), every timed launch follows an
+// untimed fill of that buffer, so that the pass meets the cold caches it meets
+// in the loop, where the other passes run between its launches.
 template <class F>
 hipError_t time_pass(const std::vector<hipStream_t>& ss, hipEvent_t e0, hipEvent_t e1, std::vector<hipEvent_t>& ej,
-                     F&& launch, double* ms) {
+                     F&& launch, double* ms, double* clear = nullptr, size_t nclear = 0) {
   hipError_t e;
   const int ns = (int)ss.size();
   for (int i = 0; i < 2; ++i)
     for (int k = 0; k < ns; ++k)
       if ((e = launch(k)) != hipSuccess) return e;
   const int reps = 5;
+  if (clear && ns == 1) {
+    double tot = 0.0;
+    for (int i = 0; i < reps; ++i) {
+      if ((e = launch_fill_doubles(clear, nclear, 0.0, ss[0])) != hipSuccess) return e;
+      if ((e = hipEventRecord(e0, ss[0])) != hipSuccess) return e;
+      if ((e = launch(0)) != hipSuccess) return e;
+      if ((e = hipEventRecord(e1, ss[0])) != hipSuccess) return e;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+      float t = 0.0f;
+      if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+      tot += t;
+    }
+    *ms = tot / reps;
+    return hipSuccess;
+  }
   if ((e = hipEventRecord(e0, ss[0])) != hipSuccess) return e;
   for (int k = 1; k < ns; ++k)
     if ((e = hipStreamWaitEvent(ss[k], e0, 0)) != hipSuccess) return e;
@@ -149,6 +167,17 @@ hipError_t run_tuning(nf_grid* g, bool f32, int nstreams, Choice* out) {
     owned.push_back(q);
     bufs[0].mr = q;
   }
+  // timed alone on a grid whose passes do not fit the 256 MB Infinity Cache:
+  // a 320 MB buffer to clear it before each timed launch
+  double* clear = nullptr;
+  size_t nclear = 0;
+  if (nstreams == 1 && (long long)g->nx * g->ny > CONTEND_MAX_POINTS) {
+    nclear = (size_t)320 << 17;  // doubles
+    void* q = nullptr;
+    TCHK(hipMalloc(&q, nclear * sizeof(double)));
+    owned.push_back(q);
+    clear = (double*)q;
+  }
   for (int k = 1; k < nstreams; ++k) {
     void* q = nullptr;
     TCHK(hipMalloc(&q, 6 * spec + 3 * n * es));
@@ -188,21 +217,21 @@ hipError_t run_tuning(nf_grid* g, bool f32, int nstreams, Choice* out) {
                                            ss[k])
                        : launch_row_flux(G, b.M0, b.M1, (const double*)b.mr, (const double*)b.mr + 2 * n, 0,
                                          nullptr, 0.0, ss[k]);
-          }, &ms));
+          }, &ms, clear, nclear));
         } else if (pass == 1) {
           G.var_div[k32] = v;
           TCHK(time_pass(ss, e0, e1, ej, [&](int k) {
             const TuneBufs& b = bufs[k];
             return f32 ? launch_col_div32(G, b.M0, b.M1, b.Q, b.D, b.R, 0, ss[k])
                        : launch_col_div(G, 0, b.M0, b.M1, b.Q, b.D, b.R, g->bh, 0, 0, ss[k]);
-          }, &ms));
+          }, &ms, clear, nclear));
         } else {
           G.var_upd[k32] = v;
           TCHK(time_pass(ss, e0, e1, ej, [&](int k) {
             const TuneBufs& b = bufs[k];
             return f32 ? launch_col_update32(G, b.X, b.R, b.D, b.Q, b.M0, b.M1, 1, INT_MAX, 0.0, ss[k])
                        : launch_col_update(G, 0, b.X, b.R, b.D, b.Q, b.M0, b.M1, 1, INT_MAX, 0.0, ss[k]);
-          }, &ms));
+          }, &ms, clear, nclear));
         }
         if (best[v] < 0.0 || ms < best[v]) best[v] = ms;
       }
