@@ -679,11 +679,11 @@ __device__ __forceinline__ void col_fwd_body(Geo g, cd* in, cd* __restrict__ out
   colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_fwd(Geo g, cd* in, cd* __restrict__ out, int mode, cd* Gx, cd* Gy) {
   col_fwd_body<NY>(g, in, out, mode, Gx, Gy);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) kb_col_fwd(const ColFwdArgs* __restrict__ A, int mode) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) kb_col_fwd(const ColFwdArgs* __restrict__ A, int mode) {
   const ColFwdArgs& a = A[blockIdx.y];
   col_fwd_body<NY>(a.g, (cd*)a.in, (cd*)a.out, mode, (cd*)a.Gx, (cd*)a.Gy);
 }
@@ -713,12 +713,12 @@ __device__ __forceinline__ void col_grad_body(Geo g, const cd* __restrict__ xh, 
   else colT_store<C, 1>(buf, P, nullptr, kx0, g.h);
 }
 template <int NY, bool GRAD>
-__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
+__global__ void __launch_bounds__((ColCfg<NY, GRAD ? 2 : 1>::NT)) k_col_grad(Geo g, const cd* __restrict__ xh, cd* P, cd* Gx,
                                                                cd* Gy) {
   col_grad_body<NY, GRAD>(g, xh, P, Gx, Gy);
 }
 template <int NY, bool GRAD>
-__global__ void __launch_bounds__(GRAD ? 2 * TPF : TPF) kb_col_grad(const ColGradArgs* __restrict__ A) {
+__global__ void __launch_bounds__((ColCfg<NY, GRAD ? 2 : 1>::NT)) kb_col_grad(const ColGradArgs* __restrict__ A) {
   const ColGradArgs& a = A[blockIdx.y];
   col_grad_body<NY, GRAD>(a.g, (const cd*)a.xh, (cd*)a.P, (cd*)a.Gx, (cd*)a.Gy);
 }
@@ -1075,14 +1075,14 @@ __device__ __forceinline__ void col_refine_start_body(Geo g, const cd* __restric
   colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_refine_start(Geo g, const cd* __restrict__ r64, cd* x64,
                                                           cx<float>* x32, cx<float>* r32, cx<float>* d32,
                                                           cx<float>* Gx, cx<float>* Gy, double tol2,
                                                           double floor_in, int max_iter, int nwg_col) {
   col_refine_start_body<NY>(g, r64, x64, x32, r32, d32, Gx, Gy, tol2, floor_in, max_iter, nwg_col);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) kb_col_refine_start(const RefStartArgs* __restrict__ A, double tol2, double floor_in, int max_iter, int nwg_col) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) kb_col_refine_start(const RefStartArgs* __restrict__ A, double tol2, double floor_in, int max_iter, int nwg_col) {
   const RefStartArgs& a = A[blockIdx.y];
   col_refine_start_body<NY>(a.g, (const cd*)a.r64, (cd*)a.x64, (cx<float>*)a.x32, (cx<float>*)a.r32, (cx<float>*)a.d32, (cx<float>*)a.Gx, (cx<float>*)a.Gy, tol2, floor_in, max_iter, nwg_col);
 }
@@ -1125,12 +1125,12 @@ __device__ __forceinline__ void col_refine_acc_body(Geo g, cd* x64, const cx<flo
   colT_store<C, 2>(buf, Gx, Gy, kx0, g.h);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_refine_acc(Geo g, cd* x64, const cx<float>* __restrict__ x32,
                                                         cd* Gx, cd* Gy) {
   col_refine_acc_body<NY>(g, x64, x32, Gx, Gy);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) kb_col_refine_acc(const RefAccArgs* __restrict__ A) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) kb_col_refine_acc(const RefAccArgs* __restrict__ A) {
   const RefAccArgs& a = A[blockIdx.y];
   col_refine_acc_body<NY>(a.g, (cd*)a.x64, (const cx<float>*)a.x32, (cd*)a.Gx, (cd*)a.Gy);
 }
@@ -1202,11 +1202,11 @@ __device__ __forceinline__ void col_heat_body(Geo g, cd* Mx, cd* My, double D2dt
   }
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_heat(Geo g, cd* Mx, cd* My, double D2dt, double* eslot) {
   col_heat_body<NY>(g, Mx, My, D2dt, eslot);
 }
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) kb_col_heat(const HeatArgs* __restrict__ A) {
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) kb_col_heat(const HeatArgs* __restrict__ A) {
   const HeatArgs& a = A[blockIdx.y];
   col_heat_body<NY>(a.g, (cd*)a.Mx, (cd*)a.My, a.D2dt, (double*)a.eslot);
 }
@@ -1214,7 +1214,7 @@ __global__ void __launch_bounds__(2 * TPF) kb_col_heat(const HeatArgs* __restric
 // Adjoint right-hand side: b_hat = Pi F(G^T v) = -i xi_tilde . F(v) for the
 // two mixed fields of v (null modes vanish since xi_tilde does).
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_divrhs(Geo g, const cd* __restrict__ V0, const cd* __restrict__ V1,
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_divrhs(Geo g, const cd* __restrict__ V0, const cd* __restrict__ V1,
                                                         cd* __restrict__ bh) {
   using C = ColCfg<NY, 2>;
   __shared__ cd buf[C::NB * C::LS];
@@ -1244,7 +1244,7 @@ __global__ void k_zero_d(double* p, size_t n) {
 
 // Parseval sum w |xi_tilde|^2 |f_hat|^2 over two mixed fields (||grad m||^2 * n)
 template <int NY>
-__global__ void __launch_bounds__(2 * TPF) k_col_gradnorm(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
+__global__ void __launch_bounds__((ColCfg<NY, 2>::NT)) k_col_gradnorm(Geo g, const cd* __restrict__ Mx, const cd* __restrict__ My,
                                                       double* eslot) {
   using C = ColCfg<NY, 2>;
   __shared__ cd buf[C::NB * C::LS];
@@ -1510,7 +1510,7 @@ int flux_var_threads(const Geo& g, int rv) {
   return nt / (rv == VAR_DEFAULT ? 1 : rv_td(rv));
 }
 int div_var_cols(const Geo& g, int cv) { return cv == VAR_DEFAULT ? col_cols(g.ny) : cv_cols(g.ny, cv); }
-int div_var_threads(const Geo& g, int cv) { return 2 * TPF * (cv == VAR_DEFAULT ? 1 : cv_tm(cv)); }
+int div_var_threads(const Geo& g, int cv) { return cv == VAR_DEFAULT ? col_threads(g.ny, 2) : 2 * TPF * cv_tm(cv); }
 bool var_grid(const Geo& g) { return g.nz == 1 && (var_size(g.nx) || var_size(g.ny)); }
 
 hipError_t launch_status_reset(const Geo& g, int full, hipStream_t s) {
@@ -1594,7 +1594,7 @@ hipError_t launch_row_energy(const Geo& g, const void* Gx, const void* Gy, const
 }
 
 hipError_t launch_col_fwd(const Geo& g, void* in, void* out, int with_grad, void* Gx, void* Gy, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(k_col_fwd<N>, grid, blk, 0, s, g, (cd*)in, (cd*)out, with_grad, (cd*)Gx, (cd*)Gy)
   NF_DISPATCH(g.ny, L_)
 #undef L_
@@ -1603,12 +1603,12 @@ hipError_t launch_col_fwd(const Geo& g, void* in, void* out, int with_grad, void
 hipError_t launch_col_grad(const Geo& g, const void* xh, void* P, void* Gx, void* Gy, hipStream_t s) {
   const dim3 grid(col_nwg(g));
   if (P) {
-#define L_(N) hipLaunchKernelGGL((k_col_grad<N, false>), grid, dim3(TPF), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
+#define L_(N) hipLaunchKernelGGL((k_col_grad<N, false>), grid, dim3(col_threads(g.ny, 1)), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
   if (Gx) {
-#define L_(N) hipLaunchKernelGGL((k_col_grad<N, true>), grid, dim3(2 * TPF), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
+#define L_(N) hipLaunchKernelGGL((k_col_grad<N, true>), grid, dim3(col_threads(g.ny, 2)), 0, s, g, (const cd*)xh, (cd*)P, (cd*)Gx, (cd*)Gy)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
@@ -1620,7 +1620,7 @@ hipError_t launch_col_div(const Geo& g, int init, const void* Fx, const void* Fy
                           void* rh, const void* bh, int it, int nwg_row, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1) {
   if (init) {
-    const dim3 grid(col_nwg(g)), blk(2 * TPF);
+    const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N)                                                                                                  \
   NF_LAUNCH((k_col_div<N, true, double, VAR_DEFAULT>), grid, blk, s, e0, e1, g, (const cd*)Fx, (const cd*)Fy,  \
             (cd*)qh, (const cd*)dh, (cd*)rh, (const cd*)bh, it, nwg_row)
@@ -1674,7 +1674,7 @@ hipError_t launch_col_update32(const Geo& g, void* xh, void* rh, void* dh, const
 hipError_t launch_col_refine_start(const Geo& g, const void* r64, void* x64, void* x32, void* r32, void* d32,
                                    void* Gx, void* Gy, double tol2, double floor_in, int max_iter, hipStream_t s) {
   typedef cx<float> cf;
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
   const int nwg = col_nwg(g);
 #define L_(N)                                                                                                 \
   hipLaunchKernelGGL(k_col_refine_start<N>, grid, blk, 0, s, g, (const cd*)r64, (cd*)x64, (cf*)x32, (cf*)r32,  \
@@ -1684,7 +1684,7 @@ hipError_t launch_col_refine_start(const Geo& g, const void* r64, void* x64, voi
   return hipGetLastError();
 }
 hipError_t launch_col_refine_acc(const Geo& g, void* x64, const void* x32, void* Gx, void* Gy, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N)                                                                                                 \
   hipLaunchKernelGGL(k_col_refine_acc<N>, grid, blk, 0, s, g, (cd*)x64, (const cx<float>*)x32, (cd*)Gx, (cd*)Gy)
   NF_DISPATCH(g.ny, L_)
@@ -1692,14 +1692,14 @@ hipError_t launch_col_refine_acc(const Geo& g, void* x64, const void* x32, void*
   return hipGetLastError();
 }
 hipError_t launch_col_heat(const Geo& g, void* Mx, void* My, double D2dt, double* eslot, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(k_col_heat<N>, grid, blk, 0, s, g, (cd*)Mx, (cd*)My, D2dt, eslot)
   NF_DISPATCH(g.ny, L_)
 #undef L_
   return hipGetLastError();
 }
 hipError_t launch_col_gradnorm(const Geo& g, const void* Mx, const void* My, double* eslot, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(k_col_gradnorm<N>, grid, blk, 0, s, g, (const cd*)Mx, (const cd*)My, eslot)
   NF_DISPATCH(g.ny, L_)
 #undef L_
@@ -1723,7 +1723,7 @@ hipError_t launchb_row_r2c(const Geo& g, const RowR2cArgs* A, int count, hipStre
   return hipGetLastError();
 }
 hipError_t launchb_col_fwd(const Geo& g, const ColFwdArgs* A, int count, int mode, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(kb_col_fwd<N>, grid, blk, 0, s, A, mode)
   NF_DISPATCH(g.ny, L_)
 #undef L_
@@ -1732,11 +1732,11 @@ hipError_t launchb_col_fwd(const Geo& g, const ColFwdArgs* A, int count, int mod
 hipError_t launchb_col_grad(const Geo& g, const ColGradArgs* A, int count, bool grad, hipStream_t s) {
   const dim3 grid(col_nwg(g), count);
   if (grad) {
-#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, true>), grid, dim3(2 * TPF), 0, s, A)
+#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, true>), grid, dim3(col_threads(g.ny, 2)), 0, s, A)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   } else {
-#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, false>), grid, dim3(TPF), 0, s, A)
+#define L_(N) hipLaunchKernelGGL((kb_col_grad<N, false>), grid, dim3(col_threads(g.ny, 1)), 0, s, A)
     NF_DISPATCH(g.ny, L_)
 #undef L_
   }
@@ -1759,7 +1759,7 @@ hipError_t launchb_row_flux(const Geo& g, bool f32, const FluxArgs* A, int count
 }
 hipError_t launchb_col_div(const Geo& g, bool f32, bool init, const DivArgs* A, int count, int it, hipStream_t s) {
   if (init) {
-    const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+    const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));
     const int nwg_row = row_nwg(g);
 #define L_(N) hipLaunchKernelGGL((kb_col_div<N, true, double, VAR_DEFAULT>), grid, blk, 0, s, A, it, nwg_row)
     NF_DISPATCH(g.ny, L_)
@@ -1801,7 +1801,7 @@ hipError_t launchb_row_split(const Geo& g, const SplitArgs* A, int count, hipStr
   return hipGetLastError();
 }
 hipError_t launchb_col_heat(const Geo& g, const HeatArgs* A, int count, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(kb_col_heat<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.ny, L_)
 #undef L_
@@ -1816,7 +1816,7 @@ hipError_t launchb_row_final(const Geo& g, const FinalArgs* A, int count, hipStr
 }
 hipError_t launchb_col_refine_start(const Geo& g, const RefStartArgs* A, int count, double tol2, double floor_in,
                                     int max_iter, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));
   const int nwg = col_nwg(g);
 #define L_(N) hipLaunchKernelGGL(kb_col_refine_start<N>, grid, blk, 0, s, A, tol2, floor_in, max_iter, nwg)
   NF_DISPATCH(g.ny, L_)
@@ -1824,7 +1824,7 @@ hipError_t launchb_col_refine_start(const Geo& g, const RefStartArgs* A, int cou
   return hipGetLastError();
 }
 hipError_t launchb_col_refine_acc(const Geo& g, const RefAccArgs* A, int count, hipStream_t s) {
-  const dim3 grid(col_nwg(g), count), blk(2 * TPF);
+  const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(kb_col_refine_acc<N>, grid, blk, 0, s, A)
   NF_DISPATCH(g.ny, L_)
 #undef L_
@@ -1856,7 +1856,7 @@ hipError_t launch_row_adj2(const Geo& g, const void* M1, const void* M2, const v
   return hipGetLastError();
 }
 hipError_t launch_col_divrhs(const Geo& g, const void* V0, const void* V1, void* bh, hipStream_t s) {
-  const dim3 grid(col_nwg(g)), blk(2 * TPF);
+  const dim3 grid(col_nwg(g)), blk(col_threads(g.ny, 2));
 #define L_(N) hipLaunchKernelGGL(k_col_divrhs<N>, grid, blk, 0, s, g, (const cd*)V0, (const cd*)V1, (cd*)bh)
   NF_DISPATCH(g.ny, L_)
 #undef L_

@@ -64,13 +64,20 @@ struct RowCfg {
 template <int NX, int NF>
 using Row2D = RowCfg<NX, NF, row_tile(NX, NF)>;
 
-template <int NY, int NF, int CT = TILE, int PL = 0, int TM = 1>
+// Default thread multiple of a column tile: columns of 4096 (one column per
+// workgroup whose two FP64 fields take 131 KB of LDS, one workgroup per
+// compute unit) take twice the threads, so that a compute unit runs 8 waves
+// rather than 4.
+__host__ __device__ constexpr int col_tm_default(int ny) { return ny >= 4096 ? 2 : 1; }
+__host__ __device__ constexpr int col_threads(int ny, int nf) { return TPF * nf * col_tm_default(ny); }
+template <int NY, int NF, int CT = TILE, int PL = 0, int TM = 0>
 struct ColCfg {
   static constexpr int C0 = CT / NY;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);   // columns per workgroup
   static constexpr int PLAN = PL;                               // radix plan of the y transforms
   static constexpr int NYv = NY;
-  static constexpr int NT = TPF * NF * TM;                      // TM: thread multiple of the tile
+  // TM: thread multiple of the tile (0: the default of the column length)
+  static constexpr int NT = TPF * NF * (TM > 0 ? TM : col_tm_default(NY));
   static constexpr int LS = lpad_use(NY) ? lpad_len(NY) : NY;   // room for the FFT's padded layout
   static constexpr int CN = C * NY;                             // elements per field in the block
   static constexpr int NB = NF * C;                             // LDS lines
