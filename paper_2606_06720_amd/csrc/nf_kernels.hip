@@ -122,7 +122,7 @@ __global__ void __launch_bounds__((Row2D<NX, 1>::NT)) kb_row_r2c(const RowR2cArg
 
 // mixed -> physical (unnormalised inverse: the caller folds 1/n into the spectral side)
 template <int NX>
-__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
+__device__ __forceinline__ void row_c2r_body(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
   using C = Row2D<NX, 1>;
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
@@ -141,6 +141,16 @@ __global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_c2r(Geo g, const cd*
       *(double2*)(f + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(v.x, v.y);
     }
   }
+}
+template <int NX>
+__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) k_row_c2r(Geo g, const cd* __restrict__ in, double* __restrict__ f) {
+  row_c2r_body<NX>(g, in, f);
+}
+// the pressure of a split update written out on its own (see launch_row_split)
+template <int NX>
+__global__ void __launch_bounds__((Row2D<NX, 1>::NT)) kb_row_split_p(const SplitArgs* __restrict__ A) {
+  const SplitArgs& a = A[blockIdx.y];
+  row_c2r_body<NX>(a.g, (const cd*)a.P, (double*)a.p_out);
 }
 
 // Operator middle: gradient fields (mixed) -> physical g -> flux K g -> mixed,
@@ -276,18 +286,32 @@ __global__ void __launch_bounds__((FluxCfg<NX, RV>::NT)) kb_row_flux(const FluxA
 // Split update, pointwise part: p = F^-1 x_hat (written out), g = grad p,
 // exact activation then exact relaxation of m, forward x transform of the
 // result.  In place: P, Gx hold the transformed m_x, m_y on exit.
+// WITHP: the three fields (P, Gx, Gy) in one tile, p written here; otherwise
+// only Gx, Gy (p is written by a pass of its own before), in the two-row tile
+// SplitCfg: rows of 2048 and more hold one row per workgroup with three fields
+// (16-byte runs through the mixed layout) but two with two.
 template <int NX>
+using SplitCfg = RowCfg<NX, 2, NX, 0, ((NX / 8) * 2 >= 1024 ? 2 : 1)>;
+template <int NX>
+constexpr bool split_separate_p() { return Row2D<NX, 3>::R < 2 && (NX & (NX - 1)) == 0; }
+template <int NX, bool WITHP>
+using SplitTile = typename std::conditional<WITHP, Row2D<NX, 3>, SplitCfg<NX>>::type;
+template <int NX, bool WITHP>
 __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
-  using C = Row2D<NX, 3>;
+  using C = SplitTile<NX, WITHP>;
+  constexpr int OFF = WITHP ? C::R : 0;  // first line of Gx
   __shared__ cd buf[C::NB * C::LS];
   const cd* tw = (const cd*)g.tw;
   const int y0 = xcd_block() * C::R;
   const int nrow = min(C::R, g.ny - y0);
   const size_t n = (size_t)g.nx * g.ny;
   cd tv[C::ET];
-  rowT_gload<C>(tv, P, Gx, Gy, g.ny, y0, nrow);
+  if constexpr (WITHP)
+    rowT_gload<C>(tv, P, Gx, Gy, g.ny, y0, nrow);
+  else
+    rowT_gload<C>(tv, Gx, Gy, nullptr, g.ny, y0, nrow);
   double2 mxv[C::EP], myv[C::EP];
   rowP_gload<C>(mxv, m, y0, nrow);
   rowP_gload<C>(myv, m + n, y0, nrow);
@@ -303,11 +327,14 @@ __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* _
     const int p = threadIdx.x + i * C::NT;
     const int rr = p / C::H, j = p % C::H;
     if (p < C::RH && rr < nrow) {
+      // m_x and m_y replace the first two fields' lines
       cd* pp = buf + rr * C::LS + j;
       cd* px = buf + (C::R + rr) * C::LS + j;
-      const cd pv = *pp;
-      const cd gxv = *px, gyv = buf[(2 * C::R + rr) * C::LS + j];
-      *(double2*)(p_out + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(pv.x, pv.y);
+      const cd gxv = buf[(OFF + rr) * C::LS + j], gyv = buf[(OFF + C::R + rr) * C::LS + j];
+      if constexpr (WITHP) {
+        const cd pv = *pp;
+        *(double2*)(p_out + (size_t)(y0 + rr) * NX + 2 * j) = make_double2(pv.x, pv.y);
+      }
       double mx[2] = {mxv[i].x, mxv[i].y}, my[2] = {myv[i].x, myv[i].y};
       const double gxa[2] = {gxv.x, gxv.y}, gya[2] = {gyv.x, gyv.y};
 #pragma unroll
@@ -348,16 +375,16 @@ __device__ __forceinline__ void row_split_body(Geo g, cd* P, cd* Gx, const cd* _
   rfft_post<double, C::H, 2 * C::R, C::LS, C::NT>(buf, tw, g.twn);
   rowT_store<C, 2>(buf, P, Gx, nullptr, g.ny, y0, nrow);
 }
-template <int NX>
-__global__ void __launch_bounds__((Row2D<NX, 3>::NT)) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
+template <int NX, bool WITHP>
+__global__ void __launch_bounds__((SplitTile<NX, WITHP>::NT)) k_row_split(Geo g, cd* P, cd* Gx, const cd* __restrict__ Gy,
                                                    const double* __restrict__ m, double* __restrict__ p_out,
                                                    double c2dt, double gamma, double dt, double relax1) {
-  row_split_body<NX>(g, P, Gx, Gy, m, p_out, c2dt, gamma, dt, relax1);
+  row_split_body<NX, WITHP>(g, P, Gx, Gy, m, p_out, c2dt, gamma, dt, relax1);
 }
-template <int NX>
-__global__ void __launch_bounds__((Row2D<NX, 3>::NT)) kb_row_split(const SplitArgs* __restrict__ A) {
+template <int NX, bool WITHP>
+__global__ void __launch_bounds__((SplitTile<NX, WITHP>::NT)) kb_row_split(const SplitArgs* __restrict__ A) {
   const SplitArgs& a = A[blockIdx.y];
-  row_split_body<NX>(a.g, (cd*)a.P, (cd*)a.Gx, (const cd*)a.Gy, (const double*)a.m, (double*)a.p_out, a.c2dt, a.gamma, a.dt, a.relax1);
+  row_split_body<NX, WITHP>(a.g, (cd*)a.P, (cd*)a.Gx, (const cd*)a.Gy, (const double*)a.m, (double*)a.p_out, a.c2dt, a.gamma, a.dt, a.relax1);
 }
 
 // Last pass of the step: inverse x transform of the diffused m, written over
@@ -1565,15 +1592,30 @@ hipError_t launch_row_flux32(const Geo& g, void* G0, void* G1, const float* m32,
 #undef L_
   return hipErrorInvalidValue;
 }
+// Split update, pointwise part.  Where the three-field tile holds one row per
+// workgroup (rows of 2048 and more), p is written by a one-field pass first and
+// the activation and relaxation run in the two-field, two-row tile: the same
+// bytes in runs of twice the length.
+template <int NX>
+static hipError_t split_go(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out, double c2dt,
+                           double gamma, double dt, double relax1, hipStream_t s) {
+  if constexpr (split_separate_p<NX>()) {
+    hipLaunchKernelGGL(k_row_c2r<NX>, dim3(row_nwg(g, 1)), dim3(row_threads(g.nx, 1)), 0, s, g, (const cd*)P, p_out);
+    const int R = SplitCfg<NX>::R;
+    hipLaunchKernelGGL((k_row_split<NX, false>), dim3((g.ny + R - 1) / R), dim3(SplitCfg<NX>::NT), 0, s, g, (cd*)P,
+                       (cd*)Gx, (const cd*)Gy, m, p_out, c2dt, gamma, dt, relax1);
+  } else {
+    hipLaunchKernelGGL((k_row_split<NX, true>), dim3(row_nwg(g, 3)), dim3(row_threads(g.nx, 3)), 0, s, g, (cd*)P,
+                       (cd*)Gx, (const cd*)Gy, m, p_out, c2dt, gamma, dt, relax1);
+  }
+  return hipGetLastError();
+}
 hipError_t launch_row_split(const Geo& g, void* P, void* Gx, void* Gy, const double* m, double* p_out,
                             double c2dt, double gamma, double dt, double relax1, hipStream_t s) {
-  const dim3 grid(row_nwg(g, 3)), blk(row_threads(g.nx, 3));
-#define L_(N)                                                                                            \
-  hipLaunchKernelGGL(k_row_split<N>, grid, blk, 0, s, g, (cd*)P, (cd*)Gx, (const cd*)Gy, m, p_out, c2dt, \
-                     gamma, dt, relax1)
+#define L_(N) return split_go<N>(g, P, Gx, Gy, m, p_out, c2dt, gamma, dt, relax1, s)
   NF_DISPATCH(g.nx, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launch_row_final(const Geo& g, const void* Mx, const void* My, double* m, double* dslot,
                             hipStream_t s) {
@@ -1793,12 +1835,22 @@ hipError_t launchb_col_update(const Geo& g, bool f32, const UpdArgs* A, int coun
   }
   return hipErrorInvalidValue;
 }
+template <int NX>
+static hipError_t splitb_go(const Geo& g, const SplitArgs* A, int count, hipStream_t s) {
+  if constexpr (split_separate_p<NX>()) {
+    hipLaunchKernelGGL(kb_row_split_p<NX>, dim3(row_nwg(g, 1), count), dim3(row_threads(g.nx, 1)), 0, s, A);
+    const int R = SplitCfg<NX>::R;
+    hipLaunchKernelGGL((kb_row_split<NX, false>), dim3((g.ny + R - 1) / R, count), dim3(SplitCfg<NX>::NT), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((kb_row_split<NX, true>), dim3(row_nwg(g, 3), count), dim3(row_threads(g.nx, 3)), 0, s, A);
+  }
+  return hipGetLastError();
+}
 hipError_t launchb_row_split(const Geo& g, const SplitArgs* A, int count, hipStream_t s) {
-  const dim3 grid(row_nwg(g, 3), count), blk(row_threads(g.nx, 3));
-#define L_(N) hipLaunchKernelGGL(kb_row_split<N>, grid, blk, 0, s, A)
+#define L_(N) return splitb_go<N>(g, A, count, s)
   NF_DISPATCH(g.nx, L_)
 #undef L_
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 hipError_t launchb_col_heat(const Geo& g, const HeatArgs* A, int count, hipStream_t s) {
   const dim3 grid(col_nwg(g), count), blk(col_threads(g.ny, 2));

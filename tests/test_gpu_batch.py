@@ -236,3 +236,33 @@ def test_batch_paper_grids_and_boxes(env):
             info1 = g.run(*w["prm"], 5e-4, 4, m1, p1, r1, S1, rtol=1e-10)
         assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), i
         assert _key(infos[i]) == _key(info1), i
+
+
+def test_batch_wide_rows(env):
+    # rows of 2048 and 4096 points: the split update writes p in a pass of its
+    # own and runs activation and relaxation in the two-row tile, in the batch
+    # as on a single handle (bitwise), and within the FP64 bar of the oracle
+    NF, T, torch = env
+    rng = np.random.default_rng(5000)
+    inst = []
+    for n, gamma in (((2048, 16), 0.75), ((4096, 8), 1.0), ((4096, 8), 0.5)):
+        sh = n[::-1]
+        S = rng.standard_normal(sh)
+        inst.append(dict(n=n, L=(1.0, n[1] / n[0]), m0=rng.uniform(-1.0, 1.0, (2,) + sh),
+                         r=rng.uniform(0.05, 0.15, sh), S=S - S.mean(), prm=(50.0, 1e-4, gamma)))
+    steps, dt = 3, 5e-4
+    ms = [T(w["m0"]) for w in inst]
+    ps = [torch.zeros_like(T(w["r"])) for w in inst]
+    with NF.Batch([w["n"] for w in inst], L=[w["L"] for w in inst]) as b:
+        infos = b.run([w["prm"] for w in inst], dt, steps, ms, ps, [T(w["r"]) for w in inst],
+                      [T(w["S"]) for w in inst], rtol=1e-12)
+    for i, w in enumerate(inst):
+        m1, p1 = T(w["m0"]), torch.zeros_like(T(w["r"]))
+        with NF.Grid(w["n"], w["L"]) as g:
+            info1 = g.run(*w["prm"], dt, steps, m1, p1, T(w["r"]), T(w["S"]), rtol=1e-12)
+        assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), i
+        assert _key(infos[i]) == _key(info1), i
+    w = inst[2]
+    mo, po, _ = O.run(w["m0"], None, w["r"], w["S"], *w["prm"], dt, steps, rtol=1e-12, L=w["L"])
+    assert rel(ms[2].cpu().numpy(), mo) <= 1e-10
+    assert rel(ps[2].cpu().numpy(), po) <= 1e-10
