@@ -56,12 +56,12 @@ __device__ __forceinline__ double precond3_inv(const double* K, double a, double
 // Tiles of 8-byte elements (ES = 8, the FP32 loop passes) hold twice the lines
 // with twice the threads, so that their runs stay 128 bytes long for the same
 // LDS and the same registers per thread.
-template <int NZ, int NF, int ES = 16>
+template <int NZ, int NF, int ES = 16, int TW = 1>
 struct ZCfg {
   static constexpr int W = ES == 8 ? 2 : 1;
   static constexpr int C0 = 2 * TILE * W / NZ;
   static constexpr int C = C0 < 1 ? 1 : (C0 > 64 ? 64 : C0);  // lines (kx, ky) per workgroup
-  static constexpr int NT = TPF * NF * W;
+  static constexpr int NT = TPF * NF * W * TW;  // TW: extra thread multiple (same lines)
   static constexpr int LS = lpad_use(NZ) ? lpad_len(NZ) : NZ + 1;  // room for the FFT's padded layout
   static constexpr int CN = C * NZ;
   static constexpr int NB = NF * C;
@@ -80,10 +80,10 @@ __device__ __forceinline__ V* pick4w(int f, V* a, V* b, V* c, V* d) {
 
 // gathered image: element e -> field e / CN, line (e % CN) % C, z (e % CN) / C;
 // consecutive threads read consecutive ky of one z (coalesced runs of C)
-template <int NZ, int NF, int NFL, typename V, int ES = 16>
-__device__ __forceinline__ void zT_gload(V (&v)[(ZCfg<NZ, NF, ES>::ET)], const V* s0, const same<V>* s1,
+template <int NZ, int NF, int NFL, typename V, int ES = 16, int TW = 1>
+__device__ __forceinline__ void zT_gload(V (&v)[(ZCfg<NZ, NF, ES, TW>::ET)], const V* s0, const same<V>* s1,
                                          const same<V>* s2, const same<V>* s3, int lam0, int nlam, int ny) {
-  using C = ZCfg<NZ, NF, ES>;
+  using C = ZCfg<NZ, NF, ES, TW>;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -98,9 +98,9 @@ __device__ __forceinline__ void zT_gload(V (&v)[(ZCfg<NZ, NF, ES>::ET)], const V
     v[i] = x;
   }
 }
-template <int NZ, int NF, int NFL, typename V, int ES = 16>
-__device__ __forceinline__ void zT_put(V* buf, const V (&v)[(ZCfg<NZ, NF, ES>::ET)]) {
-  using C = ZCfg<NZ, NF, ES>;
+template <int NZ, int NF, int NFL, typename V, int ES = 16, int TW = 1>
+__device__ __forceinline__ void zT_put(V* buf, const V (&v)[(ZCfg<NZ, NF, ES, TW>::ET)]) {
+  using C = ZCfg<NZ, NF, ES, TW>;
 #pragma unroll
   for (int i = 0; i < C::ET; ++i) {
     const int e = threadIdx.x + i * C::NT;
@@ -108,10 +108,10 @@ __device__ __forceinline__ void zT_put(V* buf, const V (&v)[(ZCfg<NZ, NF, ES>::E
     if (e < NFL * C::CN) buf[(f * C::C + ee % C::C) * C::LS + ee / C::C] = v[i];
   }
 }
-template <int NZ, int NF, int NFS, typename V, int ES = 16>
+template <int NZ, int NF, int NFS, typename V, int ES = 16, int TW = 1>
 __device__ __forceinline__ void zT_store(const V* buf, same<V>* d0, same<V>* d1, same<V>* d2, same<V>* d3, int lam0,
                                          int nlam, int ny) {
-  using C = ZCfg<NZ, NF, ES>;
+  using C = ZCfg<NZ, NF, ES, TW>;
   for (int e = threadIdx.x; e < NFS * C::CN; e += C::NT) {
     const int f = e / C::CN, ee = e % C::CN;
     const int c = ee % C::C, z = ee / C::C;
@@ -123,9 +123,9 @@ __device__ __forceinline__ void zT_store(const V* buf, same<V>* d0, same<V>* d1,
   }
 }
 // contiguous spectral image of one field: p -> line p / NZ, kz = p % NZ
-template <int NZ, int NF, typename V, int ES = 16>
-__device__ __forceinline__ void zP_gload(V (&v)[(ZCfg<NZ, NF, ES>::EP)], const V* __restrict__ src, int lam0, int nlam) {
-  using C = ZCfg<NZ, NF, ES>;
+template <int NZ, int NF, typename V, int ES = 16, int TW = 1>
+__device__ __forceinline__ void zP_gload(V (&v)[(ZCfg<NZ, NF, ES, TW>::EP)], const V* __restrict__ src, int lam0, int nlam) {
+  using C = ZCfg<NZ, NF, ES, TW>;
 #pragma unroll
   for (int i = 0; i < C::EP; ++i) {
     const int p = threadIdx.x + i * C::NT;
@@ -135,10 +135,10 @@ __device__ __forceinline__ void zP_gload(V (&v)[(ZCfg<NZ, NF, ES>::EP)], const V
 }
 
 // gradient multipliers i xi_c v / n of one spectral value into lines f0..f0+2
-template <int NZ, int NF, typename T, int ES = 16>
+template <int NZ, int NF, typename T, int ES = 16, int TW = 1>
 __device__ __forceinline__ void put_grad3(cx<T>* buf, int f0, int c, int kz, const cx<T> v, double xx, double yy,
                                           double zz, double inv_n) {
-  using C = ZCfg<NZ, NF, ES>;
+  using C = ZCfg<NZ, NF, ES, TW>;
   const T sx = (T)(xx * inv_n), sy = (T)(yy * inv_n), sz = (T)(zz * inv_n);
   buf[(f0 * C::C + c) * C::LS + kz] = mk<T>(-sx * v.y, sx * v.x);
   buf[((f0 + 1) * C::C + c) * C::LS + kz] = mk<T>(-sy * v.y, sy * v.x);
@@ -559,12 +559,17 @@ __global__ void __launch_bounds__((MODE == 1 ? 1 : (MODE == 2 ? 3 : 4)) * TPF)
 //   status.kbar and the incompatibility flag.
 // else: q stored; totals <d,q>, <q,M^-1 r>, <q,M^-1 q>, <r,q>, <q,q>,
 //   <r,M^-1 r>, <r,r>.
+// z tile of the loop passes: 128-byte runs in both precisions (section of
+// ZCfg); FP64 with twice the threads (the tile's 111 KB of LDS admit one
+// workgroup per compute unit: 12 waves rather than 6)
+template <typename T>
+constexpr int z_tw() { return sizeof(T) == sizeof(double) ? 2 : 1; }
 template <int NZ, bool INIT, typename T>
-__global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
+__global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>), z_tw<T>()>::NT))
     k3_zdiv(Geo g, const cx<T>* F0, const cx<T>* F1, const cx<T>* F2, cx<T>* __restrict__ qh,
             const cx<T>* __restrict__ dh, cx<T>* rh, const cx<T>* __restrict__ bh, int it) {
-  constexpr int ES = sizeof(cx<T>);
-  using C = ZCfg<NZ, 3, ES>;
+  constexpr int ES = sizeof(cx<T>), TW = z_tw<T>();
+  using C = ZCfg<NZ, 3, ES, TW>;
   using V = cx<T>;
   static_assert(!INIT || sizeof(T) == sizeof(double), "INIT pass is FP64");
   if (INIT ? g.st->outer_done != 0 : g.st->conv_at <= it) return;
@@ -576,12 +581,12 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
   const int nlam = g.h * g.ny;
   const int lam0 = xcd_block() * C::C;
   V tv[C::ET], av[C::EP], bv[C::EP];
-  zT_gload<NZ, 3, 3, V, ES>(tv, F0, F1, F2, nullptr, lam0, nlam, g.ny);
+  zT_gload<NZ, 3, 3, V, ES, TW>(tv, F0, F1, F2, nullptr, lam0, nlam, g.ny);
   if (INIT) {
-    zP_gload<NZ, 3, V, ES>(av, bh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(av, bh, lam0, nlam);
   } else {
-    zP_gload<NZ, 3, V, ES>(av, dh, lam0, nlam);
-    zP_gload<NZ, 3, V, ES>(bv, rh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(av, dh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(bv, rh, lam0, nlam);
   }
   if (INIT) {
     if (threadIdx.x == 0) {
@@ -602,7 +607,7 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
   } else if (threadIdx.x < 6) {
     Ks[threadIdx.x] = g.st->kbar[threadIdx.x];
   }
-  zT_put<NZ, 3, 3, V, ES>(buf, tv);
+  zT_put<NZ, 3, 3, V, ES, TW>(buf, tv);
   __syncthreads();
   lds_fft<T, -1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
   constexpr int KP = INIT ? 3 : 4;  // partial sums stored (see below)
@@ -655,11 +660,11 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
 // PCG scalar step + vector update + next direction + its gradient through the
 // inverse z transform (the 2D column update with three gradient fields).
 template <int NZ, typename T>
-__global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
+__global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>), z_tw<T>()>::NT))
     k3_zupdate(Geo g, int first, cx<T>* xh, cx<T>* rh, cx<T>* dh, const cx<T>* __restrict__ qh, cx<T>* G0,
                cx<T>* G1, cx<T>* G2, int it, int max_iter, double tol2) {
-  constexpr int ES = sizeof(cx<T>);
-  using C = ZCfg<NZ, 3, ES>;
+  constexpr int ES = sizeof(cx<T>), TW = z_tw<T>();
+  using C = ZCfg<NZ, 3, ES, TW>;
   using V = cx<T>;
   DevStatus* st = g.st;
   if (st->conv_at < it) return;
@@ -674,11 +679,11 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
   double K[6];
   for (int i = 0; i < 6; ++i) K[i] = st->kbar[i];
   V xv[C::EP], rv0[C::EP], dv0[C::EP], qv[C::EP];
-  zP_gload<NZ, 3, V, ES>(rv0, rh, lam0, nlam);
+  zP_gload<NZ, 3, V, ES, TW>(rv0, rh, lam0, nlam);
   if (!first) {
-    zP_gload<NZ, 3, V, ES>(xv, xh, lam0, nlam);
-    zP_gload<NZ, 3, V, ES>(dv0, dh, lam0, nlam);
-    zP_gload<NZ, 3, V, ES>(qv, qh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(xv, xh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(dv0, dh, lam0, nlam);
+    zP_gload<NZ, 3, V, ES, TW>(qv, qh, lam0, nlam);
   }
   double alpha = 0.0, beta = 0.0;
   bool stop = false, zero_x = false;
@@ -753,7 +758,7 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
         }
       }
     }
-    if (!stop && p < C::CN) put_grad3<NZ, 3, T, ES>(buf, 0, c, kz, d, xx, yy, zz, g.inv_n);
+    if (!stop && p < C::CN) put_grad3<NZ, 3, T, ES, TW>(buf, 0, c, kz, d, xx, yy, zz, g.inv_n);
   }
   if (!first && !zero_x) store_partials<C::NT, 1>(rrp, g, SLOT_RR, red);
   if (stop) {
@@ -762,7 +767,7 @@ __global__ void __launch_bounds__((ZCfg<NZ, 3, sizeof(cx<T>)>::NT))
   }
   __syncthreads();
   lds_fft<T, +1, NZ, C::NB, C::LS, C::NT>(buf, tw, g.twn);
-  zT_store<NZ, 3, 3, V, ES>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
+  zT_store<NZ, 3, 3, V, ES, TW>(buf, G0, G1, G2, nullptr, lam0, nlam, g.ny);
   tclk_end(g, 2, tit);
 }
 
@@ -1267,7 +1272,7 @@ hipError_t launch3_zdiv(const Geo& g, bool f32, int init, const void* F0, const 
                         const void* dh, void* rh, const void* bh, int it, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1) {
   const bool lo = f32 && !init;
-  const dim3 grid(nwg3_z(g, lo)), blk(lo ? 6 * TPF : 3 * TPF);
+  const dim3 grid(nwg3_z(g, lo)), blk(6 * TPF);  // FP32: twice the lines, FP64: twice the threads
   if (init) {
 #define L_(N)                                                                                                  \
   NF3_LAUNCH((k3_zdiv<N, true, double>), grid, blk, s, e0, e1, g, (const cd*)F0, (const cd*)F1, (const cd*)F2, \
@@ -1294,7 +1299,7 @@ hipError_t launch3_zdiv(const Geo& g, bool f32, int init, const void* F0, const 
 hipError_t launch3_zupdate(const Geo& g, bool f32, int first, void* xh, void* rh, void* dh, const void* qh, void* G0,
                            void* G1, void* G2, int it, int max_iter, double tol2, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {
-  const dim3 grid(nwg3_z(g, f32)), blk(f32 ? 6 * TPF : 3 * TPF);
+  const dim3 grid(nwg3_z(g, f32)), blk(6 * TPF);  // FP32: twice the lines, FP64: twice the threads
   if (f32) {
     typedef cx<float> cf;
 #define L_(N)                                                                                               \
