@@ -3,6 +3,7 @@
 // stopping criteria (Algorithm 1, Sec. 2.5) and the discrete energy.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -15,6 +16,23 @@
 #include "nf_internal.h"
 
 using namespace nf;
+
+namespace nf {
+
+// Wait for an event of the polling loops by querying it: a blocking wait can
+// take tens of microseconds to return after the event completes, time in which
+// the GPU runs dry once the queued work is a single PCG iteration.  After
+// about a millisecond the wait blocks instead.
+hipError_t poll_event(hipEvent_t e) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipEventQuery(e);
+    if (q != hipErrorNotReady) return q;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(1000)) return hipEventSynchronize(e);
+  }
+}
+
+}  // namespace nf
 
 namespace {
 
@@ -258,7 +276,7 @@ int pcg_loop(nf_grid* g, bool f32, const double* m, const double* r, int max_ite
     HIPCHK(g, hipMemcpyAsync(&g->hst[slot], g->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipEventRecord(g->ev[slot], s));
     if (pending >= 0) {
-      HIPCHK(g, hipEventSynchronize(g->ev[pending]));
+      HIPCHK(g, poll_event(g->ev[pending]));
       if (g->hst[pending].conv_at != INT_MAX) {
         stopped = true;
         break;

@@ -261,7 +261,10 @@ int run_chunk(Part* b, bool f32, int it0, int nk, int max_iter, double tol2) {
 }
 
 // PCG iterations of all instances, chunked and polled as in the single-instance
-// loop; stops once every instance's status reports a stop.
+// loop; stops once every instance's status reports a stop.  The polled copy
+// that shows every stop is final (no later launch of the loop writes a stopped
+// instance's status), so b->fin is taken from it without waiting for the
+// queued no-op tail; later launches queue behind that tail.
 int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
   hipStream_t s = b->stream;
   const int c = b->count;
@@ -280,10 +283,13 @@ int batch_loop(Part* b, bool f32, int max_iter, double tol2, int expect) {
     BCHK(b, hipMemcpyAsync(b->hst + (size_t)slot * c, b->st, sizeof(DevStatus) * c, hipMemcpyDeviceToHost, s));
     BCHK(b, hipEventRecord(b->ev[slot], s));
     if (pending >= 0) {
-      BCHK(b, hipEventSynchronize(b->ev[pending]));
+      BCHK(b, poll_event(b->ev[pending]));
       bool all = true;
       for (int i = 0; i < c && all; ++i) all = b->hst[(size_t)pending * c + i].conv_at != INT_MAX;
-      if (all) break;
+      if (all) {
+        std::memcpy(b->fin.data(), b->hst + (size_t)pending * c, sizeof(DevStatus) * c);
+        return NF_OK;
+      }
     }
     pending = slot;
     slot ^= 1;
@@ -324,10 +330,18 @@ int batch_solve(Part* b, bool first, double* const* p, double rtol, int max_iter
     int rc = batch_loop(b, false, max_iter, tol2, b->last_iters);
     if (rc) return rc;
     // final convergence test of solves stopped by max_iter, on the last residual
-    for (auto& G : b->groups)
-      BCHK(b, launchb_sum_slot(G.t.sum_rr, (int)G.idx.size(), 1, rr_nwg(G.shape, false), 11, s));
-    rc = read_all(b);
-    if (rc) return rc;
+    bool capped = false;
+    for (int i = 0; i < c; ++i) {
+      const DevStatus& f = b->fin[i];
+      capped = capped || (!f.converged && f.conv_at == max_iter && max_iter > 0 &&
+                          !(f.flags & (FLAG_NONFINITE | FLAG_INCOMPAT)));
+    }
+    if (capped) {
+      for (auto& G : b->groups)
+        BCHK(b, launchb_sum_slot(G.t.sum_rr, (int)G.idx.size(), 1, rr_nwg(G.shape, false), 11, s));
+      rc = read_all(b);
+      if (rc) return rc;
+    }
     int mx = 0;
     for (int i = 0; i < c; ++i) {
       const DevStatus& f = b->fin[i];

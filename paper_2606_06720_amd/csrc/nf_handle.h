@@ -66,6 +66,8 @@ struct nf_grid {
 };
 
 namespace nf {
+// Wait for an event of a polling loop: query it, block after about a millisecond.
+hipError_t poll_event(hipEvent_t e);
 // Set the handle's tile variants for its grid shape and real type: from the
 // process-wide cache, else by timing the candidates on its buffers (2D grids
 // with tuned sizes, when autotuning is on); otherwise the default tiles.

@@ -42,7 +42,7 @@ def _key(info):
     return (info.steps, info.stop_reason, info.last_dm, info.total_cg_iters, info.unconverged_solves)
 
 
-def _run_batch(env, inst, dtype, steps, dt, rtol, parts=None, out=None):
+def _run_batch(env, inst, dtype, steps, dt, rtol, parts=None, out=None, max_iter=1000):
     NF, T, torch = env
     ms = [T(w["m0"]) for w in inst]
     ps = [torch.zeros_like(T(w["r"])) for w in inst]
@@ -53,18 +53,18 @@ def _run_batch(env, inst, dtype, steps, dt, rtol, parts=None, out=None):
     with NF.Batch([w["n"] for w in inst], dtype=dtype) as b:
         if parts is not None:
             b.set_partitions(parts)
-        infos = b.run([w["prm"] for w in inst], dt, steps, ms, ps, rs, Ss, rtol=rtol)
+        infos = b.run([w["prm"] for w in inst], dt, steps, ms, ps, rs, Ss, rtol=rtol, max_iter=max_iter)
         if out is not None:
             out["parts"] = b.partitions()
     return ms, ps, infos
 
 
-def _run_single(env, w, dtype, steps, dt, rtol):
+def _run_single(env, w, dtype, steps, dt, rtol, max_iter=1000):
     NF, T, torch = env
     m, r, S = T(w["m0"]), T(w["r"]), T(w["S"])
     p = torch.zeros_like(r)
     with NF.Grid(w["n"], dtype=dtype) as g:
-        info = g.run(*w["prm"], dt, steps, m, p, r, S, rtol=rtol)
+        info = g.run(*w["prm"], dt, steps, m, p, r, S, rtol=rtol, max_iter=max_iter)
     return m, p, info
 
 
@@ -78,6 +78,26 @@ def test_batch_is_bitwise_the_single_instance_run(env, dtype_name):
         m1, p1, info1 = _run_single(env, w, dtype, 6, 5e-4, 1e-10)
         assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), i
         assert _key(infos[i]) == _key(info1), (i, infos[i], info1)
+
+
+@pytest.mark.parametrize("dtype_name", ["NF_F64", "NF_F32_REFINED"])
+def test_batch_capped_solves_match_single_runs(env, dtype_name):
+    # max_iter below what the solves need: every solve stops at the cap, takes
+    # the final residual test there and counts as unconverged, as in nf_run;
+    # a looser cap lets the instances that converge fast finish while the
+    # others are capped in the same launches
+    NF, T, torch = env
+    dtype = getattr(NF, dtype_name)
+    inst = _instances(((64, 2), (32, 2)), 1500)
+    for max_iter in (3, 12):
+        for parts in (1, 2):
+            ms, ps, infos = _run_batch(env, inst, dtype, 3, 5e-4, 1e-10, parts=parts, max_iter=max_iter)
+            for i, w in enumerate(inst):
+                m1, p1, info1 = _run_single(env, w, dtype, 3, 5e-4, 1e-10, max_iter=max_iter)
+                assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), (max_iter, parts, i)
+                assert _key(infos[i]) == _key(info1), (max_iter, parts, i, infos[i], info1)
+        if max_iter == 3:
+            assert all(x.unconverged_solves == 4 for x in infos), [x.unconverged_solves for x in infos]
 
 
 def test_batch_matches_oracle(env):
