@@ -640,6 +640,12 @@ def main():
         "step_achieved": step_bytes / elapsed / 1e9,
         "step_frac": step_bytes / elapsed / 1e9 / HBM_PEAK_GBS,
     }
+    # context: the tuner's throughput of the chosen operator-middle tile, one launch per
+    # interval when three run concurrently on separate buffers (as the three streams do)
+    tun = inst[0]["g"].tuning()
+    if args.kernel == "row_flux" and tun.get("tuned") and tun["us"][0] > 0:
+        roofline["three_stream_throughput_us"] = tun["us"][0]
+        roofline["frac_three_stream_throughput"] = alg_bytes / (tun["us"][0] * 1e-6) / 1e9 / HBM_PEAK_GBS
     finite = all(torch.isfinite(it["m"]).all().item() for it in inst)
 
     # context: the gamma = 0.75 instance alone on one stream over the same steps
