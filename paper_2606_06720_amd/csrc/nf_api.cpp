@@ -19,9 +19,9 @@ using namespace nf;
 
 namespace nf {
 
-// Wait for an event of the polling loops by querying it: a blocking wait can
-// take tens of microseconds to return after the event completes, time in which
-// the GPU runs dry once the queued work is a single PCG iteration.  After
+// Wait for an event of the polling loops by querying it, which returns as soon
+// as the event completes; a blocking wait can return later, while the queued
+// work (a single PCG iteration once the first chunk is done) runs out.  After
 // about a millisecond the wait blocks instead.
 hipError_t poll_event(hipEvent_t e) {
   const auto t0 = std::chrono::steady_clock::now();
