@@ -100,6 +100,50 @@ def test_batch_capped_solves_match_single_runs(env, dtype_name):
             assert all(x.unconverged_solves == 4 for x in infos), [x.unconverged_solves for x in infos]
 
 
+def _rect_instance(n, L, seed):
+    """An ensemble-type instance on an Nx x Ny grid over an Lx x Ly box."""
+    rng = np.random.default_rng(seed)
+    X = W.grid_coords(n, L)
+    S = W.gaussian(X, (0.25 * L[0], 0.5 * L[1]), 0.05 * L[1]) - W.gaussian(X, (0.75 * L[0], 0.5 * L[1]), 0.05 * L[1])
+    return dict(n=n, L=L, r=np.ascontiguousarray(0.05 + 0.05 * W.smooth_random_field(rng, n, L)),
+                S=np.ascontiguousarray(S - S.mean()), m0=np.ascontiguousarray(rng.random((2, n[1], n[0]))),
+                prm=(float(rng.uniform(5.0, 50.0)), float(rng.uniform(1e-5, 1e-3)), float(rng.uniform(0.5, 1.25))))
+
+
+@pytest.mark.parametrize("dtype_name", ["NF_F64", "NF_F32_REFINED"])
+def test_batch_paper_grids_and_boxes(env, dtype_name):
+    # launch groups keyed by grid and box: the paper's 50 * 2^k grids (radix-5
+    # stages, square and rectangular) next to power-of-two rectangular grids
+    # over non-square boxes, two partitions; every instance bitwise its own
+    # nf_run on a handle of that box, and the FP64 fields against the oracle's
+    # time loop
+    NF, T, torch = env
+    dtype = getattr(NF, dtype_name)
+    inst = _instances(((50, 2), (100, 1)), 8000)
+    inst += [_rect_instance((64, 32), (2.0, 1.0), 8100), _rect_instance((64, 32), (2.0, 1.0), 8101),
+             _rect_instance((32, 64), (1.0, 0.5), 8102), _rect_instance((100, 50), (2.0, 1.0), 8103),
+             _rect_instance((100, 50), (2.0, 1.0), 8104)]
+    steps, dt = 3, 5e-4
+    ms = [T(w["m0"]) for w in inst]
+    ps = [torch.zeros_like(T(w["r"])) for w in inst]
+    rs = [T(w["r"]) for w in inst]
+    Ss = [T(w["S"]) for w in inst]
+    with NF.Batch([w["n"] for w in inst], [w["L"] for w in inst], dtype=dtype) as b:
+        b.set_partitions(2)
+        infos = b.run([w["prm"] for w in inst], dt, steps, ms, ps, rs, Ss, rtol=1e-12)
+    for i, w in enumerate(inst):
+        m1, r1, S1 = T(w["m0"]), T(w["r"]), T(w["S"])
+        p1 = torch.zeros_like(r1)
+        with NF.Grid(w["n"], w["L"], dtype=dtype) as g:
+            info1 = g.run(*w["prm"], dt, steps, m1, p1, r1, S1, rtol=1e-12)
+        assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), (dtype_name, i)
+        assert _key(infos[i]) == _key(info1), (dtype_name, i)
+        if dtype_name == "NF_F64":
+            mo, po, _ = O.run(w["m0"], None, w["r"], w["S"], *w["prm"], dt, steps, rtol=1e-12, L=w["L"])
+            assert rel(ms[i].cpu().numpy(), mo) <= 1e-10, i
+            assert rel(ps[i].cpu().numpy(), po) <= 1e-10, i
+
+
 def test_batch_matches_oracle(env):
     NF, T, torch = env
     inst = _instances(((32, 2), (64, 1)), 2000)
@@ -225,37 +269,6 @@ def test_batch_graph_replays_match_eager_launches(env, dtype_name):
         for i in range(len(inst)):
             assert torch.equal(g[0][i], e[0][i]) and torch.equal(g[1][i], e[1][i]), (rep, i)
         assert g[2] == e[2], rep
-
-
-def test_batch_paper_grids_and_boxes(env):
-    # radix-5 grids of the paper's convergence study and non-unit boxes in one
-    # ensemble (two instances share a shape and box, so they form one launch
-    # group); every instance is bitwise its own nf_run on a handle of that box
-    NF, T, torch = env
-    specs = (((50, 50), (1.0, 1.0)), ((100, 50), (2.0, 1.0)), ((64, 32), (1.0, 0.5)), ((100, 50), (2.0, 1.0)))
-    inst = []
-    for k, (n, L) in enumerate(specs):
-        rng = np.random.default_rng(8000 + k)
-        X = W.grid_coords(n, L)
-        S = W.gaussian(X, (0.3 * L[0], 0.5 * L[1]), 0.1 * L[0]) - W.gaussian(X, (0.7 * L[0], 0.5 * L[1]), 0.1 * L[0])
-        S -= S.mean()
-        r = 0.05 + 0.05 * W.smooth_random_field(rng, n, L)
-        m0 = np.ascontiguousarray(rng.random((2,) + n[::-1]))
-        inst.append(dict(n=n, L=L, S=S, r=r, m0=m0, prm=(20.0 + 10 * k, 1e-4, 0.75)))
-    ms = [T(w["m0"]) for w in inst]
-    ps = [torch.zeros_like(T(w["r"])) for w in inst]
-    rs = [T(w["r"]) for w in inst]
-    Ss = [T(w["S"]) for w in inst]
-    with NF.Batch([w["n"] for w in inst], L=[w["L"] for w in inst]) as b:
-        b.set_partitions(2)
-        infos = b.run([w["prm"] for w in inst], 5e-4, 4, ms, ps, rs, Ss, rtol=1e-10)
-    for i, w in enumerate(inst):
-        m1, r1, S1 = T(w["m0"]), T(w["r"]), T(w["S"])
-        p1 = torch.zeros_like(r1)
-        with NF.Grid(w["n"], L=w["L"]) as g:
-            info1 = g.run(*w["prm"], 5e-4, 4, m1, p1, r1, S1, rtol=1e-10)
-        assert torch.equal(ms[i], m1) and torch.equal(ps[i], p1), i
-        assert _key(infos[i]) == _key(info1), i
 
 
 def test_batch_wide_rows(env):
