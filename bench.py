@@ -212,6 +212,12 @@ def adjoint_cost(N, steps, fd_dirs=32):
         A.adjoint_sweep(g, prm, w["dt"], steps, r, S, ckpt, lam_T, rtol, 1000, stride, st)
         torch.cuda.synchronize()
         t_sweep = time.perf_counter() - t0
+        # the same sweep with the recomputation in line (one handle, one stream),
+        # for the cost of the adjoint steps themselves
+        t0 = time.perf_counter()
+        A.adjoint_sweep(g, prm, w["dt"], steps, r, S, ckpt, lam_T, rtol, 1000, stride, overlap=False)
+        torch.cuda.synchronize()
+        t_sweep_seq = time.perf_counter() - t0
         # the sweep recomputes every segment: time that part alone
         t0 = time.perf_counter()
         for c in sorted(ckpt):
@@ -252,7 +258,7 @@ def adjoint_cost(N, steps, fd_dirs=32):
                   "max_rel_err_r": max(err_r) if err_r else None, "max_rel_err_S": max(err_S) if err_S else None,
                   "median_rel_err_r": float(np.median(err_r)) if err_r else None,
                   "median_rel_err_S": float(np.median(err_S)) if err_S else None}
-    t_adj = t_sweep - t_rec
+    t_adj = t_sweep_seq - t_rec
     t_fwd = t_run / steps
     return {
         "fd_check": fd,
@@ -265,8 +271,12 @@ def adjoint_cost(N, steps, fd_dirs=32):
         "forward_pcg_iters_per_step": st.get("recompute_iters", 0) / steps,
         "adjoint_pcg_iters_per_step": st.get("adjoint_iters", 0) / steps,
         "forward_run_ms": 1e3 * t_run,
+        # the sweep recomputes segment j - 1 on a second handle and stream while the
+        # adjoint steps of segment j run (adjoint.adjoint_sweep); sequential: in line
         "checkpointed_gradient_ms": 1e3 * (t_ckpt + t_sweep),
         "gradient_over_forward_run": (t_ckpt + t_sweep) / t_run,
+        "checkpointed_gradient_sequential_ms": 1e3 * (t_ckpt + t_sweep_seq),
+        "gradient_sequential_over_forward_run": (t_ckpt + t_sweep_seq) / t_run,
     }
 
 

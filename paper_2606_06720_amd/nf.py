@@ -207,6 +207,7 @@ class Grid:
             raise ValueError("2D or 3D grids only")
         self.n = n
         self.dim = len(n)
+        self.dtype = int(dtype)
         self.L = tuple(float(v) for v in (L if L is not None else (1.0,) * self.dim))
         if len(self.L) != self.dim:
             raise ValueError("one box length per axis")

@@ -73,6 +73,35 @@ def test_checkpointed_gradient_matches_oracle(env):
             assert rel(gS.cpu().numpy(), gS_or) <= 1e-7
 
 
+@pytest.mark.parametrize("n,stride", [((64, 64), 4), ((50, 100), 3), ((32, 32), 1)])
+def test_overlapped_sweep_is_bitwise_the_sequential_one(env, n, stride):
+    # the sweep recomputes segment j - 1 on a second handle and stream while the
+    # adjoint steps of segment j run: every result and iteration count must be
+    # the in-line sweep's
+    NF, A, T, torch = env
+    rng = np.random.default_rng(90)
+    sh = n[::-1]
+    m0 = T(rng.uniform(0.2, 1.0, (2,) + sh))
+    r = T(rng.uniform(0.05, 0.15, sh))
+    S0 = rng.standard_normal(sh)
+    S = T(S0 - S0.mean())
+    prm, dt, steps = (30.0, 1e-3, 0.75), 1e-3, 10
+    with NF.Grid(n, (1.0, 2.0)) as g:
+        m_T, ckpt = A.forward_states(g, prm, dt, steps, m0, r, S, 1e-12, 2000, stride)
+        lam_T = T(rng.standard_normal((2,) + sh))
+        out = []
+        for overlap in (False, True):
+            st = {}
+            lam0, gr, gS = A.adjoint_sweep(g, prm, dt, steps, r, S, ckpt, lam_T, 1e-12, 2000, stride, st,
+                                           overlap=overlap)
+            torch.cuda.synchronize()
+            out.append((lam0.clone(), gr.clone(), gS.clone(), st))
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert torch.equal(a, b)
+    assert out[0][3] == out[1][3]
+    assert out[0][3]["adjoint_iters"] > 0 and out[0][3]["recompute_iters"] > 0
+
+
 def test_autograd_function_and_central_differences_1024(env):
     # the 1024^2 case: gradient of the misfit of the final |m| (target from a
     # run with r perturbed by a second smooth random field) w.r.t. r and S,
